@@ -1,0 +1,164 @@
+/*
+ * bzq.h -- the homogeneous Boltzmann collision operator with a non-cutoff
+ * angular kernel, evaluated by the fast Fourier spectral method of
+ * J. Hu and K. Qi, "A fast Fourier spectral method for the homogeneous
+ * Boltzmann equation with non-cutoff collision kernels" (arXiv:2004.11239),
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2, eq. eqnR and the Galerkin system that follows it):
+ *   d f_k / dt = Q_k,   k in K_N = {-N/2+1 .. N/2-1}^3,
+ *   f_N(v) = sum_k f_k e^{i pi k.v / L} on the periodic box D_L = [-L, L]^3,
+ *   Q_k = sum_{l+m=k} G(l,m) f_l f_m                        (eq. sum)
+ * with the weight G split into a radial Gauss-Legendre rule on [0, R] and a
+ * spherical rule (eq. approxG), which gives the fast form (eq. realQ)
+ *   Q_k = sum_{rho,sigma} w_rho w_sigma rho^{2+gamma} F(k, rho, sigma)
+ *                         sum_{l+m=k} f_l e^{-i pi rho m.sigma / L} f_m.
+ * Collision kernel B = |q|^gamma b(cos th) (eq. Bb) with the angular part
+ *   b = c t^{-1-s} (1-t)^{-r},  t = sin^2(th/2),
+ * whose singularity at th = 0 is non-integrable for s >= 0 (eq. Bb1 with
+ * nu = 2s); F (eq. FF) is the exact angular integral.
+ *
+ * Data layout of every spectral array exchanged at this boundary:
+ *   device pointer to N*N*N complex128 values, interleaved (re, im) doubles,
+ *   C order [i1][i2][i3], FFT index order along each axis (index i <-> k = i
+ *   for i < N/2, k = i - N otherwise).  Entries with any index equal to N/2
+ *   (the Nyquist planes) are not read and are written as 0.
+ *   Normalisation: f_k = (2L)^-3 \int_{D_L} f e^{-i pi k.v/L} dv.
+ *
+ * Ownership and concurrency:
+ *   the caller owns f_hat / Q_hat; the plan owns its tables and scratch and is
+ *   immutable after creation.  Calls on one plan must not overlap in time:
+ *   issue them on one stream (scratch is shared between calls).  All calls
+ *   are asynchronous on `stream` (a hipStream_t; NULL = default stream)
+ *   unless stated otherwise; errors in argument checking are reported before
+ *   anything is enqueued.
+ *
+ * Errors: functions return bzq_status; no exception crosses this boundary.
+ *   bzq_last_error() returns a thread-local description of the last failure.
+ */
+#ifndef BZQ_H
+#define BZQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bzq_plan_s* bzq_plan;
+
+typedef enum {
+    BZQ_OK = 0,
+    BZQ_EINVAL = 1,        /* an argument is out of range                          */
+    BZQ_ENOMEM = 2,        /* device memory could not be allocated                 */
+    BZQ_EDEVICE = 3,       /* a HIP runtime call failed (details: bzq_last_error)  */
+    BZQ_EUNSUPPORTED = 4,  /* valid in principle, but no kernel for this size      */
+    BZQ_ENONFINITE = 5     /* NaN or Inf found in the input                        */
+} bzq_status;
+
+typedef enum {
+    BZQ_FP64 = 0,          /* FFTs, products, table and accumulation in FP64           */
+    BZQ_FP32_ACC64 = 1     /* FFTs, products and table in FP32; the quadrature
+                              accumulation over (rho, sigma), the output and every
+                              moment in FP64                                           */
+} bzq_precision;
+
+/*
+ * Create a plan for the operator of eq. realQ with the power-law angular
+ * kernel b = c_s sin^{-(2+2s)}(th/2), c_s = (1-s)(2-s)/(24 pi) (the
+ * normalisation that gives the BKW rate lambda = 1/6 of Section 5.1).
+ *   N      grid size per axis; one of 8, 16, 24, 32, 48, 64 (EUNSUPPORTED else)
+ *   L      half-width of the periodic box D_L (> 0)
+ *   R      radius of the ball B_R that truncates |q| (> 0)
+ *   gamma  exponent of Phi(|q|) = |q|^gamma, -3 < gamma <= 1 (eq. Bb)
+ *   s      order of the angular singularity, 0 <= s < 1 (nu = 2s < 2)
+ *   N_rho  number of Gauss-Legendre nodes in |q| on [0, R] (>= 1)
+ *   M      size of the Lebedev rule on S^2: 6, 14, 26, 38, 50, 74, 86, 110,
+ *          146, 170, 194, 230, 266, 302 or 350
+ *   precision  a bzq_precision value
+ * Synchronous: builds the weight tables on the device and returns when they
+ * are ready.  On failure *out is set to NULL and nothing stays allocated.
+ */
+bzq_status bzq_plan_create(bzq_plan* out, int N, double L, double R, double gamma, double s,
+                           int N_rho, int M, int precision, void* stream);
+
+/*
+ * Same with a general angular kernel b = c t^{-1-s} (1-t)^{-r}
+ * (t = sin^2(th/2)); covers the paper's 3-D kernels of Section 5.3:
+ *   b5 (cutoff, 1/(4 pi)): c = 1/(4 pi), s = -1, r = 0
+ *   b6: c = 1/(16 pi), s = 0, r = 1/2      b7: c = 1/(12 pi^2), s = 1/2, r = 1/2
+ *   b8: c = 5/(384 pi), s = 3/4, r = 0
+ * Requires -1 <= s < 1, 0 <= r < 1, c > 0.  n_jacobi (8..256) is the number of
+ * Gauss-Jacobi nodes used for the t-integral of F (64 in bzq_plan_create).
+ */
+bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, double gamma,
+                                   double b_c, double b_s, double b_r, int n_jacobi,
+                                   int N_rho, int M, int precision, void* stream);
+
+/* Q_hat = Q(f_hat, f_hat) (eq. realQ).  f_hat and Q_hat: device, complex128
+ * N^3 (layout above); they must not overlap.  Q_hat[0] is exactly 0
+ * (Remark 4.1).  A non-finite f_hat gives a non-finite Q_hat. */
+bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream);
+
+/* Advance d f/dt = Q(f, f) by n_steps steps of Heun's method (explicit
+ * trapezoid: f* = f + dt Q(f), f <- f + dt/2 (Q(f) + Q(f*))), in place on the
+ * device array f_hat. */
+bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream);
+
+/*
+ * FP64 diagnostics of f on the N^3 grid v_j = -L + j 2L/N (Section 1):
+ *   out[0] mass (2L)^3 Re f_0 (Remark 4.1)
+ *   out[1..3] momentum \int f v, out[4] energy \int f |v|^2 (trapezoid rule)
+ *   out[5] entropy dissipation \int Q ln f over points with f > 1e-14 max f
+ *          (H-theorem: <= 0); Q is Q_hat if given, else Q(f_hat) is evaluated.
+ * `out` is host memory (6 doubles).  Synchronous on `stream`.
+ */
+bzq_status bzq_moments(bzq_plan p, const double* f_hat, const double* Q_hat, double* out,
+                       void* stream);
+
+/* Synchronous check of f_hat for NaN/Inf: BZQ_OK or BZQ_ENONFINITE. */
+bzq_status bzq_check_finite(bzq_plan p, const double* f_hat, void* stream);
+
+/*
+ * Independent cells (the batched form): Q_hats[i] = Q(f_hats[i]) under
+ * plans[i], for count cells whose plans may differ in N, gamma, s and
+ * precision.  All work is enqueued on `stream`; each cell's result is
+ * bitwise identical to bzq_collision with the same plan.  Plans may repeat.
+ */
+bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hats,
+                               double* const* Q_hats, int count, void* stream);
+
+/* Device bytes held by the plan (tables + scratch), for admission control. */
+size_t bzq_plan_device_bytes(bzq_plan p);
+
+/* Per-request state a caller needs besides a plan: f_hat and Q_hat for one
+ * cell of size N (complex128 N^3 each). */
+size_t bzq_request_device_bytes(int N);
+
+/*
+ * Introspection for tests:
+ *   bzq_plan_info: host out[8] = {N, P (padded FFT size), number of antipodal
+ *     quadrature pairs (rho_p, sigma_q+), pairs per chunk, K3 splits,
+ *     precision, n_jacobi, table bytes}.
+ *   bzq_plan_pairs: host out[npairs*6] = {rho_p, sigma_x, sigma_y, sigma_z,
+ *     w_sigma, w_rho rho^{2+gamma}} per pair, sigma taken from the half of the
+ *     sphere rule whose first non-zero coordinate is positive.
+ *   bzq_plan_weights: the stored real weight of pair j at every half-spectrum
+ *     mode, as FP64 into host memory out[((N-1)^2+1)/2 * (N-1)]; entry
+ *     [c][i3] is mode k = (i1 - N/2 + 1, i2 - N/2 + 1, i3 - N/2 + 1) with
+ *     c = i1 (N-1) + i2 (c <= ((N-1)^2-1)/2).  The value is
+ *     2 w_sigma Re(e^{-ix} F(k, rho, sigma)) / P^3, x = pi rho k.sigma / (2L).
+ *     Synchronous.
+ */
+bzq_status bzq_plan_info(bzq_plan p, double* out);
+bzq_status bzq_plan_pairs(bzq_plan p, double* out);
+bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out);
+
+bzq_status bzq_plan_destroy(bzq_plan p);
+const char* bzq_status_string(bzq_status s);
+const char* bzq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BZQ_H */

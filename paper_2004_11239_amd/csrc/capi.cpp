@@ -1,0 +1,458 @@
+// The C ABI of include/bzq.h: plan construction (quadrature rules, weight
+// tables, scratch) and the host-side orchestration of the device pipeline.
+//
+// A plan holds, for the operator of eq. realQ:
+//   * the antipodal quadrature pairs (rho_p, sigma_q+), sigma_q+ from the half
+//     of the Lebedev rule with a positive leading coordinate; the pair stands
+//     for sigma and -sigma together, which is exact because the rule is
+//     centrally symmetric with equal weights (F(k, rho, -sigma) is the complex
+//     conjugate of F(k, rho, sigma) and the two convolutions differ by the
+//     phase e^{i pi rho k.sigma / L});
+//   * the real weight V_j(k) = 2 w_sigma Re(e^{-ix} F(k, rho, sigma)) / P^3,
+//     x = pi rho k.sigma / (2L), on the half spectrum, built on the device;
+//     Phi(rho) rho^2 w_rho = w_rho rho^{2+gamma} is applied per pair at run
+//     time so one table serves every gamma;
+//   * the separable phase tables e^{i pi rho n sigma_d / (2L)} for |n| <= N-2;
+//   * twiddles and the scratch of the chunked pipeline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bzq.h"
+#include "kernels.hpp"
+#include "quadrature.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bzq_status fail(bzq_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(BZQ_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+const long double kPi = 3.141592653589793238462643383279502884L;
+
+bool supported_N(int N) {
+  return N == 8 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64;
+}
+
+}  // namespace
+
+struct bzq_plan_s {
+  int N = 0, P = 0, n1 = 0, nn = 0, nh = 0;
+  double L = 0, R = 0, gamma = 0, bc = 0, bs = 0, br = 0;
+  int N_rho = 0, M = 0, nj = 0;
+  bool fp32 = false;
+  int npairs = 0;     // antipodal pairs incl. a zero pad to make the count even
+  int npt = 0;        // pairs of pairs (packed into one complex transform)
+  int G = 0;          // pair-twos per chunk
+  int S = 0;          // accumulation splits of the last stage
+  std::vector<double> pair_host;  // [npairs][6] for introspection
+  size_t bytes = 0;
+  size_t esz = 0;     // bytes per real element (4 or 8)
+  // device
+  void* V = nullptr;            // [npairs][nh][n1] real
+  double* ph = nullptr;         // [npairs][3][2N-3] complex128
+  double* cp = nullptr;         // [npairs]
+  void* tw_pad = nullptr;       // P twiddles, compute precision
+  double* tw_grid = nullptr;    // N twiddles, FP64 (physical grid transforms)
+  void* fc = nullptr;           // (N-1)^3 complex, compute precision
+  void* fgrid = nullptr;        // P^3 real, compute precision
+  void* A = nullptr;            // G * P * nn complex
+  void* Bbuf = nullptr;         // G * P * nn complex
+  double* Qpart = nullptr;      // S * nh * n1 complex128
+  double* q1 = nullptr;         // N^3 complex128 each: step / moments scratch
+  double* q2 = nullptr;
+  double* fs = nullptr;
+  double* gfc = nullptr;        // (N-1)^3 complex128
+  double* gA = nullptr;         // N * nn complex128
+  double* gf = nullptr;         // N^3 real
+  double* gq = nullptr;         // N^3 real
+  double* part = nullptr;       // moment partials
+  int* flag = nullptr;
+  std::vector<void*> allocs;
+
+  ~bzq_plan_s() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  template <typename Tp>
+  bzq_status alloc(Tp** out, size_t nbytes) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, nbytes ? nbytes : 16);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BZQ_ENOMEM, "hipMalloc(" + std::to_string(nbytes) + ") failed: " + hipGetErrorString(e));
+    }
+    allocs.push_back(p);
+    bytes += nbytes;
+    *out = (Tp*)p;
+    return BZQ_OK;
+  }
+};
+
+namespace {
+
+constexpr int kMomentBlocks = 256;
+
+bzq_status build_plan(bzq_plan_s* p, hipStream_t st) {
+  const int N = p->N, P = p->P, n1 = p->n1, nn = p->nn, nh = p->nh;
+  // -- quadrature
+  std::vector<double> rho, wr;
+  bzq::gauss_legendre(p->N_rho, p->R, rho, wr);
+  std::vector<double> leb, half;
+  if (!bzq::lebedev_rule(p->M, leb)) return fail(BZQ_EINVAL, "M is not the size of an available Lebedev rule");
+  const int Mh = bzq::lebedev_half(leb, half);
+  if (Mh < 1) return fail(BZQ_EINVAL, "sphere rule is not centrally symmetric");
+  std::vector<double> gt, gw;
+  if (!bzq::gauss_jacobi01(p->nj, p->bs, p->br, gt, gw)) return fail(BZQ_EINVAL, "Gauss-Jacobi rule failed");
+  const int nreal = p->N_rho * Mh;
+  p->npairs = nreal + (nreal & 1);
+  p->npt = p->npairs / 2;
+  // -- per-pair data
+  const int PL = 2 * N - 3;
+  std::vector<double> pd((size_t)p->npairs * 8, 0.0), cp(p->npairs, 0.0), ph((size_t)p->npairs * 3 * PL * 2);
+  p->pair_host.assign((size_t)p->npairs * 6, 0.0);
+  const long double P3 = (long double)P * P * P;
+  for (int j = 0; j < p->npairs; ++j) {
+    long double a = 0, sx = 0, sy = 0, sz = 1, wq = 0, c = 0, r = 0;
+    if (j < nreal) {
+      const int ip = j / Mh, iq = j % Mh;
+      r = rho[ip];
+      a = kPi * r / (2.0L * p->L);
+      sx = half[4 * iq];
+      sy = half[4 * iq + 1];
+      sz = half[4 * iq + 2];
+      wq = half[4 * iq + 3];
+      c = (long double)wr[ip] * powl(r, 2.0L + p->gamma);
+    }
+    pd[8 * j + 0] = (double)a;
+    pd[8 * j + 1] = (double)sx;
+    pd[8 * j + 2] = (double)sy;
+    pd[8 * j + 3] = (double)sz;
+    pd[8 * j + 4] = (double)(2.0L * wq * 4.0L * kPi * p->bc / P3);
+    cp[j] = (double)c;
+    double* ho = &p->pair_host[6 * j];
+    ho[0] = (double)r; ho[1] = (double)sx; ho[2] = (double)sy; ho[3] = (double)sz;
+    ho[4] = (double)wq; ho[5] = (double)c;
+    const long double sd[3] = {sx, sy, sz};
+    for (int d = 0; d < 3; ++d)
+      for (int n = -(N - 2); n <= N - 2; ++n) {
+        const long double ang = a * sd[d] * n;
+        const size_t o = (((size_t)j * 3 + d) * PL + (n + N - 2)) * 2;
+        ph[o] = (double)cosl(ang);
+        ph[o + 1] = (double)sinl(ang);
+      }
+  }
+  // -- chunking: keep the two pipeline intermediates near 128 MiB
+  p->esz = p->fp32 ? 4 : 8;
+  const size_t per_pt = 2ull * P * nn * 2 * p->esz;
+  p->G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p->npt, (128ull << 20) / per_pt));
+  const int tiles = (nh + 7) / 8;
+  p->S = std::max(1, std::min(p->G, (1024 + tiles - 1) / tiles));
+  // -- allocations
+  bzq_status s;
+  const size_t vcount = (size_t)p->npairs * nh * n1;
+#define ALLOC(ptr, nbytes) if ((s = p->alloc(&(ptr), (nbytes))) != BZQ_OK) return s
+  ALLOC(p->V, vcount * p->esz);
+  ALLOC(p->ph, ph.size() * sizeof(double));
+  ALLOC(p->cp, cp.size() * sizeof(double));
+  ALLOC(p->tw_pad, (size_t)P * 2 * p->esz);
+  ALLOC(p->tw_grid, (size_t)N * 2 * sizeof(double));
+  ALLOC(p->fc, (size_t)n1 * nn * 2 * p->esz);
+  ALLOC(p->fgrid, (size_t)P * P * P * p->esz);
+  ALLOC(p->A, (size_t)p->G * P * nn * 2 * p->esz);
+  ALLOC(p->Bbuf, (size_t)p->G * P * nn * 2 * p->esz);
+  ALLOC(p->Qpart, (size_t)p->S * nh * n1 * 2 * sizeof(double));
+  const size_t n3 = (size_t)N * N * N;
+  ALLOC(p->q1, n3 * 2 * sizeof(double));
+  ALLOC(p->q2, n3 * 2 * sizeof(double));
+  ALLOC(p->fs, n3 * 2 * sizeof(double));
+  ALLOC(p->gfc, (size_t)n1 * nn * 2 * sizeof(double));
+  ALLOC(p->gA, (size_t)N * nn * 2 * sizeof(double));
+  ALLOC(p->gf, n3 * sizeof(double));
+  ALLOC(p->gq, n3 * sizeof(double));
+  ALLOC(p->part, (size_t)kMomentBlocks * 8 * sizeof(double));
+  ALLOC(p->flag, sizeof(int) * 4);
+#undef ALLOC
+  double* d_pd = nullptr;
+  double* d_gj = nullptr;
+  HIP_TRY(hipMalloc(&d_pd, pd.size() * sizeof(double)));
+  if (hipMalloc(&d_gj, 2 * gt.size() * sizeof(double)) != hipSuccess) {
+    (void)hipFree(d_pd);
+    return fail(BZQ_ENOMEM, "hipMalloc for Gauss-Jacobi nodes failed");
+  }
+  std::vector<double> gj(gt);
+  gj.insert(gj.end(), gw.begin(), gw.end());
+  // twiddles e^{-2 pi i m / n}
+  std::vector<double> twp(2 * P), twg(2 * N);
+  for (int m = 0; m < P; ++m) {
+    twp[2 * m] = (double)cosl(2 * kPi * m / P);
+    twp[2 * m + 1] = (double)-sinl(2 * kPi * m / P);
+  }
+  for (int m = 0; m < N; ++m) {
+    twg[2 * m] = (double)cosl(2 * kPi * m / N);
+    twg[2 * m + 1] = (double)-sinl(2 * kPi * m / N);
+  }
+  std::vector<float> twpf(twp.begin(), twp.end());
+  bzq_status rc = BZQ_OK;
+  auto copy = [&](void* dst, const void* src, size_t n) -> bool {
+    hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) { rc = fail(BZQ_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e)); return false; }
+    return true;
+  };
+  bool ok = copy(p->ph, ph.data(), ph.size() * sizeof(double)) &&
+            copy(p->cp, cp.data(), cp.size() * sizeof(double)) &&
+            copy(d_pd, pd.data(), pd.size() * sizeof(double)) &&
+            copy(d_gj, gj.data(), gj.size() * sizeof(double)) &&
+            copy(p->tw_grid, twg.data(), twg.size() * sizeof(double)) &&
+            (p->fp32 ? copy(p->tw_pad, twpf.data(), twpf.size() * sizeof(float))
+                     : copy(p->tw_pad, twp.data(), twp.size() * sizeof(double)));
+  if (ok) {
+    hipError_t e = bzq::launch_table(p->V, d_pd, d_gj, p->nj, N, p->npairs, p->fp32, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(BZQ_EDEVICE, std::string("weight table: ") + hipGetErrorString(e));
+  }
+  (void)hipFree(d_pd);
+  (void)hipFree(d_gj);
+  return rc;
+}
+
+bzq_status create_common(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
+                         double br, int nj, int N_rho, int M, int precision, void* stream) {
+  if (!out) return fail(BZQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (N < 8 || (N & 1)) return fail(BZQ_EINVAL, "N must be even and >= 8");
+  if (!(L > 0) || !std::isfinite(L)) return fail(BZQ_EINVAL, "L must be > 0");
+  if (!(R > 0) || !std::isfinite(R)) return fail(BZQ_EINVAL, "R must be > 0");
+  if (!(gamma > -3.0 && gamma <= 1.0)) return fail(BZQ_EINVAL, "gamma must lie in (-3, 1]");
+  if (!(bs >= -1.0 && bs < 1.0)) return fail(BZQ_EINVAL, "s must lie in [-1, 1) (in [0, 1) for the power kernel)");
+  if (!(br >= 0.0 && br < 1.0)) return fail(BZQ_EINVAL, "r must lie in [0, 1)");
+  if (!(bc > 0) || !std::isfinite(bc)) return fail(BZQ_EINVAL, "kernel constant c must be > 0");
+  if (nj < 8 || nj > 256) return fail(BZQ_EINVAL, "n_jacobi must lie in [8, 256]");
+  if (N_rho < 1 || N_rho > 4096) return fail(BZQ_EINVAL, "N_rho must lie in [1, 4096]");
+  if (precision != BZQ_FP64 && precision != BZQ_FP32_ACC64) return fail(BZQ_EINVAL, "unknown precision");
+  std::vector<double> tmp;
+  if (!bzq::lebedev_rule(M, tmp)) return fail(BZQ_EINVAL, "M is not the size of an available Lebedev rule");
+  if (!supported_N(N)) return fail(BZQ_EUNSUPPORTED, "no FFT schedule for this N (supported: 8 16 24 32 48 64)");
+  bzq_plan_s* p = new bzq_plan_s();
+  p->N = N;
+  p->P = 3 * N / 2;
+  p->n1 = N - 1;
+  p->nn = p->n1 * p->n1;
+  p->nh = (p->nn + 1) / 2;
+  p->L = L; p->R = R; p->gamma = gamma;
+  p->bc = bc; p->bs = bs; p->br = br; p->nj = nj;
+  p->N_rho = N_rho; p->M = M;
+  p->fp32 = precision == BZQ_FP32_ACC64;
+  bzq_status s = build_plan(p, (hipStream_t)stream);
+  if (s != BZQ_OK) {
+    delete p;
+    return s;
+  }
+  *out = p;
+  return BZQ_OK;
+}
+
+// Enqueue one evaluation of eq. realQ: f_hat (device, complex128 N^3) -> Q_hat.
+bzq_status enqueue_collision(bzq_plan_s* p, const double* f_hat, double* Q_hat, hipStream_t st) {
+  const bzq::Geometry g{p->N, p->P};
+  HIP_TRY(bzq::launch_ingest(f_hat, p->fc, p->N, p->fp32, st));
+  // f(v) on the padded grid, shared by every pair
+  HIP_TRY(bzq::launch_zinv(p->fc, nullptr, p->A, p->tw_pad, g, 0, 1, bzq::ZINV_PLAIN, p->fp32, st));
+  HIP_TRY(bzq::launch_plane(p->A, nullptr, nullptr, p->fgrid, p->tw_pad, g, 1, bzq::PLANE_TO_GRID, p->fp32, st));
+  HIP_TRY(bzq::launch_fill(p->Qpart, 0.0, (size_t)p->S * p->nh * p->n1 * 2, st));
+  for (int c0 = 0; c0 < p->npt; c0 += p->G) {
+    const int n = std::min(p->G, p->npt - c0);
+    HIP_TRY(bzq::launch_zinv(p->fc, p->ph, p->A, p->tw_pad, g, 2 * c0, n, bzq::ZINV_PAIRS, p->fp32, st));
+    HIP_TRY(bzq::launch_plane(p->A, p->Bbuf, p->fgrid, nullptr, p->tw_pad, g, n, bzq::PLANE_PRODUCT, p->fp32, st));
+    HIP_TRY(bzq::launch_zfwd(p->Bbuf, p->V, p->ph, p->cp, p->Qpart, p->tw_pad, g, 2 * c0, n, p->S, p->fp32, st));
+  }
+  HIP_TRY(bzq::launch_finalize(p->Qpart, Q_hat, p->N, p->S, st));
+  return BZQ_OK;
+}
+
+// f on the physical N^3 grid (FP64) into dst, layout [z][x][y]
+bzq_status enqueue_to_grid(bzq_plan_s* p, const double* f_hat, double* dst, hipStream_t st) {
+  const bzq::Geometry g{p->N, p->N};
+  HIP_TRY(bzq::launch_ingest(f_hat, p->gfc, p->N, false, st));
+  HIP_TRY(bzq::launch_zinv(p->gfc, nullptr, p->gA, p->tw_grid, g, 0, 1, bzq::ZINV_GRID_SIGN, false, st));
+  HIP_TRY(bzq::launch_plane(p->gA, nullptr, nullptr, dst, p->tw_grid, g, 1, bzq::PLANE_TO_GRID, false, st));
+  return BZQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bzq_status bzq_plan_create(bzq_plan* out, int N, double L, double R, double gamma, double s, int N_rho, int M,
+                           int precision, void* stream) {
+  if (!(s >= 0.0 && s < 1.0)) {
+    if (out) *out = nullptr;
+    return fail(BZQ_EINVAL, "s must lie in [0, 1)");
+  }
+  const double c = (1.0 - s) * (2.0 - s) / (24.0 * (double)kPi);
+  return create_common(out, N, L, R, gamma, c, s, 0.0, 64, N_rho, M, precision, stream);
+}
+
+bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, double gamma, double b_c,
+                                   double b_s, double b_r, int n_jacobi, int N_rho, int M, int precision,
+                                   void* stream) {
+  return create_common(out, N, L, R, gamma, b_c, b_s, b_r, n_jacobi, N_rho, M, precision, stream);
+}
+
+bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream) {
+  if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
+  if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
+  return enqueue_collision(p, f_hat, Q_hat, (hipStream_t)stream);
+}
+
+bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream) {
+  if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
+  if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n3 = (size_t)p->N * p->N * p->N;
+  for (int i = 0; i < n_steps; ++i) {
+    bzq_status s;
+    if ((s = enqueue_collision(p, f_hat, p->q1, st)) != BZQ_OK) return s;
+    HIP_TRY(bzq::launch_axpy(p->fs, f_hat, dt, p->q1, n3, st));
+    if ((s = enqueue_collision(p, p->fs, p->q2, st)) != BZQ_OK) return s;
+    HIP_TRY(bzq::launch_heun(f_hat, p->q1, p->q2, 0.5 * dt, n3, st));
+  }
+  return BZQ_OK;
+}
+
+bzq_status bzq_moments(bzq_plan p, const double* f_hat, const double* Q_hat, double* out, void* stream) {
+  if (!p || !f_hat || !out) return fail(BZQ_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  bzq_status s;
+  const double* q = Q_hat;
+  if (!q) {
+    if ((s = enqueue_collision(p, f_hat, p->q1, st)) != BZQ_OK) return s;
+    q = p->q1;
+  }
+  if ((s = enqueue_to_grid(p, f_hat, p->gf, st)) != BZQ_OK) return s;
+  if ((s = enqueue_to_grid(p, q, p->gq, st)) != BZQ_OK) return s;
+  HIP_TRY(bzq::launch_moments(p->gf, nullptr, -1.0, p->L, p->N, p->part, kMomentBlocks, st));
+  std::vector<double> part((size_t)kMomentBlocks * 8);
+  double f0[2];
+  HIP_TRY(hipMemcpyAsync(part.data(), p->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(f0, f_hat, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double sums[5] = {0, 0, 0, 0, 0}, fmax = -1e300;
+  for (int b = 0; b < kMomentBlocks; ++b) {
+    for (int k = 0; k < 5; ++k) sums[k] += part[b * 8 + k];
+    fmax = std::max(fmax, part[b * 8 + 5]);
+  }
+  HIP_TRY(bzq::launch_moments(p->gf, p->gq, 1e-14 * std::max(fmax, 0.0), p->L, p->N, p->part, kMomentBlocks, st));
+  HIP_TRY(hipMemcpyAsync(part.data(), p->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double ent = 0;
+  for (int b = 0; b < kMomentBlocks; ++b) ent += part[b * 8 + 6];
+  const double h3 = std::pow(2.0 * p->L / p->N, 3);
+  out[0] = std::pow(2.0 * p->L, 3) * f0[0];
+  out[1] = h3 * sums[1];
+  out[2] = h3 * sums[2];
+  out[3] = h3 * sums[3];
+  out[4] = h3 * sums[4];
+  out[5] = h3 * ent;
+  return BZQ_OK;
+}
+
+bzq_status bzq_check_finite(bzq_plan p, const double* f_hat, void* stream) {
+  if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(p->flag, &h, sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(bzq::launch_finite(f_hat, (size_t)p->N * p->N * p->N * 2, p->flag, st));
+  HIP_TRY(hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return h ? fail(BZQ_ENONFINITE, "f_hat holds NaN or Inf") : BZQ_OK;
+}
+
+bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hats, double* const* Q_hats,
+                               int count, void* stream) {
+  if (count < 0 || (count > 0 && (!plans || !f_hats || !Q_hats))) return fail(BZQ_EINVAL, "bad batch arguments");
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !f_hats[i] || !Q_hats[i]) return fail(BZQ_EINVAL, "NULL entry in batch");
+  for (int i = 0; i < count; ++i) {
+    bzq_status s = enqueue_collision(plans[i], f_hats[i], Q_hats[i], (hipStream_t)stream);
+    if (s != BZQ_OK) return s;
+  }
+  return BZQ_OK;
+}
+
+size_t bzq_plan_device_bytes(bzq_plan p) { return p ? p->bytes : 0; }
+
+size_t bzq_request_device_bytes(int N) {
+  return N > 0 ? 2ull * N * N * N * 2 * sizeof(double) : 0;
+}
+
+bzq_status bzq_plan_info(bzq_plan p, double* out) {
+  if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
+  out[0] = p->N;
+  out[1] = p->P;
+  out[2] = p->npairs;
+  out[3] = 2.0 * p->G;
+  out[4] = p->S;
+  out[5] = p->fp32 ? BZQ_FP32_ACC64 : BZQ_FP64;
+  out[6] = p->nj;
+  out[7] = (double)((size_t)p->npairs * p->nh * p->n1 * p->esz);
+  return BZQ_OK;
+}
+
+bzq_status bzq_plan_pairs(bzq_plan p, double* out) {
+  if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
+  std::memcpy(out, p->pair_host.data(), p->pair_host.size() * sizeof(double));
+  return BZQ_OK;
+}
+
+bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
+  if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
+  if (pair < 0 || pair >= p->npairs) return fail(BZQ_EINVAL, "pair index out of range");
+  const size_t cnt = (size_t)p->nh * p->n1;
+  const char* src = (const char*)p->V + (size_t)pair * cnt * p->esz;
+  if (p->fp32) {
+    std::vector<float> tmp(cnt);
+    HIP_TRY(hipMemcpy(tmp.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cnt; ++i) out[i] = tmp[i];
+  } else {
+    HIP_TRY(hipMemcpy(out, src, cnt * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  return BZQ_OK;
+}
+
+bzq_status bzq_plan_destroy(bzq_plan p) {
+  if (!p) return BZQ_OK;
+  (void)hipDeviceSynchronize();
+  delete p;
+  return BZQ_OK;
+}
+
+const char* bzq_status_string(bzq_status s) {
+  switch (s) {
+    case BZQ_OK: return "ok";
+    case BZQ_EINVAL: return "invalid argument";
+    case BZQ_ENOMEM: return "out of device memory";
+    case BZQ_EDEVICE: return "HIP runtime error";
+    case BZQ_EUNSUPPORTED: return "unsupported size";
+    case BZQ_ENONFINITE: return "non-finite input";
+  }
+  return "unknown status";
+}
+
+const char* bzq_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Device-side FFT building blocks for gfx950: complex arithmetic, small
+// in-register DFTs (radix 2, 3, 4, 6, 8, 12) and Stockham autosort passes over
+// pencils resident in LDS.
+//
+// The convolutions of the fast method (Section 4, eq. realQ) are evaluated by
+// zero-padded 3-D FFTs of size P = 3N/2 per axis; P and the unpadded N are of
+// the form 2^a 3^b, so every length here factors into the radices below:
+//   8 = 8, 12 = 12, 16 = 4*4, 24 = 4*6, 32 = 4*8, 36 = 6*6, 48 = 4*12,
+//   64 = 8*8, 72 = 6*12, 96 = 8*12.
+// Convention: X[q] = sum_r x[r] e^{SIGN 2 pi i r q / n}, unnormalised.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace bzq {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// i * SIGN * a
+template <int SIGN, typename T>
+__host__ __device__ __forceinline__ cx<T> rot(cx<T> a) {
+  return SIGN > 0 ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------- small DFTs
+template <int SIGN, typename T>
+__host__ __device__ __forceinline__ void dft2(cx<T>& a, cx<T>& b) {
+  cx<T> t = a;
+  a = cadd(t, b);
+  b = csub(t, b);
+}
+
+template <int SIGN, typename T>
+__host__ __device__ __forceinline__ void dft3(cx<T>& a, cx<T>& b, cx<T>& c) {
+  const T s3 = T(0.86602540378443864676372317075294);
+  cx<T> t1 = cadd(b, c);
+  cx<T> t2 = {a.x - T(0.5) * t1.x, a.y - T(0.5) * t1.y};
+  cx<T> d = csub(b, c);
+  cx<T> t3 = rot<SIGN>(cx<T>{s3 * d.x, s3 * d.y});
+  a = cadd(a, t1);
+  b = cadd(t2, t3);
+  c = csub(t2, t3);
+}
+
+template <int SIGN, typename T>
+__host__ __device__ __forceinline__ void dft4(cx<T>& a, cx<T>& b, cx<T>& c, cx<T>& d) {
+  cx<T> s0 = cadd(a, c), d0 = csub(a, c);
+  cx<T> s1 = cadd(b, d), d1 = rot<SIGN>(csub(b, d));
+  a = cadd(s0, s1);
+  c = csub(s0, s1);
+  b = cadd(d0, d1);
+  d = csub(d0, d1);
+}
+
+// radix-2 decimation in time over two DFT4s
+template <int SIGN, typename T>
+__host__ __device__ __forceinline__ void dft8(cx<T>* v) {
+  const T h = T(0.70710678118654752440084436210485);
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<SIGN>(e0, e1, e2, e3);
+  dft4<SIGN>(o0, o1, o2, o3);
+  // o_q *= e^{SIGN 2 pi i q / 8}
+  o1 = cx<T>{h * (o1.x - T(SIGN) * o1.y), h * (o1.y + T(SIGN) * o1.x)};
+  o2 = rot<SIGN>(o2);
+  o3 = cx<T>{h * (-o3.x - T(SIGN) * o3.y), h * (-o3.y + T(SIGN) * o3.x)};
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// Good-Thomas: 6 = 2 x 3, input n = (3 n1 + 2 n2) mod 6, output k = (3 k1 + 4 k2) mod 6
+template <int SIGN, typename T>
+__host__ __device__ __forceinline__ void dft6(cx<T>* v) {
+  cx<T> a0 = v[0], a1 = v[2], a2 = v[4];   // n1 = 0: n2 = 0,1,2 -> n = 0,2,4
+  cx<T> b0 = v[3], b1 = v[5], b2 = v[1];   // n1 = 1: n = 3,5,1
+  dft2<SIGN>(a0, b0);
+  dft2<SIGN>(a1, b1);
+  dft2<SIGN>(a2, b2);
+  dft3<SIGN>(a0, a1, a2);                  // k1 = 0
+  dft3<SIGN>(b0, b1, b2);                  // k1 = 1
+  v[0] = a0; v[4] = a1; v[2] = a2;         // k = 4 k2 mod 6
+  v[3] = b0; v[1] = b1; v[5] = b2;         // k = 3 + 4 k2 mod 6
+}
+
+// Good-Thomas: 12 = 4 x 3, input n = (3 n1 + 4 n2) mod 12, output k = (9 k1 + 4 k2) mod 12
+template <int SIGN, typename T>
+__host__ __device__ __forceinline__ void dft12(cx<T>* v) {
+  cx<T> u[4][3];
+#pragma unroll
+  for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) u[n1][n2] = v[(3 * n1 + 4 * n2) % 12];
+    dft4<SIGN>(u[0][n2], u[1][n2], u[2][n2], u[3][n2]);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    dft3<SIGN>(u[k1][0], u[k1][1], u[k1][2]);
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2) v[(9 * k1 + 4 * k2) % 12] = u[k1][k2];
+  }
+}
+
+template <int R, int SIGN, typename T>
+__host__ __device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 2) {
+    dft2<SIGN>(v[0], v[1]);
+  } else if constexpr (R == 3) {
+    dft3<SIGN>(v[0], v[1], v[2]);
+  } else if constexpr (R == 4) {
+    dft4<SIGN>(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 6) {
+    dft6<SIGN>(v);
+  } else if constexpr (R == 8) {
+    dft8<SIGN>(v);
+  } else if constexpr (R == 12) {
+    dft12<SIGN>(v);
+  } else {
+    static_assert(R == 2, "unsupported radix");
+  }
+}
+
+// ------------------------------------------------------------- radix plans
+template <int P>
+struct RadixPlan;
+template <> struct RadixPlan<8>  { static constexpr int R0 = 8, R1 = 1; };
+template <> struct RadixPlan<12> { static constexpr int R0 = 12, R1 = 1; };
+template <> struct RadixPlan<16> { static constexpr int R0 = 4, R1 = 4; };
+template <> struct RadixPlan<24> { static constexpr int R0 = 4, R1 = 6; };
+template <> struct RadixPlan<32> { static constexpr int R0 = 4, R1 = 8; };
+template <> struct RadixPlan<36> { static constexpr int R0 = 6, R1 = 6; };
+template <> struct RadixPlan<48> { static constexpr int R0 = 4, R1 = 12; };
+template <> struct RadixPlan<64> { static constexpr int R0 = 8, R1 = 8; };
+template <> struct RadixPlan<72> { static constexpr int R0 = 6, R1 = 12; };
+template <> struct RadixPlan<96> { static constexpr int R0 = 8, R1 = 12; };
+
+// ------------------------------------------------------ Stockham LDS passes
+// One radix-R pass over `npencils` pencils of length P stored in LDS.
+// Element e of pencil p lives at buf[addr(p) + e * es].  Butterfly j of a
+// pencil reads elements j + r P/R (r < R), multiplies element r by
+// w^{r (j mod NS)} with w = e^{SIGN 2 pi i / (NS R)}, applies the R-point DFT
+// and writes element r to (j / NS) NS R + (j mod NS) + r NS.  Passes with
+// NS = 1, R0, R0 R1 ... give the DFT in natural order (Stockham autosort).
+// The caller must have synchronised before the call; the pass ends with a
+// barrier.  `tw` holds e^{-2 pi i m / P}, m < P (LDS).
+template <typename T, int P, int R, int NS, int SIGN, int BMAX, int NT, typename Addr>
+__device__ __forceinline__ void stockham_pass(cx<T>* __restrict__ buf, int npencils, Addr addr,
+                                              int es, const cx<T>* __restrict__ tw) {
+  constexpr int NB = P / R;
+  const int total = npencils * NB;
+  cx<T> v[BMAX][R];
+  int dst[BMAX];
+#pragma unroll
+  for (int b = 0; b < BMAX; ++b) {
+    const int idx = threadIdx.x + b * NT;
+    if (idx < total) {
+      const int p = idx / NB;
+      const int j = idx - p * NB;
+      const int base = addr(p);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[base + (j + r * NB) * es];
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[r * k * (P / (NS * R))];
+          if constexpr (SIGN > 0) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
+      }
+      dft<R, SIGN>(v[b]);
+      dst[b] = base + ((j / NS) * NS * R + (j % NS)) * es;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BMAX; ++b) {
+    const int idx = threadIdx.x + b * NT;
+    if (idx < total) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[dst[b] + r * NS * es] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int MAXP, int P, int R, int NT>
+struct Bmax {
+  static constexpr int value = (MAXP * (P / R) + NT - 1) / NT;
+};
+
+// Full length-P transform of up to MAXP pencils (all passes).
+template <typename T, int P, int SIGN, int NT, int MAXP, typename Addr>
+__device__ __forceinline__ void fft_pencils(cx<T>* __restrict__ buf, int npencils, Addr addr, int es,
+                                            const cx<T>* __restrict__ tw) {
+  constexpr int R0 = RadixPlan<P>::R0;
+  constexpr int R1 = RadixPlan<P>::R1;
+  stockham_pass<T, P, R0, 1, SIGN, Bmax<MAXP, P, R0, NT>::value, NT>(buf, npencils, addr, es, tw);
+  if constexpr (R1 > 1)
+    stockham_pass<T, P, R1, R0, SIGN, Bmax<MAXP, P, R1, NT>::value, NT>(buf, npencils, addr, es, tw);
+}
+
+}  // namespace bzq

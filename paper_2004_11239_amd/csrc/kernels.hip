@@ -1,0 +1,516 @@
+// Device kernels of the fast collision operator (Section 4, eq. realQ) for gfx950.
+//
+// One evaluation Q = Q(f, f) runs, per chunk of quadrature pairs:
+//   zinv : modulation by the separable phases e^{-i pi rho m.sigma / L} of two
+//          antipodal pairs packed as one complex spectrum Z = f (E_A + i E_B),
+//          zero padding to P = 3N/2, inverse FFT along axis 3;
+//   plane: per (pair-two, z) plane in LDS, inverse FFT along axes 2 and 1, the
+//          pointwise product with f(v) on the padded grid, forward FFT along
+//          axes 1 and 2 (only the N-1 kept modes leave the kernel);
+//   zfwd : forward FFT along axis 3, separation of the two packed pairs by
+//          Hermitian symmetry, the weight 2 w_sigma Re(e^{-ix} F) e^{ix} c_p and
+//          the FP64 accumulation over pairs.
+// Layouts: compact spectra are centred, index i <-> k = i - (N/2 - 1),
+// i < N-1; c = i1 (N-1) + i2 indexes a pencil along axis 3.  The mirror of
+// pencil c is (N-1)^2 - 1 - c and the mirror of i3 is N-2-i3.
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace bzq {
+
+namespace {
+
+constexpr int K1_TP = 32;   // pencils per zinv workgroup
+constexpr int K3_TQ = 8;    // half-spectrum pencils per zfwd workgroup
+constexpr int NT_SMALL = 256;
+
+template <int P>
+struct PlaneThreads {
+  static constexpr int value = P >= 72 ? 512 : 256;
+};
+
+// position of centred index i (k = i - (h-1)) in a length-P FFT-order axis
+__device__ __forceinline__ int posK(int i, int h, int P) {
+  const int k = i - (h - 1);
+  return k >= 0 ? k : k + P;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> to_cx(double2 v) {
+  return {(T)v.x, (T)v.y};
+}
+__device__ __forceinline__ cx<double> d2c(double2 v) { return {v.x, v.y}; }
+
+struct RowAddr {
+  int ld;
+  __device__ int operator()(int p) const { return p * ld; }
+};
+struct RowKAddr {
+  int ld, h, P;
+  __device__ int operator()(int p) const { return posK(p, h, P) * ld; }
+};
+struct ColAddr {
+  __device__ int operator()(int p) const { return p; }
+};
+
+// ------------------------------------------------------------------ ingest
+template <typename T>
+__global__ void k_ingest(const double2* __restrict__ f, cx<T>* __restrict__ fc, int N) {
+  const int n1 = N - 1, h = N / 2;
+  const int total = n1 * n1 * n1;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int i1 = e / (n1 * n1);
+    const int i2 = (e / n1) % n1;
+    const int i3 = e % n1;
+    const int a = (i1 - h + 1 + N) % N, b = (i2 - h + 1 + N) % N, c = (i3 - h + 1 + N) % N;
+    fc[e] = to_cx<T>(f[((size_t)a * N + b) * N + c]);
+  }
+}
+
+// -------------------------------------------------------------------- zinv
+template <typename T, int P, int NT>
+__global__ __launch_bounds__(NT) void k_zinv(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
+                                             cx<T>* __restrict__ A, const cx<T>* __restrict__ twg, int N,
+                                             int pair0, int mode) {
+  constexpr int LD = P + 1;
+  __shared__ cx<T> buf[K1_TP * LD];
+  __shared__ cx<T> tw[P];
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
+  const int c0 = blockIdx.x * K1_TP;
+  const int np = min(K1_TP, nn - c0);
+  const int pt = blockIdx.y;
+  for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < K1_TP * LD; i += NT) buf[i] = cx<T>{0, 0};
+  __syncthreads();
+  const double2* phA = nullptr;
+  const double2* phB = nullptr;
+  if (mode == ZINV_PAIRS) {
+    phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
+    phB = phA + 3 * PL;
+  }
+  for (int e = threadIdx.x; e < np * n1; e += NT) {
+    const int p = e / n1, i3 = e - p * n1;
+    const int c = c0 + p;
+    const int i1 = c / n1, i2 = c - i1 * n1;
+    const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
+    const cx<T> f = fc[(size_t)c * n1 + i3];
+    cx<T> z;
+    if (mode == ZINV_PAIRS) {
+      cx<double> eA = cmul(cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2])), d2c(phA[2 * PL - 2 * k3]));
+      cx<double> eB = cmul(cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2])), d2c(phB[2 * PL - 2 * k3]));
+      // E_A + i E_B
+      cx<T> m = {(T)(eA.x - eB.y), (T)(eA.y + eB.x)};
+      z = cmul(f, m);
+    } else if (mode == ZINV_GRID_SIGN) {
+      z = ((k1 + k2 + k3) & 1) ? cx<T>{-f.x, -f.y} : f;
+    } else {
+      z = f;
+    }
+    buf[p * LD + posK(i3, h, P)] = z;
+  }
+  __syncthreads();
+  fft_pencils<T, P, +1, NT, K1_TP>(buf, np, RowAddr{LD}, 1, tw);
+  cx<T>* Aout = A + (size_t)pt * P * nn;
+  for (int e = threadIdx.x; e < np * P; e += NT) {
+    const int z = e / np, p = e - z * np;
+    Aout[(size_t)z * nn + c0 + p] = buf[p * LD + z];
+  }
+}
+
+// ------------------------------------------------------------------- plane
+template <typename T, int P, int NT>
+__global__ __launch_bounds__(NT) void k_plane(const cx<T>* __restrict__ A, cx<T>* __restrict__ B,
+                                              const T* __restrict__ fgrid, T* __restrict__ gridout,
+                                              const cx<T>* __restrict__ twg, int N, int mode) {
+  constexpr int LD = P + 1;
+  __shared__ cx<T> plane[P * LD];
+  __shared__ cx<T> tw[P];
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1;
+  const int z = blockIdx.x, pt = blockIdx.y;
+  for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < P * LD; i += NT) plane[i] = cx<T>{0, 0};
+  __syncthreads();
+  const cx<T>* Ain = A + ((size_t)pt * P + z) * nn;
+  for (int c = threadIdx.x; c < nn; c += NT) {
+    const int i1 = c / n1, i2 = c - i1 * n1;
+    plane[posK(i1, h, P) * LD + posK(i2, h, P)] = Ain[c];
+  }
+  __syncthreads();
+  // inverse along axis 2 (rows; only the N-1 rows that hold modes), then axis 1 (columns)
+  fft_pencils<T, P, +1, NT, P>(plane, n1, RowKAddr{LD, h, P}, 1, tw);
+  fft_pencils<T, P, +1, NT, P>(plane, P, ColAddr{}, LD, tw);
+  if (mode == PLANE_TO_GRID) {
+    T* out = gridout + (size_t)z * P * P;
+    for (int e = threadIdx.x; e < P * P; e += NT) {
+      const int x = e / P, y = e - x * P;
+      out[e] = plane[x * LD + y].x;
+    }
+    return;
+  }
+  const T* fz = fgrid + (size_t)z * P * P;
+  for (int e = threadIdx.x; e < P * P; e += NT) {
+    const int x = e / P, y = e - x * P;
+    plane[x * LD + y] = cscale(plane[x * LD + y], fz[e]);
+  }
+  __syncthreads();
+  fft_pencils<T, P, -1, NT, P>(plane, P, ColAddr{}, LD, tw);
+  fft_pencils<T, P, -1, NT, P>(plane, n1, RowKAddr{LD, h, P}, 1, tw);
+  cx<T>* Bout = B + ((size_t)pt * P + z) * nn;
+  for (int c = threadIdx.x; c < nn; c += NT) {
+    const int i1 = c / n1, i2 = c - i1 * n1;
+    Bout[c] = plane[posK(i1, h, P) * LD + posK(i2, h, P)];
+  }
+}
+
+// -------------------------------------------------------------------- zfwd
+template <typename T, int P, int NT>
+__global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const T* __restrict__ V,
+                                             const double2* __restrict__ ph, const double* __restrict__ cp,
+                                             double2* __restrict__ Qpart, const cx<T>* __restrict__ twg,
+                                             int N, int pair0, int npt, int S) {
+  constexpr int LD = P + 1;
+  constexpr int ROWS = 2 * K3_TQ;
+  constexpr int NMAX = (2 * P) / 3;                       // N for the padded length P
+  constexpr int OPT = (K3_TQ * (NMAX - 1) + NT - 1) / NT;
+  __shared__ cx<T> buf[ROWS * LD];
+  __shared__ cx<T> tw[P];
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  const int c0 = blockIdx.x * K3_TQ;
+  const int nq = min(K3_TQ, nh - c0);
+  const int s = blockIdx.y;
+  for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < ROWS * LD; i += NT) buf[i] = cx<T>{0, 0};
+  double accx[OPT], accy[OPT];
+#pragma unroll
+  for (int b = 0; b < OPT; ++b) accx[b] = accy[b] = 0.0;
+  __syncthreads();
+  for (int pt = s; pt < npt; pt += S) {
+    const cx<T>* Bin = B + (size_t)pt * P * nn;
+    for (int e = threadIdx.x; e < 2 * nq * P; e += NT) {
+      const int z = e / (2 * nq), q = e - z * (2 * nq);
+      int c, row;
+      if (q < nq) { c = c0 + q; row = q; }
+      else { c = nn - 1 - (c0 + q - nq); row = K3_TQ + q - nq; }
+      buf[row * LD + z] = Bin[(size_t)z * nn + c];
+    }
+    __syncthreads();
+    fft_pencils<T, P, -1, NT, ROWS>(buf, ROWS, RowAddr{LD}, 1, tw);
+    const int jA = pair0 + 2 * pt, jB = jA + 1;
+    const double2* phA = ph + (size_t)jA * 3 * PL + (N - 2);
+    const double2* phB = phA + 3 * PL;
+    const double cA = cp[jA], cB = cp[jB];
+#pragma unroll
+    for (int b = 0; b < OPT; ++b) {
+      const int o = threadIdx.x + b * NT;
+      if (o < nq * n1) {
+        const int q = o / n1, i3 = o - q * n1;
+        const int c = c0 + q;
+        const int i1 = c / n1, i2 = c - i1 * n1;
+        const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
+        const cx<T> w1 = buf[q * LD + posK(i3, h, P)];
+        const cx<T> w2 = buf[(K3_TQ + q) * LD + posK(n1 - 1 - i3, h, P)];
+        // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
+        const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
+        const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
+        const size_t vi = (size_t)c * n1 + i3;
+        const double vA = cA * (double)V[(size_t)jA * nh * n1 + vi];
+        const double vB = cB * (double)V[(size_t)jB * nh * n1 + vi];
+        const cx<double> eA = cmul(cmul(d2c(phA[k1]), d2c(phA[PL + k2])), d2c(phA[2 * PL + k3]));
+        const cx<double> eB = cmul(cmul(d2c(phB[k1]), d2c(phB[PL + k2])), d2c(phB[2 * PL + k3]));
+        const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
+        accx[b] += vA * tA.x + vB * tB.x;
+        accy[b] += vA * tA.y + vB * tB.y;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < OPT; ++b) {
+    const int o = threadIdx.x + b * NT;
+    if (o < nq * n1) {
+      const int q = o / n1, i3 = o - q * n1;
+      const size_t qi = ((size_t)s * nh + c0 + q) * n1 + i3;
+      double2 v = Qpart[qi];
+      v.x += accx[b];
+      v.y += accy[b];
+      Qpart[qi] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+__global__ void k_finalize(const double2* __restrict__ Qpart, double2* __restrict__ Q, int N, int S) {
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, cmid = (nn - 1) / 2;
+  const int total = N * N * N;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int a = e / (N * N), b = (e / N) % N, d = e % N;
+    if (a == h || b == h || d == h) { Q[e] = double2{0.0, 0.0}; continue; }
+    const int k1 = a < h ? a : a - N, k2 = b < h ? b : b - N, k3 = d < h ? d : d - N;
+    int c = (k1 + h - 1) * n1 + (k2 + h - 1);
+    int i3 = k3 + h - 1;
+    bool conj = false;
+    if (c > cmid || (c == cmid && k3 < 0)) {
+      c = nn - 1 - c;
+      i3 = n1 - 1 - i3;
+      conj = true;
+    }
+    double x = 0.0, y = 0.0;
+    for (int s = 0; s < S; ++s) {
+      const double2 v = Qpart[((size_t)s * nh + c) * n1 + i3];
+      x += v.x;
+      y += v.y;
+    }
+    Q[e] = double2{x, conj ? -y : y};
+  }
+}
+
+// ------------------------------------------------------------------- table
+// coefficients (-1)^{k+1} / (k!)^2, k = 1..16, of (1 - J0(Y))/Y^2 = 1/4 sum_k c_k (Y^2/4)^{k-1}
+struct J1mSeries {
+  double c[16];
+  constexpr J1mSeries() : c{} {
+    double fk2 = 1.0;
+    for (int k = 1; k <= 16; ++k) {
+      fk2 *= (double)k * (double)k;
+      c[k - 1] = ((k & 1) ? 1.0 : -1.0) / fk2;
+    }
+  }
+};
+__constant__ J1mSeries kJ1m;
+
+// (1 - J0(Y)) / Y^2: power series below Y = 2 (first dropped term < 1e-28), else from j0
+__device__ __forceinline__ double j1m(double Y) {
+  if (Y < 2.0) {
+    const double z = 0.25 * Y * Y;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 15; k >= 0; --k) acc = acc * z + kJ1m.c[k];
+    return 0.25 * acc;
+  }
+  return (1.0 - j0(Y)) / (Y * Y);
+}
+
+template <typename TV>
+__global__ void k_table(TV* __restrict__ V, const double* __restrict__ pd, const double* __restrict__ gj,
+                        int nj, int N, int npairs) {
+  __shared__ double st[256], sw[256];
+  for (int i = threadIdx.x; i < nj; i += blockDim.x) {
+    st[i] = gj[i];
+    sw[i] = gj[nj + i];
+  }
+  __syncthreads();
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2;
+  const size_t per = (size_t)nh * n1;
+  const size_t total = per * npairs;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / per);
+    const int rem = (int)(e - (size_t)j * per);
+    const int c = rem / n1, i3 = rem - c * n1;
+    const int i1 = c / n1, i2 = c - i1 * n1;
+    const double k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
+    const double* p = pd + (size_t)j * 8;
+    const double a = p[0], sx = p[1], sy = p[2], sz = p[3], scale = p[4];
+    const double kd = k1 * sx + k2 * sy + k3 * sz;
+    const double cxp = k2 * sz - k3 * sy, cyp = k3 * sx - k1 * sz, czp = k1 * sy - k2 * sx;
+    const double x = a * kd;
+    const double y = a * sqrt(cxp * cxp + cyp * cyp + czp * czp);
+    double W = 0.0;
+    if (x != 0.0 || y != 0.0) {
+      const double cosx = cos(x);
+      for (int i = 0; i < nj; ++i) {
+        const double t = st[i];
+        const double Y = 2.0 * y * sqrt(t * (1.0 - t));
+        const double jm = j1m(Y);
+        const double J = 1.0 - Y * Y * jm;
+        // [cos(x(1-2t)) J0(Y) - cos x] / t without cancellation
+        const double g = 2.0 * sin(x * (1.0 - t)) * (sin(x * t) / t) * J - cosx * 4.0 * y * y * (1.0 - t) * jm;
+        W += sw[i] * g;
+      }
+    }
+    V[e] = (TV)(scale * W);
+  }
+}
+
+// -------------------------------------------------------------- utilities
+__global__ void k_fill(double* p, double v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_axpy(double* out, const double* x, double a, const double* y, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = x[i] + a * y[i];
+}
+__global__ void k_heun(double* f, const double* q1, const double* q2, double hh, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    f[i] = f[i] + hh * (q1[i] + q2[i]);
+}
+__global__ void k_finite(const double* x, size_t n, int* flag) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) flag[0] = 1;
+}
+
+__global__ __launch_bounds__(256) void k_moments(const double* __restrict__ f, const double* __restrict__ q,
+                                                 double fmin, double L, int N, double* __restrict__ part) {
+  __shared__ double red[7][256];
+  const double hstep = 2.0 * L / N;
+  double s[7] = {0, 0, 0, 0, 0, -1e300, 0};
+  const int total = N * N * N;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    // layout [z][x][y]: z = axis 3, x = axis 1, y = axis 2
+    const int zi = e / (N * N), xi = (e / N) % N, yi = e % N;
+    const double v1 = -L + xi * hstep, v2 = -L + yi * hstep, v3 = -L + zi * hstep;
+    const double fv = f[e];
+    s[0] += fv;
+    s[1] += fv * v1;
+    s[2] += fv * v2;
+    s[3] += fv * v3;
+    s[4] += fv * (v1 * v1 + v2 * v2 + v3 * v3);
+    s[5] = fmax(s[5], fv);
+    if (q != nullptr && fmin >= 0.0 && fv > fmin) s[6] += q[e] * log(fv);
+  }
+  for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = s[k];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int k = 0; k < 7; ++k) {
+        if (k == 5) red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        else red[k][threadIdx.x] += red[k][threadIdx.x + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 7; ++k) part[blockIdx.x * 8 + k] = red[k][0];
+}
+
+inline int grid_for(size_t n, int nt) {
+  size_t g = (n + nt - 1) / nt;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+// ----------------------------------------------------- dispatch on (P, T)
+template <typename T, int P>
+hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int N, int pair0, int npt,
+                  int mode, hipStream_t st) {
+  const int nn = (N - 1) * (N - 1);
+  dim3 grid((nn + K1_TP - 1) / K1_TP, npt);
+  hipLaunchKernelGGL((k_zinv<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)fc,
+                     (const double2*)ph, (cx<T>*)A, (const cx<T>*)tw, N, pair0, mode);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, const void* tw, int N,
+                   int npt, int mode, hipStream_t st) {
+  constexpr int NT = PlaneThreads<P>::value;
+  dim3 grid(P, npt);
+  hipLaunchKernelGGL((k_plane<T, P, NT>), grid, dim3(NT), 0, st, (const cx<T>*)A, (cx<T>*)B,
+                     (const T*)fgrid, (T*)gridout, (const cx<T>*)tw, N, mode);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
+                  const void* tw, int N, int pair0, int npt, int S, hipStream_t st) {
+  const int nn = (N - 1) * (N - 1), nh = (nn + 1) / 2;
+  dim3 grid((nh + K3_TQ - 1) / K3_TQ, S);
+  hipLaunchKernelGGL((k_zfwd<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)B,
+                     (const T*)V, (const double2*)ph, cp, (double2*)Qpart, (const cx<T>*)tw, N, pair0,
+                     npt, S);
+  return hipGetLastError();
+}
+
+#define BZQ_ALL_P(X) X(8) X(12) X(16) X(24) X(32) X(36) X(48) X(64) X(72) X(96)
+#define BZQ_PAD_P(X) X(12) X(24) X(36) X(48) X(72) X(96)
+
+}  // namespace
+
+hipError_t launch_ingest(const double* f, void* fc, int N, bool fp32, hipStream_t st) {
+  const size_t n = (size_t)(N - 1) * (N - 1) * (N - 1);
+  if (fp32)
+    hipLaunchKernelGGL(k_ingest<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double2*)f,
+                       (cx<float>*)fc, N);
+  else
+    hipLaunchKernelGGL(k_ingest<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double2*)f,
+                       (cx<double>*)fc, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_zinv(const void* fc, const double* ph, void* A, const void* tw, Geometry g, int pair0,
+                       int npt, int mode, bool fp32, hipStream_t st) {
+#define CASE(PP)                                                                            \
+  case PP:                                                                                  \
+    return fp32 ? zinv_t<float, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, st)             \
+                : zinv_t<double, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, st);
+  switch (g.P) { BZQ_ALL_P(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
+                        Geometry g, int npt, int mode, bool fp32, hipStream_t st) {
+#define CASE(PP)                                                                              \
+  case PP:                                                                                    \
+    return fp32 ? plane_t<float, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, st)           \
+                : plane_t<double, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, st);
+  switch (g.P) { BZQ_ALL_P(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
+                       const void* tw, Geometry g, int pair0, int npt, int S, bool fp32, hipStream_t st) {
+#define CASE(PP)                                                                                 \
+  case PP:                                                                                       \
+    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, st)            \
+                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, st);
+  switch (g.P) { BZQ_PAD_P(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const double* Qpart, double* Q, int N, int S, hipStream_t st) {
+  const size_t n = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double2*)Qpart,
+                     (double2*)Q, N, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_table(void* V, const double* pd, const double* gj, int nj, int N, int npairs, bool fp32,
+                        hipStream_t st) {
+  const size_t n1 = N - 1, nh = (n1 * n1 + 1) / 2;
+  const size_t n = nh * n1 * npairs;
+  const int g = grid_for(n, 256) < 4096 ? grid_for(n, 256) : 4096;
+  if (fp32)
+    hipLaunchKernelGGL(k_table<float>, dim3(g), dim3(256), 0, st, (float*)V, pd, gj, nj, N, npairs);
+  else
+    hipLaunchKernelGGL(k_table<double>, dim3(g), dim3(256), 0, st, (double*)V, pd, gj, nj, N, npairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, double v, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double* out, const double* x, double a, const double* y, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(2 * n, 256)), dim3(256), 0, st, out, x, a, y, 2 * n);
+  return hipGetLastError();
+}
+hipError_t launch_heun(double* f, const double* q1, const double* q2, double hh, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_heun, dim3(grid_for(2 * n, 256)), dim3(256), 0, st, f, q1, q2, hh, 2 * n);
+  return hipGetLastError();
+}
+hipError_t launch_finite(const double* x, size_t n, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_finite, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, flag);
+  return hipGetLastError();
+}
+hipError_t launch_moments(const double* f, const double* q, double fmin, double L, int N, double* part,
+                          int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments, dim3(nblocks), dim3(256), 0, st, f, q, fmin, L, N, part);
+  return hipGetLastError();
+}
+
+}  // namespace bzq

@@ -1,0 +1,61 @@
+// Launch wrappers for the device kernels of the collision operator.
+// Each wrapper dispatches on the padded FFT length P and the precision, and
+// enqueues on `stream`; none of them synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace bzq {
+
+enum ZinvMode { ZINV_PAIRS = 0, ZINV_PLAIN = 1, ZINV_GRID_SIGN = 2 };
+enum PlaneMode { PLANE_PRODUCT = 0, PLANE_TO_GRID = 1 };
+
+struct Geometry {
+  int N;       // modes per axis incl. the (zero) Nyquist plane
+  int P;       // FFT length per axis (3N/2, or N for the physical grid)
+};
+
+// Compact spectral copy: fc[i1][i2][i3] (centred, (N-1)^3) from the FFT-order
+// complex128 array f (N^3).  fp32 selects the element type of fc.
+hipError_t launch_ingest(const double* f, void* fc, int N, bool fp32, hipStream_t st);
+
+// Step 1 of the pipeline: modulate (mode ZINV_PAIRS) and inverse-transform along
+// axis 3; writes A[pt][z][c] for pt < npt, z < P, c < (N-1)^2.
+hipError_t launch_zinv(const void* fc, const double* phase, void* A, const void* tw, Geometry g,
+                       int pair0, int npt, int mode, bool fp32, hipStream_t st);
+
+// Step 2: per (pt, z) plane: inverse along axes 2 and 1, product with the
+// physical f (mode PLANE_PRODUCT) or output of the real grid (PLANE_TO_GRID),
+// forward along axes 1 and 2.
+hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
+                        Geometry g, int npt, int mode, bool fp32, hipStream_t st);
+
+// Step 3: forward along axis 3, split the two packed pairs, apply the stored
+// weights and the phase e^{i a k.sigma}, accumulate in FP64 into Qpart[s].
+hipError_t launch_zfwd(const void* B, const void* V, const double* phase, const double* cp,
+                       double* Qpart, const void* tw, Geometry g, int pair0, int npt, int S,
+                       bool fp32, hipStream_t st);
+
+// Sum of the S partial accumulators and Hermitian completion into Q (N^3 FFT order).
+hipError_t launch_finalize(const double* Qpart, double* Q, int N, int S, hipStream_t st);
+
+// Real weight table V[pair][c][i3] (FP64 arithmetic, stored as float or double).
+hipError_t launch_table(void* V, const double* pairdat, const double* gj, int nj, int N,
+                        int npairs, bool fp32, hipStream_t st);
+
+hipError_t launch_fill(double* p, double v, size_t n, hipStream_t st);
+// out = x + a y  (n complex128)
+hipError_t launch_axpy(double* out, const double* x, double a, const double* y, size_t n,
+                       hipStream_t st);
+// f += h (q1 + q2)
+hipError_t launch_heun(double* f, const double* q1, const double* q2, double h, size_t n,
+                       hipStream_t st);
+// flag[0] = 1 if any of the n doubles is not finite (flag must be zeroed first)
+hipError_t launch_finite(const double* x, size_t n, int* flag, hipStream_t st);
+// per-block partial sums over the N^3 grid (layout [z][x][y]):
+//   part[b*8 + {0..4}] = sum f, f v1, f v2, f v3, f |v|^2;  part[b*8+5] = max f
+//   when q != nullptr and fmin >= 0: part[b*8+6] = sum q ln f over f > fmin
+hipError_t launch_moments(const double* f, const double* q, double fmin, double L, int N,
+                          double* part, int nblocks, hipStream_t st);
+
+}  // namespace bzq

@@ -1,0 +1,167 @@
+"""GPU path (HIP library through its C ABI) against the FP64 CPU oracle.
+
+Tolerances (relative L2 over the compared modes): FP64 path 1e-11, FP32-bulk /
+FP64-accumulate path 1e-5 -- the accuracy targets of the two precisions.
+"""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def bzq():
+    import torch  # noqa: F401
+    from paper_2004_11239_amd import bzq as b
+    return b
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_Q(N, L, R, gamma, s, N_rho, M, seed, kind="two"):
+    d = oracle.Discretization.power(N, L, R, gamma, s, N_rho, M)
+    f = _input(N, L, seed, kind)
+    return oracle.collision_direct(f, d)
+
+
+def _input(N, L, seed, kind="two"):
+    mix = workloads.two_maxwellians(seed) if kind == "two" else workloads.random_mixture(seed)
+    return workloads.to_spectral(mix.sample(N, L))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL64), ("fp32", TOL32)])
+@pytest.mark.parametrize("case", [
+    (8, 8.0, 4.0, 0.0, 0.5, 8, 38),      # smallest grid
+    (8, 6.0, 3.0, 0.5, 0.25, 5, 14),     # odd pair count (padding pair), gamma != 0
+    (16, 8.0, 4.0, 0.0, 0.5, 16, 38),    # the small workload, all modes
+])
+def test_collision_matches_oracle(bzq, case, prec, tol):
+    N, L, R, gamma, s, N_rho, M = case
+    f = _input(N, L, 0)
+    Qo = _oracle_Q(N, L, R, gamma, s, N_rho, M, 0)
+    plan = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision=prec)
+    Qg = _host(plan.collision(_dev(f)))
+    err = _rel(Qg, Qo)
+    print(f"N={N} prec={prec} rel err {err:.3e}")
+    assert err < tol
+    assert Qg[0, 0, 0] == 0.0
+
+
+def test_weight_table_matches_oracle(bzq):
+    N, L, R, s, N_rho, M = 16, 8.0, 4.0, 0.5, 16, 38
+    plan = bzq.Plan(N, L, R, 0.0, s, N_rho, M, precision="fp64")
+    pairs = plan.pairs()
+    P = plan.info()["P"]
+    n1 = N - 1
+    r = np.arange(n1) - (N // 2 - 1)
+    K = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(n1 * n1, n1, 3)
+    nh = (n1 * n1 + 1) // 2
+    K = K[:nh].reshape(-1, 3)
+    kern = oracle.power_kernel(s)
+    for j in (0, 7, len(pairs) // 2, len(pairs) - 1):
+        rho, sx, sy, sz, wq, _ = pairs[j]
+        a = math.pi * rho / (2 * L)
+        sig = np.array([sx, sy, sz])
+        F = oracle.F_weight(K, a, sig, kern)
+        x = a * (K @ sig)
+        ref = (2 * wq * np.real(np.exp(-1j * x) * F) / P ** 3).reshape(nh, n1)
+        got = plan.weights(j)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref)), j
+
+
+def test_exact_invariants_and_translation(bzq):
+    """Q_0 = 0, Hermitian output, and covariance under a non-grid translation
+    (which an aliased convolution would break)."""
+    N, L = 16, 8.0
+    plan = bzq.Plan(N, L, 4.0, 0.0, 0.5, 16, 38, precision="fp64")
+    f = _input(N, L, 3)
+    Q = _host(plan.collision(_dev(f)))
+    assert Q[0, 0, 0] == 0.0
+    h = N // 2
+    assert np.all(Q[h] == 0) and np.all(Q[:, h] == 0) and np.all(Q[:, :, h] == 0)
+    Qm = np.conj(np.roll(np.flip(Q, axis=(0, 1, 2)), 1, axis=(0, 1, 2)))
+    assert np.array_equal(Q, Qm)
+    u = np.array([0.37, -0.81, 0.23])
+    k = np.fft.fftfreq(N, 1.0 / N)
+    ph = np.exp(-1j * math.pi / L * (k[:, None, None] * u[0] + k[None, :, None] * u[1]
+                                     + k[None, None, :] * u[2]))
+    Qs = _host(plan.collision(_dev(f * ph)))
+    assert _rel(Qs, Q * ph) < 1e-13
+
+
+def test_zero_input_gives_zero(bzq):
+    plan = bzq.Plan(8, 8.0, 4.0, 0.0, 0.5, 4, 6, precision="fp64")
+    Q = _host(plan.collision(_dev(np.zeros((8, 8, 8), np.complex128))))
+    assert np.all(Q == 0)
+
+
+def test_heun_step_matches_oracle(bzq):
+    N, L, R, s, N_rho, M = 8, 8.0, 4.0, 0.5, 8, 14
+    d = oracle.Discretization.power(N, L, R, 0.0, s, N_rho, M)
+    f = _input(N, L, 1)
+    ref = oracle.heun_step(oracle.heun_step(f, d, 0.05), d, 0.05)
+    plan = bzq.Plan(N, L, R, 0.0, s, N_rho, M, precision="fp64")
+    g = _dev(f)
+    plan.step(g, 0.05, 2)
+    assert _rel(_host(g), ref) < 1e-13
+
+
+def test_moments_match_oracle(bzq):
+    N, L = 16, 8.0
+    f = _input(N, L, 0)
+    Qo = _oracle_Q(N, L, 4.0, 0.0, 0.5, 16, 38, 0)
+    plan = bzq.Plan(N, L, 4.0, 0.0, 0.5, 16, 38, precision="fp64")
+    m = plan.moments(_dev(f))
+    mass, mom, energy = oracle.moments(f, L)
+    assert abs(m["mass"] - mass) < 1e-14
+    assert np.max(np.abs(np.array(m["momentum"]) - mom)) < 1e-12
+    assert abs(m["energy"] - energy) < 1e-12 * abs(energy)
+    # H-theorem functional on the spectral f (the oracle samples the same f_N)
+    fN = oracle.to_physical(f, L)
+    D = oracle.entropy_dissipation(Qo, fN, L)
+    assert abs(m["entropy_dissipation"] - D) < 1e-9 * abs(D)
+    assert m["entropy_dissipation"] < 0
+
+
+def test_batch_equals_solo_bitwise(bzq):
+    import torch
+    plans = [bzq.Plan(8, 8.0, 4.0, 0.0, 0.5, 8, 14, precision="fp64"),
+             bzq.Plan(16, 8.0, 4.0, -1.0, 0.25, 16, 38, precision="fp32"),
+             bzq.Plan(8, 8.0, 4.0, 0.0, 0.75, 8, 38, precision="fp32")]
+    fs = [_dev(_input(p.N, p.L, 10 + i)) for i, p in enumerate(plans)]
+    solo = [_host(p.collision(f)) for p, f in zip(plans, fs)]
+    outs = [torch.empty_like(f) for f in fs]
+    bzq.collision_batch(plans, fs, outs)
+    for a, b in zip(solo, outs):
+        assert np.array_equal(a, _host(b))
+
+
+def test_nonfinite_detection(bzq):
+    plan = bzq.Plan(8, 8.0, 4.0, 0.0, 0.5, 4, 6, precision="fp64")
+    f = _input(8, 8.0, 0)
+    assert plan.check_finite(_dev(f))
+    f[1, 2, 3] = np.nan
+    assert not plan.check_finite(_dev(f))

@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs for the collision-operator workloads.
+r"""Seeded synthetic inputs for the collision-operator workloads.
 
 This module only produces input data: velocity grids, sampled distribution
 functions (Maxwellian mixtures, the BKW profile used as initial data) and their
