@@ -1,0 +1,262 @@
+#!/usr/bin/env python
+"""Throughput of the non-cutoff collision operator on one MI355X.
+
+A step is one Heun step (two evaluations of Q(f, f), eq. realQ, plus the
+update) of the medium workload: N = 32^3 modes on [-8, 8]^3, R = 4,
+N_rho = 32 Gauss-Legendre nodes, M = 110 Lebedev points, gamma = 0,
+s = 0.5, dt = 0.01, two-Maxwellian initial data.  The headline `value` is
+Q evaluations per second of the FP32-bulk / FP64-accumulate path; the plain
+FP64 path is timed beside it, and both are checked against each other and
+against the CPU oracle on a mode sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--large] [--no-cpu-baseline]
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3, "fp64": 78.6}          # TFLOP/s, MI355X vector ALU (dense)
+HBM_PEAK = 8.0e12                                # B/s
+
+MEDIUM = dict(N=32, L=8.0, R=4.0, gamma=0.0, s=0.5, N_rho=32, M=110)
+LARGE = dict(N=64, L=10.0, R=5.0, gamma=0.0, s=0.5, N_rho=64, M=302)
+DT = 0.01
+
+
+# ---------------------------------------------------------------- flop model
+def fft_flops(P: int) -> float:
+    """Nominal flops of one complex length-P FFT: 5 P log2 P."""
+    return 5.0 * P * math.log2(P)
+
+
+def flop_model(N: int, npairs: int):
+    """Algorithmic flops of one evaluation, split by kernel (pairs packed two by two).
+
+    zinv  : (N-1)^2 length-P inverse transforms + 12 flops/mode of modulation
+    plane : per z-plane, 2(N-1) + 2P length-P transforms + the complex*real product (2P^2)
+    zfwd  : (N-1)^2 forward transforms + 48 flops per half-spectrum mode (split + weight + acc)
+    prep  : f on the padded grid: (N-1)^2 + P(N-1) + P^2 transforms
+    """
+    P = 3 * N // 2
+    n1 = N - 1
+    nh = (n1 * n1 + 1) // 2
+    npt = npairs // 2
+    F = fft_flops(P)
+    per_pt = {
+        "zinv": n1 * n1 * F + 12.0 * n1 ** 3,
+        "plane": P * ((2 * n1 + 2 * P) * F + 2.0 * P * P),
+        "zfwd": n1 * n1 * F + 48.0 * nh * n1,
+    }
+    out = {k: v * npt for k, v in per_pt.items()}
+    out["prep"] = (n1 * n1 + P * n1 + P * P) * F
+    out["plane_per_pt"] = per_pt["plane"]
+    out["total"] = sum(out[k] for k in ("zinv", "plane", "zfwd", "prep"))
+    return out
+
+
+def table_bytes(N: int, npairs: int, esz: int) -> int:
+    n1 = N - 1
+    return npairs * ((n1 * n1 + 1) // 2) * n1 * esz
+
+
+# --------------------------------------------------------------- GPU timing
+def time_steps(bzq, torch, cfg, prec, fhat_np, steps, warmup):
+    plan = bzq.Plan(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"], cfg["N_rho"], cfg["M"],
+                    precision=prec)
+    f0 = torch.from_numpy(fhat_np).to("cuda")
+    f = f0.clone()
+    for _ in range(warmup):
+        plan.step(f, DT, 1)
+    f.copy_(f0)
+    torch.cuda.synchronize()
+    plan.set_timing(True)                       # HIP events around every launch
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(steps):
+        plan.step(f, DT, 1)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    stages = plan.stage_times()
+    plan.set_timing(False)
+    q = plan.collision(f0)
+    torch.cuda.synchronize()
+    return plan, ms, wall, stages, q
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "fft.hpp"):
+        with open(os.path.join(ROOT, "paper_2004_11239_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_tag: str):
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary,
+    or None when the summary is missing or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "plane_traffic_medium.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic:"):
+                for kv in line.split()[1:]:
+                    k, v = kv.split("=")
+                    vals[k] = v
+    if vals.get("kernel_hash") != kernel_hash() or vals.get("kernel") != kernel_tag:
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ---------------------------------------------------------------- CPU oracle
+def cpu_baseline(cfg, fhat_np, n_modes=256, seed=0):
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count() or 1
+    d = oracle.Discretization.power(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"],
+                                    cfg["N_rho"], cfg["M"])
+    modes = oracle.mode_vectors(cfg["N"])
+    rng = np.random.default_rng(seed)
+    ks = modes[rng.choice(len(modes), size=n_modes, replace=False)]
+    t0 = time.perf_counter()
+    q = oracle.collision_direct(fhat_np, d, k_out=ks, k_block=n_modes)
+    t = time.perf_counter() - t0
+    value = n_modes / (t * len(modes))
+    return ks, q, t, {"value": value, "unit": "Q evals/s", "cores": int(max(blas_threads, 8)),
+                      "kind": "oracle",
+                      "sample": f"{n_modes} of {len(modes)} output modes of one evaluation at the "
+                                f"medium workload in {t:.1f} s (direct weighted sum, FP64, weight "
+                                f"table included); value = sample / (time x modes)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--large", action="store_true", help="also time the N=64 workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "bench.py measures one GPU: this build has no multi-GPU path "
+                                   "(the pair-sharded design is described in DESIGN.md); run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2004_11239_amd import bzq
+
+    cfg = MEDIUM
+    fhat = workloads.to_spectral(workloads.two_maxwellians(0).sample(cfg["N"], cfg["L"]))
+    # FP32-bulk / FP64-accumulate (headline) and the plain FP64 path
+    p32, ms32, wall32, st32, q32 = time_steps(bzq, torch, cfg, "fp32", fhat, args.steps, args.warmup)
+    steps64 = max(3, args.steps // 2)
+    p64, ms64, wall64, st64, q64 = time_steps(bzq, torch, cfg, "fp64", fhat, steps64, max(1, args.warmup // 2))
+    q32n, q64n = q32.cpu().numpy(), q64.cpu().numpy()
+    err32_64 = float(np.linalg.norm(q32n - q64n) / np.linalg.norm(q64n))
+
+    info = p32.info()
+    npairs = info["npairs"]
+    fm = flop_model(cfg["N"], npairs)
+    evals32 = 2 * args.steps
+    value = evals32 / (ms32 * 1e-3)
+    value64 = 2 * steps64 / (ms64 * 1e-3)
+    # dominant kernel: the plane transforms (stage 2)
+    plane_ms, plane_n = st32["plane"]
+    avg_plane_s = plane_ms * 1e-3 / plane_n
+    pts_per_launch = (npairs // 2) / (plane_n / evals32)
+    achieved = fm["plane_per_pt"] * pts_per_launch / avg_plane_s / 1e12
+    kern_tag = "k_plane<float,48>"
+    traffic = traffic_from_profiles(kern_tag)
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK["fp32"], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK["fp32"], 4), "traffic": traffic,
+            "kernel": kern_tag, "avg_launch_ms": round(avg_plane_s * 1e3, 5),
+            "alg_flop_per_launch": fm["plane_per_pt"] * pts_per_launch}
+    per_eval_ms = ms32 / evals32
+    whole = {"alg_gflop_per_eval": round(fm["total"] / 1e9, 3),
+             "tflops_whole_path": round(fm["total"] / (per_eval_ms * 1e-3) / 1e12, 3),
+             "frac_of_fp32_peak": round(fm["total"] / (per_eval_ms * 1e-3) / 1e12 / PEAK["fp32"], 4),
+             "table_bytes_per_eval": table_bytes(cfg["N"], npairs, 4),
+             "table_gbps": round(table_bytes(cfg["N"], npairs, 4) / (per_eval_ms * 1e-3) / 1e9, 1)}
+    stage_ms = {k: round(v[0] / evals32, 4) for k, v in st32.items()}
+
+    out = {
+        "metric": "Q(f,f) evals/sec at N=32^3 (FP32 bulk, FP64 accumulate; FP64 path beside it)",
+        "value": round(value, 3),
+        "unit": "Q evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms32 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Heun step (2 Q evals) N=32^3 L=8 R=4 N_rho=32 M=110 Lebedev "
+                               "gamma=0 s=0.5 dt=0.01, two-Maxwellian input",
+                   "N": cfg["N"], "L": cfg["L"], "R": cfg["R"], "N_rho": cfg["N_rho"], "M": cfg["M"],
+                   "gamma": cfg["gamma"], "s": cfg["s"], "precision": "fp32 bulk, fp64 accumulate",
+                   "antipodal_pairs": npairs},
+        "roofline": roof,
+        "fp64": {"value": round(value64, 3), "ms_per_step": round(ms64 / steps64, 4),
+                 "stage_ms_per_eval": {k: round(v[0] / (2 * steps64), 4) for k, v in st64.items()}},
+        "err_fp32_vs_fp64": err32_64,
+        "stage_ms_per_eval": stage_ms,
+        "whole_path": whole,
+        "wall_s": {"fp32": round(wall32, 3), "fp64": round(wall64, 3)},
+    }
+    if args.large:
+        cl = LARGE
+        fl = workloads.to_spectral(workloads.random_mixture(0).sample(cl["N"], cl["L"]))
+        large = {}
+        qs = {}
+        for prec in ("fp32", "fp64"):
+            p, ms, wall, st, q = time_steps(bzq, torch, cl, prec, fl, 2, 1)
+            large[prec] = {"evals_per_s": round(4 / (ms * 1e-3), 3), "ms_per_eval": round(ms / 4, 3),
+                           "stage_ms_per_eval": {k: round(v[0] / 4, 3) for k, v in st.items()}}
+            qs[prec] = q.cpu().numpy()
+            del p
+            torch.cuda.empty_cache()
+        large["err_fp32_vs_fp64"] = float(np.linalg.norm(qs["fp32"] - qs["fp64"]) / np.linalg.norm(qs["fp64"]))
+        out["large_N64"] = large
+    if not args.no_cpu_baseline:
+        ks, qo, t, cb = cpu_baseline(cfg, fhat)
+        idx = tuple(np.mod(ks, cfg["N"]).T)
+        out["err_vs_oracle_sample"] = {
+            "fp32": float(np.linalg.norm(q32n[idx] - qo) / np.linalg.norm(qo)),
+            "fp64": float(np.linalg.norm(q64n[idx] - qo) / np.linalg.norm(qo))}
+        out["cpu_baseline"] = cb
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

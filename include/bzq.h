@@ -146,13 +146,26 @@ size_t bzq_request_device_bytes(int N);
  *   bzq_plan_weights: the stored real weight of pair j at every half-spectrum
  *     mode, as FP64 into host memory out[((N-1)^2+1)/2 * (N-1)]; entry
  *     [c][i3] is mode k = (i1 - N/2 + 1, i2 - N/2 + 1, i3 - N/2 + 1) with
- *     c = i1 (N-1) + i2 (c <= ((N-1)^2-1)/2).  The value is
+ *     c = i2 (N-1) + i1 (c <= ((N-1)^2-1)/2).  The value is
  *     2 w_sigma Re(e^{-ix} F(k, rho, sigma)) / P^3, x = pi rho k.sigma / (2L).
  *     Synchronous.
  */
 bzq_status bzq_plan_info(bzq_plan p, double* out);
 bzq_status bzq_plan_pairs(bzq_plan p, double* out);
 bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out);
+
+/*
+ * Kernel timing for measurement: with timing enabled, every launch the plan
+ * enqueues is bracketed by HIP events on the caller's stream.
+ * bzq_plan_stage_times (synchronous) returns into host out[10] the summed
+ * milliseconds of the launches of each stage {0 prep (ingest, f on the padded
+ * grid, accumulator clear), 1 modulate + inverse FFT along axis 3, 2 plane
+ * transforms and product, 3 forward FFT along axis 3 + weighting and
+ * accumulation, 4 finalisation} followed by the launch count of each stage,
+ * and clears the record.  Enabling or disabling clears it too.
+ */
+bzq_status bzq_plan_set_timing(bzq_plan p, int enable);
+bzq_status bzq_plan_stage_times(bzq_plan p, double* out);
 
 bzq_status bzq_plan_destroy(bzq_plan p);
 const char* bzq_status_string(bzq_status s);

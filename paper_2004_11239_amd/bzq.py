@@ -50,6 +50,8 @@ def _load():
         "bzq_plan_info": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_pairs": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_weights": ([vp, i, ctypes.POINTER(d)], i),
+        "bzq_plan_set_timing": ([vp, i], i),
+        "bzq_plan_stage_times": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_destroy": ([vp], i),
         "bzq_status_string": ([i], ctypes.c_char_p),
         "bzq_last_error": ([], ctypes.c_char_p),
@@ -65,7 +67,7 @@ _lib = _load()
 EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_step", "bzq_moments",
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
-            "bzq_plan_destroy", "bzq_status_string", "bzq_last_error")
+            "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error")
 
 
 def lib():
@@ -174,6 +176,17 @@ class Plan:
         out = (ctypes.c_double * (nh * n1))()
         _check(_lib.bzq_plan_weights(self.handle, int(pair), out))
         return np.frombuffer(out, dtype=np.float64).reshape(nh, n1).copy()
+
+    STAGES = ("prep", "zinv", "plane", "zfwd", "finalize")
+
+    def set_timing(self, enable: bool):
+        _check(_lib.bzq_plan_set_timing(self.handle, int(bool(enable))))
+
+    def stage_times(self) -> dict:
+        """{stage: (total_ms, launches)} since timing was enabled (synchronous)."""
+        out = (ctypes.c_double * 10)()
+        _check(_lib.bzq_plan_stage_times(self.handle, out))
+        return {k: (out[i], int(out[5 + i])) for i, k in enumerate(self.STAGES)}
 
     def device_bytes(self) -> int:
         return int(_lib.bzq_plan_device_bytes(self.handle))

@@ -84,9 +84,15 @@ struct bzq_plan_s {
   double* part = nullptr;       // moment partials
   int* flag = nullptr;
   std::vector<void*> allocs;
+  // optional per-launch timing (HIP events recorded around every launch)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_stage;      // stage of the launch bracketed by events 2i, 2i+1
+  size_t ev_used = 0;
 
   ~bzq_plan_s() {
     for (void* p : allocs) (void)hipFree(p);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
   template <typename Tp>
   bzq_status alloc(Tp** out, size_t nbytes) {
@@ -266,21 +272,43 @@ bzq_status create_common(bzq_plan* out, int N, double L, double R, double gamma,
   return BZQ_OK;
 }
 
+enum Stage { ST_PREP = 0, ST_ZINV = 1, ST_PLANE = 2, ST_ZFWD = 3, ST_FINAL = 4, ST_COUNT = 5 };
+
+// Record an event before (begin=true) or after a launch when timing is on.
+hipError_t mark(bzq_plan_s* p, int stage, bool begin, hipStream_t st) {
+  if (!p->timing) return hipSuccess;
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    p->ev_pool.push_back(e);
+  }
+  if (begin) p->ev_stage.push_back(stage);
+  return hipEventRecord(p->ev_pool[p->ev_used++], st);
+}
+
+#define TIMED(stage, expr)                              \
+  do {                                                  \
+    HIP_TRY(mark(p, (stage), true, st));                \
+    HIP_TRY(expr);                                      \
+    HIP_TRY(mark(p, (stage), false, st));               \
+  } while (0)
+
 // Enqueue one evaluation of eq. realQ: f_hat (device, complex128 N^3) -> Q_hat.
 bzq_status enqueue_collision(bzq_plan_s* p, const double* f_hat, double* Q_hat, hipStream_t st) {
   const bzq::Geometry g{p->N, p->P};
-  HIP_TRY(bzq::launch_ingest(f_hat, p->fc, p->N, p->fp32, st));
+  TIMED(ST_PREP, bzq::launch_ingest(f_hat, p->fc, p->N, p->fp32, st));
   // f(v) on the padded grid, shared by every pair
-  HIP_TRY(bzq::launch_zinv(p->fc, nullptr, p->A, p->tw_pad, g, 0, 1, bzq::ZINV_PLAIN, p->fp32, st));
-  HIP_TRY(bzq::launch_plane(p->A, nullptr, nullptr, p->fgrid, p->tw_pad, g, 1, bzq::PLANE_TO_GRID, p->fp32, st));
-  HIP_TRY(bzq::launch_fill(p->Qpart, 0.0, (size_t)p->S * p->nh * p->n1 * 2, st));
+  TIMED(ST_PREP, bzq::launch_zinv(p->fc, nullptr, p->A, p->tw_pad, g, 0, 1, bzq::ZINV_PLAIN, p->fp32, st));
+  TIMED(ST_PREP, bzq::launch_plane(p->A, nullptr, nullptr, p->fgrid, p->tw_pad, g, 1, bzq::PLANE_TO_GRID, p->fp32, st));
+  TIMED(ST_PREP, bzq::launch_fill(p->Qpart, 0.0, (size_t)p->S * p->nh * p->n1 * 2, st));
   for (int c0 = 0; c0 < p->npt; c0 += p->G) {
     const int n = std::min(p->G, p->npt - c0);
-    HIP_TRY(bzq::launch_zinv(p->fc, p->ph, p->A, p->tw_pad, g, 2 * c0, n, bzq::ZINV_PAIRS, p->fp32, st));
-    HIP_TRY(bzq::launch_plane(p->A, p->Bbuf, p->fgrid, nullptr, p->tw_pad, g, n, bzq::PLANE_PRODUCT, p->fp32, st));
-    HIP_TRY(bzq::launch_zfwd(p->Bbuf, p->V, p->ph, p->cp, p->Qpart, p->tw_pad, g, 2 * c0, n, p->S, p->fp32, st));
+    TIMED(ST_ZINV, bzq::launch_zinv(p->fc, p->ph, p->A, p->tw_pad, g, 2 * c0, n, bzq::ZINV_PAIRS, p->fp32, st));
+    TIMED(ST_PLANE, bzq::launch_plane(p->A, p->Bbuf, p->fgrid, nullptr, p->tw_pad, g, n, bzq::PLANE_PRODUCT, p->fp32, st));
+    TIMED(ST_ZFWD, bzq::launch_zfwd(p->Bbuf, p->V, p->ph, p->cp, p->Qpart, p->tw_pad, g, 2 * c0, n, p->S, p->fp32, st));
   }
-  HIP_TRY(bzq::launch_finalize(p->Qpart, Q_hat, p->N, p->S, st));
+  TIMED(ST_FINAL, bzq::launch_finalize(p->Qpart, Q_hat, p->N, p->S, st));
   return BZQ_OK;
 }
 
@@ -431,6 +459,29 @@ bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
   } else {
     HIP_TRY(hipMemcpy(out, src, cnt * sizeof(double), hipMemcpyDeviceToHost));
   }
+  return BZQ_OK;
+}
+
+bzq_status bzq_plan_set_timing(bzq_plan p, int enable) {
+  if (!p) return fail(BZQ_EINVAL, "NULL plan");
+  p->timing = enable != 0;
+  p->ev_stage.clear();
+  p->ev_used = 0;
+  return BZQ_OK;
+}
+
+bzq_status bzq_plan_stage_times(bzq_plan p, double* out) {
+  if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
+  for (int i = 0; i < 2 * ST_COUNT; ++i) out[i] = 0.0;
+  for (size_t i = 0; i < p->ev_stage.size(); ++i) {
+    HIP_TRY(hipEventSynchronize(p->ev_pool[2 * i + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]));
+    out[p->ev_stage[i]] += ms;
+    out[ST_COUNT + p->ev_stage[i]] += 1.0;
+  }
+  p->ev_stage.clear();
+  p->ev_used = 0;
   return BZQ_OK;
 }
 

@@ -213,4 +213,111 @@ __device__ __forceinline__ void fft_pencils(cx<T>* __restrict__ buf, int npencil
     stockham_pass<T, P, R1, R0, SIGN, Bmax<MAXP, P, R1, NT>::value, NT>(buf, npencils, addr, es, tw);
 }
 
+// ------------------------------------------------- compile-time twiddles
+// cos and sin of 2 pi m / P in double precision, evaluated at compile time:
+// quadrant reduction in exact integer arithmetic, then Taylor series on
+// [0, pi/4] (the first dropped term is below 1e-20).
+struct CosSin {
+  double c, s;
+};
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+constexpr CosSin cos_sin_2pi(int m, int P) {
+  m %= P;
+  if (m < 0) m += P;
+  const int q = (4 * m) / P;          // quadrant
+  const int rem = 4 * m - q * P;      // angle within quadrant = (pi/2) rem / P
+  double c0 = 0.0, s0 = 0.0;
+  if (2 * rem <= P) {                 // <= pi/4
+    const double phi = 0.5 * kPiD * rem / P;
+    c0 = taylor_cos(phi);
+    s0 = taylor_sin(phi);
+  } else {                            // use the complement pi/2 - phi
+    const double psi = 0.5 * kPiD * (P - rem) / P;
+    c0 = taylor_sin(psi);
+    s0 = taylor_cos(psi);
+  }
+  switch (q & 3) {
+    case 0: return {c0, s0};
+    case 1: return {-s0, c0};
+    case 2: return {-c0, -s0};
+    default: return {s0, -c0};
+  }
+}
+
+template <int P>
+struct TwiddleTable {
+  double c[P], s[P];
+  constexpr TwiddleTable() : c{}, s{} {
+    for (int m = 0; m < P; ++m) {
+      const CosSin v = cos_sin_2pi(m, P);
+      c[m] = v.c;
+      s[m] = v.s;
+    }
+  }
+};
+
+// x * e^{SIGN 2 pi i m / P} with m known after unrolling; exact for m in {0, P/4, P/2, 3P/4}
+template <int P, int SIGN, typename T>
+__host__ __device__ __forceinline__ cx<T> twiddle_mul(cx<T> x, int m) {
+  constexpr TwiddleTable<P> tw{};
+  m %= P;
+  if (m == 0) return x;
+  if (4 * m == P) return rot<SIGN>(x);
+  if (2 * m == P) return cx<T>{-x.x, -x.y};
+  if (4 * m == 3 * P) return rot<-SIGN>(x);
+  const T c = (T)tw.c[m];
+  const T s = (T)(SIGN > 0 ? tw.s[m] : -tw.s[m]);
+  return cx<T>{x.x * c - x.y * s, x.x * s + x.y * c};
+}
+
+// Length-P DFT of x[0..P) held in registers (all indices compile-time after
+// unrolling), natural order in and out.  Four-step with P = R0 R1:
+//   n = R1 n0 + n1, k = k0 + R0 k1;
+//   Y[n1][k0] = w_P^{n1 k0} DFT_R0(x[R1 n0 + n1])[k0];  X[k0 + R0 k1] = DFT_R1(Y[.][k0])[k1].
+// Zero inputs that are compile-time constants fold away (with -fno-signed-zeros).
+template <int P, int SIGN, typename T>
+__host__ __device__ __forceinline__ void fft_reg(cx<T>* x) {
+  constexpr int R0 = RadixPlan<P>::R0;
+  constexpr int R1 = RadixPlan<P>::R1;
+  if constexpr (R1 == 1) {
+    dft<R0, SIGN>(x);
+  } else {
+    cx<T> y[P];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+      cx<T> t[R0];
+#pragma unroll
+      for (int n0 = 0; n0 < R0; ++n0) t[n0] = x[R1 * n0 + n1];
+      dft<R0, SIGN>(t);
+#pragma unroll
+      for (int k0 = 0; k0 < R0; ++k0) y[n1 * R0 + k0] = twiddle_mul<P, SIGN>(t[k0], n1 * k0);
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < R0; ++k0) {
+      cx<T> t[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) t[n1] = y[n1 * R0 + k0];
+      dft<R1, SIGN>(t);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) x[k0 + R0 * k1] = t[k1];
+    }
+  }
+}
+
 }  // namespace bzq

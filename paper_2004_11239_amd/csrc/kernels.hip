@@ -11,8 +11,15 @@
 //          Hermitian symmetry, the weight 2 w_sigma Re(e^{-ix} F) e^{ix} c_p and
 //          the FP64 accumulation over pairs.
 // Layouts: compact spectra are centred, index i <-> k = i - (N/2 - 1),
-// i < N-1; c = i1 (N-1) + i2 indexes a pencil along axis 3.  The mirror of
-// pencil c is (N-1)^2 - 1 - c and the mirror of i3 is N-2-i3.
+// i < N-1; c = i2 (N-1) + i1 indexes a pencil along axis 3 (i1 fastest, so
+// that one thread per pencil reads and writes coalesced).  The mirror of
+// pencil c is (N-1)^2 - 1 - c and the mirror of i3 is N-2-i3.  The compact
+// copy of f is fc[i3][c]; the intermediates are A[pt][z][c] and B[pt][z][c].
+//
+// Two implementations of each FFT stage exist: a register one (one thread
+// holds a whole length-P pencil, twiddles are compile-time constants and the
+// zero padding folds away) used wherever a pencil fits the register file, and
+// an LDS Stockham one used otherwise (FP64 at P >= 72) and by the last stage.
 #include "fft.hpp"
 #include "kernels.hpp"
 
@@ -59,9 +66,9 @@ __global__ void k_ingest(const double2* __restrict__ f, cx<T>* __restrict__ fc, 
   const int n1 = N - 1, h = N / 2;
   const int total = n1 * n1 * n1;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int i1 = e / (n1 * n1);
+    const int i3 = e / (n1 * n1);
     const int i2 = (e / n1) % n1;
-    const int i3 = e % n1;
+    const int i1 = e % n1;
     const int a = (i1 - h + 1 + N) % N, b = (i2 - h + 1 + N) % N, c = (i3 - h + 1 + N) % N;
     fc[e] = to_cx<T>(f[((size_t)a * N + b) * N + c]);
   }
@@ -89,11 +96,11 @@ __global__ __launch_bounds__(NT) void k_zinv(const cx<T>* __restrict__ fc, const
     phB = phA + 3 * PL;
   }
   for (int e = threadIdx.x; e < np * n1; e += NT) {
-    const int p = e / n1, i3 = e - p * n1;
+    const int i3 = e / np, p = e - i3 * np;
     const int c = c0 + p;
-    const int i1 = c / n1, i2 = c - i1 * n1;
+    const int i2 = c / n1, i1 = c - i2 * n1;
     const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
-    const cx<T> f = fc[(size_t)c * n1 + i3];
+    const cx<T> f = fc[(size_t)i3 * nn + c];
     cx<T> z;
     if (mode == ZINV_PAIRS) {
       cx<double> eA = cmul(cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2])), d2c(phA[2 * PL - 2 * k3]));
@@ -132,7 +139,7 @@ __global__ __launch_bounds__(NT) void k_plane(const cx<T>* __restrict__ A, cx<T>
   __syncthreads();
   const cx<T>* Ain = A + ((size_t)pt * P + z) * nn;
   for (int c = threadIdx.x; c < nn; c += NT) {
-    const int i1 = c / n1, i2 = c - i1 * n1;
+    const int i2 = c / n1, i1 = c - i2 * n1;
     plane[posK(i1, h, P) * LD + posK(i2, h, P)] = Ain[c];
   }
   __syncthreads();
@@ -157,7 +164,7 @@ __global__ __launch_bounds__(NT) void k_plane(const cx<T>* __restrict__ A, cx<T>
   fft_pencils<T, P, -1, NT, P>(plane, n1, RowKAddr{LD, h, P}, 1, tw);
   cx<T>* Bout = B + ((size_t)pt * P + z) * nn;
   for (int c = threadIdx.x; c < nn; c += NT) {
-    const int i1 = c / n1, i2 = c - i1 * n1;
+    const int i2 = c / n1, i1 = c - i2 * n1;
     Bout[c] = plane[posK(i1, h, P) * LD + posK(i2, h, P)];
   }
 }
@@ -205,7 +212,7 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
       if (o < nq * n1) {
         const int q = o / n1, i3 = o - q * n1;
         const int c = c0 + q;
-        const int i1 = c / n1, i2 = c - i1 * n1;
+        const int i2 = c / n1, i1 = c - i2 * n1;
         const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
         const cx<T> w1 = buf[q * LD + posK(i3, h, P)];
         const cx<T> w2 = buf[(K3_TQ + q) * LD + posK(n1 - 1 - i3, h, P)];
@@ -238,6 +245,149 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
   }
 }
 
+
+// ---------------------------------------------------- register-FFT kernels
+// A pencil fits the register file when it has at most 96 FP32 or 48 FP64
+// complex values; larger pencils use the LDS kernels above.
+template <typename T, int P>
+struct RegFit {
+  static constexpr bool value = (int)sizeof(T) * P <= 4 * 96;
+};
+
+template <int P>
+constexpr int padN() { return (2 * P) / 3; }
+// lengths that occur as a padded length 3N/2 or as an unpadded grid N
+template <int P>
+constexpr bool isPad() { return P == 12 || P == 24 || P == 36 || P == 48 || P == 72 || P == 96; }
+template <int P>
+constexpr bool isGrid() { return P == 8 || P == 16 || P == 24 || P == 32 || P == 48 || P == 64; }
+
+// compile-time position of centred index i in a length-P axis with N modes
+template <int N, int P>
+__device__ __forceinline__ constexpr int posKc(int i) {
+  return i - (N / 2 - 1) >= 0 ? i - (N / 2 - 1) : i - (N / 2 - 1) + P;
+}
+
+// modulation (mode ZINV_PAIRS), plain copy or grid sign, then inverse FFT
+// along axis 3; one thread per pencil c (i1 fastest)
+template <typename T, int N, int P, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
+                                                 cx<T>* __restrict__ A, int pair0) {
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
+  const int c = blockIdx.x * NT + threadIdx.x;
+  if (c >= nn) return;
+  const int pt = blockIdx.y;
+  const int i2 = c / n1, i1 = c - i2 * n1;
+  const int k1 = i1 - h + 1, k2 = i2 - h + 1;
+  cx<T> v[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
+  cx<double> eA12 = {1.0, 0.0}, eB12 = {0.0, 0.0};
+  const double2* phA = nullptr;
+  const double2* phB = nullptr;
+  if constexpr (MODE == ZINV_PAIRS) {
+    phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
+    phB = phA + 3 * PL;
+    eA12 = cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2]));
+    eB12 = cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2]));
+  }
+#pragma unroll
+  for (int i3 = 0; i3 < n1; ++i3) {
+    const int k3 = i3 - h + 1;
+    const cx<T> f = fc[(size_t)i3 * nn + c];
+    cx<T> z;
+    if constexpr (MODE == ZINV_PAIRS) {
+      const cx<double> eA = cmul(eA12, d2c(phA[2 * PL - 2 * k3]));
+      const cx<double> eB = cmul(eB12, d2c(phB[2 * PL - 2 * k3]));
+      const cx<T> m = {(T)(eA.x - eB.y), (T)(eA.y + eB.x)};     // E_A + i E_B
+      z = cmul(f, m);
+    } else if constexpr (MODE == ZINV_GRID_SIGN) {
+      z = ((k1 + k2 + k3) & 1) ? cx<T>{-f.x, -f.y} : f;
+    } else {
+      z = f;
+    }
+    v[posKc<N, P>(i3)] = z;
+  }
+  fft_reg<P, +1>(v);
+  cx<T>* Aout = A + (size_t)pt * P * nn + c;
+#pragma unroll
+  for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * nn] = v[zi];
+}
+
+template <typename T, int P>
+struct PlaneCfg {
+  static constexpr int Z = P == 8 ? 8 : P == 12 ? 12 : P == 16 ? 8 : P == 24 ? 8 : P == 32 ? 4
+                         : P == 36 ? 3 : P == 48 ? (sizeof(T) == 4 ? 4 : 2) : P == 64 ? 2
+                         : P == 72 ? 2 : 1;
+  static constexpr int NT = ((Z * P + 63) / 64) * 64;
+};
+
+// Z planes of one pair-two per workgroup; one thread per row (axis 2) or
+// column (axis 1) of a plane.  LDS holds the N-1 mode rows of each plane.
+template <typename T, int N, int P, int MODE>
+__global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>* __restrict__ A,
+                                                                  cx<T>* __restrict__ B,
+                                                                  const T* __restrict__ fgrid,
+                                                                  T* __restrict__ gridout) {
+  constexpr int n1 = N - 1, nn = n1 * n1, LD = P + 1;
+  constexpr int Z = PlaneCfg<T, P>::Z;
+  __shared__ cx<T> sm[Z * n1 * LD];
+  const int z0 = blockIdx.x * Z, pt = blockIdx.y;
+  const int tid = threadIdx.x;
+  // rows: inverse along axis 2
+  if (tid < Z * n1) {
+    const int zz = tid / n1, i1 = tid - zz * n1;
+    const cx<T>* Ain = A + ((size_t)pt * P + z0 + zz) * nn + i1;
+    cx<T> v[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
+#pragma unroll
+    for (int i2 = 0; i2 < n1; ++i2) v[posKc<N, P>(i2)] = Ain[(size_t)i2 * n1];
+    fft_reg<P, +1>(v);
+    cx<T>* row = sm + (zz * n1 + i1) * LD;
+#pragma unroll
+    for (int y = 0; y < P; ++y) row[y] = v[y];
+  }
+  __syncthreads();
+  // columns: inverse along axis 1, product with f (or output of the grid), forward
+  if (tid < Z * P) {
+    const int zz = tid / P, y = tid - zz * P;
+    const int z = z0 + zz;
+    cx<T> v[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
+#pragma unroll
+    for (int i1 = 0; i1 < n1; ++i1) v[posKc<N, P>(i1)] = sm[(zz * n1 + i1) * LD + y];
+    fft_reg<P, +1>(v);
+    if constexpr (MODE == PLANE_TO_GRID) {
+      T* out = gridout + (size_t)z * P * P + y;
+#pragma unroll
+      for (int x = 0; x < P; ++x) out[x * P] = v[x].x;
+    } else {
+      const T* fz = fgrid + (size_t)z * P * P + y;
+#pragma unroll
+      for (int x = 0; x < P; ++x) v[x] = cscale(v[x], fz[x * P]);
+      fft_reg<P, -1>(v);
+#pragma unroll
+      for (int k1 = 0; k1 < n1; ++k1) sm[(zz * n1 + k1) * LD + y] = v[posKc<N, P>(k1)];
+    }
+  }
+  if constexpr (MODE == PLANE_TO_GRID) return;
+  __syncthreads();
+  // rows: forward along axis 2, keep the N-1 modes
+  if (tid < Z * n1) {
+    const int zz = tid / n1, k1 = tid - zz * n1;
+    cx<T> v[P];
+    const cx<T>* row = sm + (zz * n1 + k1) * LD;
+#pragma unroll
+    for (int y = 0; y < P; ++y) v[y] = row[y];
+    fft_reg<P, -1>(v);
+    cx<T>* Bout = B + ((size_t)pt * P + z0 + zz) * nn + k1;
+#pragma unroll
+    for (int k2 = 0; k2 < n1; ++k2) Bout[(size_t)k2 * n1] = v[posKc<N, P>(k2)];
+  }
+}
+
 // ---------------------------------------------------------------- finalize
 __global__ void k_finalize(const double2* __restrict__ Qpart, double2* __restrict__ Q, int N, int S) {
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, cmid = (nn - 1) / 2;
@@ -246,7 +396,7 @@ __global__ void k_finalize(const double2* __restrict__ Qpart, double2* __restric
     const int a = e / (N * N), b = (e / N) % N, d = e % N;
     if (a == h || b == h || d == h) { Q[e] = double2{0.0, 0.0}; continue; }
     const int k1 = a < h ? a : a - N, k2 = b < h ? b : b - N, k3 = d < h ? d : d - N;
-    int c = (k1 + h - 1) * n1 + (k2 + h - 1);
+    int c = (k2 + h - 1) * n1 + (k1 + h - 1);
     int i3 = k3 + h - 1;
     bool conj = false;
     if (c > cmid || (c == cmid && k3 < 0)) {
@@ -307,7 +457,7 @@ __global__ void k_table(TV* __restrict__ V, const double* __restrict__ pd, const
     const int j = (int)(e / per);
     const int rem = (int)(e - (size_t)j * per);
     const int c = rem / n1, i3 = rem - c * n1;
-    const int i1 = c / n1, i2 = c - i1 * n1;
+    const int i2 = c / n1, i1 = c - i2 * n1;
     const double k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
     const double* p = pd + (size_t)j * 8;
     const double a = p[0], sx = p[1], sy = p[2], sz = p[3], scale = p[4];
@@ -392,9 +542,45 @@ inline int grid_for(size_t n, int nt) {
 }
 
 // ----------------------------------------------------- dispatch on (P, T)
+// N for a launch of length P: the padded length (P = 3N/2) or the grid (P = N)
+template <typename T, int P, int N>
+hipError_t zinv_reg_t(const void* fc, const double* ph, void* A, int pair0, int npt, int mode, hipStream_t st) {
+  constexpr int nn = (N - 1) * (N - 1);
+  constexpr int NT = 64;
+  dim3 grid((nn + NT - 1) / NT, npt);
+  if (mode == ZINV_PAIRS)
+    hipLaunchKernelGGL((k_zinv_reg<T, N, P, NT, ZINV_PAIRS>), grid, dim3(NT), 0, st, (const cx<T>*)fc,
+                       (const double2*)ph, (cx<T>*)A, pair0);
+  else if (mode == ZINV_GRID_SIGN)
+    hipLaunchKernelGGL((k_zinv_reg<T, N, P, NT, ZINV_GRID_SIGN>), grid, dim3(NT), 0, st, (const cx<T>*)fc,
+                       (const double2*)ph, (cx<T>*)A, pair0);
+  else
+    hipLaunchKernelGGL((k_zinv_reg<T, N, P, NT, ZINV_PLAIN>), grid, dim3(NT), 0, st, (const cx<T>*)fc,
+                       (const double2*)ph, (cx<T>*)A, pair0);
+  return hipGetLastError();
+}
+
+template <typename T, int P, int N>
+hipError_t plane_reg_t(const void* A, void* B, const void* fgrid, void* gridout, int npt, int mode,
+                       hipStream_t st) {
+  using C = PlaneCfg<T, P>;
+  dim3 grid(P / C::Z, npt);
+  if (mode == PLANE_TO_GRID)
+    hipLaunchKernelGGL((k_plane_reg<T, N, P, PLANE_TO_GRID>), grid, dim3(C::NT), 0, st, (const cx<T>*)A,
+                       (cx<T>*)B, (const T*)fgrid, (T*)gridout);
+  else
+    hipLaunchKernelGGL((k_plane_reg<T, N, P, PLANE_PRODUCT>), grid, dim3(C::NT), 0, st, (const cx<T>*)A,
+                       (cx<T>*)B, (const T*)fgrid, (T*)gridout);
+  return hipGetLastError();
+}
+
 template <typename T, int P>
 hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int N, int pair0, int npt,
                   int mode, hipStream_t st) {
+  if constexpr (RegFit<T, P>::value && isPad<P>())
+    if (N == padN<P>()) return zinv_reg_t<T, P, padN<P>()>(fc, ph, A, pair0, npt, mode, st);
+  if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
+    if (N == P) return zinv_reg_t<T, P, P>(fc, ph, A, pair0, npt, mode, st);
   const int nn = (N - 1) * (N - 1);
   dim3 grid((nn + K1_TP - 1) / K1_TP, npt);
   hipLaunchKernelGGL((k_zinv<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)fc,
@@ -405,6 +591,10 @@ hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int
 template <typename T, int P>
 hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, const void* tw, int N,
                    int npt, int mode, hipStream_t st) {
+  if constexpr (RegFit<T, P>::value && isPad<P>())
+    if (N == padN<P>()) return plane_reg_t<T, P, padN<P>()>(A, B, fgrid, gridout, npt, mode, st);
+  if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
+    if (N == P) return plane_reg_t<T, P, P>(A, B, fgrid, gridout, npt, mode, st);
   constexpr int NT = PlaneThreads<P>::value;
   dim3 grid(P, npt);
   hipLaunchKernelGGL((k_plane<T, P, NT>), grid, dim3(NT), 0, st, (const cx<T>*)A, (cx<T>*)B,

@@ -77,7 +77,8 @@ def test_weight_table_matches_oracle(bzq):
     P = plan.info()["P"]
     n1 = N - 1
     r = np.arange(n1) - (N // 2 - 1)
-    K = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(n1 * n1, n1, 3)
+    # entry [c][i3] with pencil index c = i2 (N-1) + i1
+    K = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).transpose(1, 0, 2, 3).reshape(n1 * n1, n1, 3)
     nh = (n1 * n1 + 1) // 2
     K = K[:nh].reshape(-1, 3)
     kern = oracle.power_kernel(s)
