@@ -160,6 +160,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--large", action="store_true", help="also time the N=64 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run 3 device-to-device copies of MIB MiB (reference kernel for "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -171,6 +174,16 @@ def main():
     import torch
     import workloads
     from paper_2004_11239_amd import bzq
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}))
+        return
 
     cfg = MEDIUM
     fhat = workloads.to_spectral(workloads.two_maxwellians(0).sample(cfg["N"], cfg["L"]))

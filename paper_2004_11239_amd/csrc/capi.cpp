@@ -52,7 +52,7 @@ bool supported_N(int N) {
 }  // namespace
 
 struct bzq_plan_s {
-  int N = 0, P = 0, n1 = 0, nn = 0, nh = 0;
+  int N = 0, P = 0, n1 = 0, nn = 0, nh = 0, nhp = 0;
   double L = 0, R = 0, gamma = 0, bc = 0, bs = 0, br = 0;
   int N_rho = 0, M = 0, nj = 0;
   bool fp32 = false;
@@ -162,12 +162,19 @@ bzq_status build_plan(bzq_plan_s* p, hipStream_t st) {
         ph[o + 1] = (double)sinl(ang);
       }
   }
-  // -- chunking: keep the two pipeline intermediates near 128 MiB
+  // -- chunking: the two pipeline intermediates stay below 1 GiB (one chunk
+  //    per evaluation up to N = 32; they stream through HBM either way)
   p->esz = p->fp32 ? 4 : 8;
-  const size_t per_pt = 2ull * P * nn * 2 * p->esz;
-  p->G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p->npt, (128ull << 20) / per_pt));
-  const int tiles = (nh + 7) / 8;
-  p->S = std::max(1, std::min(p->G, (1024 + tiles - 1) / tiles));
+  p->nhp = (nh + 15) / 16 * 16;
+  const size_t per_pt = (size_t)P * (nn + 2 * p->nhp) * 2 * p->esz;
+  p->G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p->npt, (1024ull << 20) / per_pt));
+  // splits of the last stage: enough workgroups to fill the chip, but no more
+  // than there are groups of pair-twos (4 per group in the register variant)
+  const bool reg_zfwd = p->fp32 ? true : (P <= 48);
+  const int tq = reg_zfwd ? 16 : 8;
+  const int groups = reg_zfwd ? (p->G + 3) / 4 : p->G;
+  const int tiles = (nh + tq - 1) / tq;
+  p->S = std::max(1, std::min(groups, (2048 + tiles - 1) / tiles));
   // -- allocations
   bzq_status s;
   const size_t vcount = (size_t)p->npairs * nh * n1;
@@ -180,7 +187,7 @@ bzq_status build_plan(bzq_plan_s* p, hipStream_t st) {
   ALLOC(p->fc, (size_t)n1 * nn * 2 * p->esz);
   ALLOC(p->fgrid, (size_t)P * P * P * p->esz);
   ALLOC(p->A, (size_t)p->G * P * nn * 2 * p->esz);
-  ALLOC(p->Bbuf, (size_t)p->G * P * nn * 2 * p->esz);
+  ALLOC(p->Bbuf, (size_t)p->G * P * 2 * p->nhp * 2 * p->esz);
   ALLOC(p->Qpart, (size_t)p->S * nh * n1 * 2 * sizeof(double));
   const size_t n3 = (size_t)N * N * N;
   ALLOC(p->q1, n3 * 2 * sizeof(double));
@@ -450,15 +457,19 @@ bzq_status bzq_plan_pairs(bzq_plan p, double* out) {
 bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
   if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
   if (pair < 0 || pair >= p->npairs) return fail(BZQ_EINVAL, "pair index out of range");
+  // stored as [i3][c]; returned as [c][i3]
   const size_t cnt = (size_t)p->nh * p->n1;
   const char* src = (const char*)p->V + (size_t)pair * cnt * p->esz;
+  std::vector<double> tmp(cnt);
   if (p->fp32) {
-    std::vector<float> tmp(cnt);
-    HIP_TRY(hipMemcpy(tmp.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < cnt; ++i) out[i] = tmp[i];
+    std::vector<float> tf(cnt);
+    HIP_TRY(hipMemcpy(tf.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cnt; ++i) tmp[i] = tf[i];
   } else {
-    HIP_TRY(hipMemcpy(out, src, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(tmp.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost));
   }
+  for (int i3 = 0; i3 < p->n1; ++i3)
+    for (int c = 0; c < p->nh; ++c) out[(size_t)c * p->n1 + i3] = tmp[(size_t)i3 * p->nh + c];
   return BZQ_OK;
 }
 

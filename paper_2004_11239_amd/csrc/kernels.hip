@@ -14,7 +14,11 @@
 // i < N-1; c = i2 (N-1) + i1 indexes a pencil along axis 3 (i1 fastest, so
 // that one thread per pencil reads and writes coalesced).  The mirror of
 // pencil c is (N-1)^2 - 1 - c and the mirror of i3 is N-2-i3.  The compact
-// copy of f is fc[i3][c]; the intermediates are A[pt][z][c] and B[pt][z][c].
+// copy of f is fc[i3][c]; the first intermediate is A[pt][z][c].  The second,
+// B[pt][z][slot], is folded so that a pencil and its mirror sit at the same
+// offset of two aligned halves: slot(c) = c for c <= cmid and
+// nhp + (nn - 1 - c) otherwise, nhp = nh rounded up to 16 (the centre pencil
+// cmid is stored in both halves).
 //
 // Two implementations of each FFT stage exist: a register one (one thread
 // holds a whole length-P pencil, twiddles are compile-time constants and the
@@ -28,13 +32,23 @@ namespace bzq {
 namespace {
 
 constexpr int K1_TP = 32;   // pencils per zinv workgroup
-constexpr int K3_TQ = 8;    // half-spectrum pencils per zfwd workgroup
+constexpr int K3_TQ = 8;    // half-spectrum pencils per zfwd workgroup (LDS variant)
 constexpr int NT_SMALL = 256;
 
 template <int P>
 struct PlaneThreads {
   static constexpr int value = P >= 72 ? 512 : 256;
 };
+
+// half-spectrum pencil count rounded up to the zfwd tile, and the folded B slot
+__host__ __device__ __forceinline__ int nh_pad(int N) {
+  const int nh = ((N - 1) * (N - 1) + 1) / 2;
+  return (nh + 15) / 16 * 16;
+}
+__device__ __forceinline__ int fold_slot(int c, int nn, int nhp) {
+  const int cmid = (nn - 1) / 2;
+  return c <= cmid ? c : nhp + (nn - 1 - c);
+}
 
 // position of centred index i (k = i - (h-1)) in a length-P FFT-order axis
 __device__ __forceinline__ int posK(int i, int h, int P) {
@@ -162,10 +176,13 @@ __global__ __launch_bounds__(NT) void k_plane(const cx<T>* __restrict__ A, cx<T>
   __syncthreads();
   fft_pencils<T, P, -1, NT, P>(plane, P, ColAddr{}, LD, tw);
   fft_pencils<T, P, -1, NT, P>(plane, n1, RowKAddr{LD, h, P}, 1, tw);
-  cx<T>* Bout = B + ((size_t)pt * P + z) * nn;
+  const int nhp = nh_pad(N), cmid = (nn - 1) / 2;
+  cx<T>* Bout = B + ((size_t)pt * P + z) * 2 * nhp;
   for (int c = threadIdx.x; c < nn; c += NT) {
     const int i2 = c / n1, i1 = c - i2 * n1;
-    Bout[c] = plane[posK(i1, h, P) * LD + posK(i2, h, P)];
+    const cx<T> v = plane[posK(i1, h, P) * LD + posK(i2, h, P)];
+    Bout[fold_slot(c, nn, nhp)] = v;
+    if (c == cmid) Bout[nhp + cmid] = v;
   }
 }
 
@@ -192,13 +209,14 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
   for (int b = 0; b < OPT; ++b) accx[b] = accy[b] = 0.0;
   __syncthreads();
   for (int pt = s; pt < npt; pt += S) {
-    const cx<T>* Bin = B + (size_t)pt * P * nn;
+    const int nhp = nh_pad(N);
+    const cx<T>* Bin = B + (size_t)pt * P * 2 * nhp;
     for (int e = threadIdx.x; e < 2 * nq * P; e += NT) {
       const int z = e / (2 * nq), q = e - z * (2 * nq);
-      int c, row;
-      if (q < nq) { c = c0 + q; row = q; }
-      else { c = nn - 1 - (c0 + q - nq); row = K3_TQ + q - nq; }
-      buf[row * LD + z] = Bin[(size_t)z * nn + c];
+      int slot, row;
+      if (q < nq) { slot = c0 + q; row = q; }
+      else { slot = nhp + c0 + q - nq; row = K3_TQ + q - nq; }
+      buf[row * LD + z] = Bin[(size_t)z * 2 * nhp + slot];
     }
     __syncthreads();
     fft_pencils<T, P, -1, NT, ROWS>(buf, ROWS, RowAddr{LD}, 1, tw);
@@ -219,7 +237,7 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
         // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
         const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
         const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
-        const size_t vi = (size_t)c * n1 + i3;
+        const size_t vi = (size_t)i3 * nh + c;
         const double vA = cA * (double)V[(size_t)jA * nh * n1 + vi];
         const double vB = cB * (double)V[(size_t)jB * nh * n1 + vi];
         const cx<double> eA = cmul(cmul(d2c(phA[k1]), d2c(phA[PL + k2])), d2c(phA[2 * PL + k3]));
@@ -236,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
     const int o = threadIdx.x + b * NT;
     if (o < nq * n1) {
       const int q = o / n1, i3 = o - q * n1;
-      const size_t qi = ((size_t)s * nh + c0 + q) * n1 + i3;
+      const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + q;
       double2 v = Qpart[qi];
       v.x += accx[b];
       v.y += accy[b];
@@ -382,9 +400,131 @@ __global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>*
 #pragma unroll
     for (int y = 0; y < P; ++y) v[y] = row[y];
     fft_reg<P, -1>(v);
-    cx<T>* Bout = B + ((size_t)pt * P + z0 + zz) * nn + k1;
+    constexpr int nhp = ((nn + 1) / 2 + 15) / 16 * 16, cmid = (nn - 1) / 2;
+    cx<T>* Bout = B + ((size_t)pt * P + z0 + zz) * 2 * nhp;
 #pragma unroll
-    for (int k2 = 0; k2 < n1; ++k2) Bout[(size_t)k2 * n1] = v[posKc<N, P>(k2)];
+    for (int k2 = 0; k2 < n1; ++k2) {
+      const int c = k2 * n1 + k1;
+      const cx<T> w = v[posKc<N, P>(k2)];
+      Bout[c <= cmid ? c : nhp + (nn - 1 - c)] = w;
+      if (c == cmid) Bout[nhp + cmid] = w;
+    }
+  }
+}
+
+
+// Forward FFT along axis 3 with one thread per (pencil, pair-two), then the
+// split of the two packed pairs, the weights and the FP64 accumulation.
+// A workgroup owns TQ half-spectrum pencils c0..c0+TQ-1 (and their mirrors)
+// and walks over groups of PT pair-twos; the kept modes of each transform go
+// through LDS to the epilogue threads, which own fixed output modes and keep
+// their FP64 sums in registers for the whole launch.
+template <typename T, int P>
+struct ZfwdCfg {
+  static constexpr int TQ = 16;
+  static constexpr int PT = 4;
+  static constexpr int NT = 2 * TQ * PT;
+};
+
+template <typename T, int N, int P>
+__global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
+    const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
+    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int npt, int S) {
+  using C = ZfwdCfg<T, P>;
+  constexpr int TQ = C::TQ, PT = C::PT, NT = C::NT;
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  constexpr int OPT = (TQ * n1 + NT - 1) / NT;
+  __shared__ cx<T> W[PT][n1][2 * TQ];            // kept modes [pt][i3][pencil]
+  __shared__ double2 E12[PT][2][TQ];             // e^{ia(k1 s1 + k2 s2)} per pair A/B, pencil
+  __shared__ double2 E3[PT][2][n1];              // e^{ia k3 s3} per pair A/B
+  __shared__ double CPV[PT][2];
+  const int c0 = blockIdx.x * TQ;
+  const int s = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int ngroups = (npt + PT - 1) / PT;
+  double accx[OPT], accy[OPT];
+#pragma unroll
+  for (int b = 0; b < OPT; ++b) accx[b] = accy[b] = 0.0;
+  // this thread's transform: pt slot p, pencil r (r < TQ: c0 + r, else its mirror)
+  const int p = tid / (2 * TQ), r = tid - p * 2 * TQ;
+  const int q = r < TQ ? r : r - TQ;
+  const bool have = c0 + q < nh;
+  const int cpen = r < TQ ? c0 + q : nn - 1 - (c0 + q);
+  constexpr int nhp = (nh + 15) / 16 * 16;
+  const int slot = r < TQ ? c0 + q : nhp + c0 + q;
+  for (int g = s; g < ngroups; g += S) {
+    const int pt = g * PT + p;
+    if (have && pt < npt) {
+      cx<T> v[P];
+      const cx<T>* Bin = B + (size_t)pt * P * 2 * nhp + slot;
+#pragma unroll
+      for (int z = 0; z < P; ++z) v[z] = Bin[(size_t)z * 2 * nhp];
+      fft_reg<P, -1>(v);
+#pragma unroll
+      for (int i3 = 0; i3 < n1; ++i3) W[p][i3][r] = v[posKc<N, P>(i3)];
+    }
+    // stage the phase factors of this group's pairs
+    if (pt < npt) {
+      const int jA = pair0 + 2 * pt;
+      if (r < TQ && have) {
+        const int i2 = cpen / n1, i1 = cpen - i2 * n1;
+        const int k1 = i1 - h + 1, k2 = i2 - h + 1;
+        for (int w = 0; w < 2; ++w) {
+          const double2* pj = ph + (size_t)(jA + w) * 3 * PL + (N - 2);
+          const cx<double> e = cmul(d2c(pj[k1]), d2c(pj[PL + k2]));
+          E12[p][w][r] = double2{e.x, e.y};
+        }
+      }
+      for (int e = r; e < 2 * n1; e += 2 * TQ) {
+        const int w = e / n1, i3 = e - w * n1;
+        const double2* pj = ph + (size_t)(jA + w) * 3 * PL + (N - 2);
+        E3[p][w][i3] = pj[2 * PL + i3 - h + 1];
+      }
+      if (r < 2) CPV[p][r] = cp[jA + r];
+    }
+    __syncthreads();
+    const int np = min(PT, npt - g * PT);
+#pragma unroll
+    for (int b = 0; b < OPT; ++b) {
+      const int o = tid + b * NT;
+      if (o < TQ * n1) {
+        const int i3 = o / TQ, qq = o - i3 * TQ;
+        const int c = c0 + qq;
+        if (c < nh) {
+          for (int pp = 0; pp < np; ++pp) {
+            const int jA = pair0 + 2 * (g * PT + pp);
+            const cx<T> w1 = W[pp][i3][qq];
+            const cx<T> w2 = W[pp][n1 - 1 - i3][TQ + qq];
+            // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
+            const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
+            const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
+            const size_t vi = (size_t)i3 * nh + c;
+            const double vA = CPV[pp][0] * (double)V[(size_t)jA * nh * n1 + vi];
+            const double vB = CPV[pp][1] * (double)V[(size_t)(jA + 1) * nh * n1 + vi];
+            const cx<double> eA = cmul(d2c(E12[pp][0][qq]), d2c(E3[pp][0][i3]));
+            const cx<double> eB = cmul(d2c(E12[pp][1][qq]), d2c(E3[pp][1][i3]));
+            const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
+            accx[b] += vA * tA.x + vB * tB.x;
+            accy[b] += vA * tA.y + vB * tB.y;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < OPT; ++b) {
+    const int o = tid + b * NT;
+    if (o < TQ * n1) {
+      const int i3 = o / TQ, qq = o - i3 * TQ;
+      if (c0 + qq < nh) {
+        const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + qq;
+        double2 v = Qpart[qi];
+        v.x += accx[b];
+        v.y += accy[b];
+        Qpart[qi] = v;
+      }
+    }
   }
 }
 
@@ -406,7 +546,7 @@ __global__ void k_finalize(const double2* __restrict__ Qpart, double2* __restric
     }
     double x = 0.0, y = 0.0;
     for (int s = 0; s < S; ++s) {
-      const double2 v = Qpart[((size_t)s * nh + c) * n1 + i3];
+      const double2 v = Qpart[((size_t)s * n1 + i3) * nh + c];
       x += v.x;
       y += v.y;
     }
@@ -456,7 +596,7 @@ __global__ void k_table(TV* __restrict__ V, const double* __restrict__ pd, const
        e += (size_t)gridDim.x * blockDim.x) {
     const int j = (int)(e / per);
     const int rem = (int)(e - (size_t)j * per);
-    const int c = rem / n1, i3 = rem - c * n1;
+    const int i3 = rem / nh, c = rem - i3 * nh;
     const int i2 = c / n1, i1 = c - i2 * n1;
     const double k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
     const double* p = pd + (size_t)j * 8;
@@ -605,6 +745,15 @@ hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, con
 template <typename T, int P>
 hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
                   const void* tw, int N, int pair0, int npt, int S, hipStream_t st) {
+  if constexpr (RegFit<T, P>::value && isPad<P>()) {
+    using C = ZfwdCfg<T, P>;
+    constexpr int NN = padN<P>();
+    constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
+    dim3 grid((nh + C::TQ - 1) / C::TQ, S);
+    hipLaunchKernelGGL((k_zfwd_reg<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
+                       (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S);
+    return hipGetLastError();
+  }
   const int nn = (N - 1) * (N - 1), nh = (nn + 1) / 2;
   dim3 grid((nh + K3_TQ - 1) / K3_TQ, S);
   hipLaunchKernelGGL((k_zfwd<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)B,
