@@ -46,6 +46,9 @@ extern "C" {
 #endif
 
 typedef struct bzq_plan_s* bzq_plan;
+typedef struct bzq_workspace_s* bzq_workspace;
+typedef struct bzq_batch_s* bzq_batch;
+typedef struct bzq_server_s* bzq_server;
 
 typedef enum {
     BZQ_OK = 0,
@@ -120,16 +123,97 @@ bzq_status bzq_moments(bzq_plan p, const double* f_hat, const double* Q_hat, dou
 bzq_status bzq_check_finite(bzq_plan p, const double* f_hat, void* stream);
 
 /*
- * Independent cells (the batched form): Q_hats[i] = Q(f_hats[i]) under
- * plans[i], for count cells whose plans may differ in N, gamma, s and
- * precision.  All work is enqueued on `stream`; each cell's result is
- * bitwise identical to bzq_collision with the same plan.  Plans may repeat.
+ * Extra scratch for concurrent use of one plan: a plan's tables are
+ * read-only, so evaluations on different streams may share it as long as each
+ * stream uses its own workspace (the plan's built-in workspace serves
+ * bzq_collision / bzq_step).  Results are bitwise identical to the built-in
+ * path.  bzq_workspace_destroy synchronises the device.
+ */
+bzq_status bzq_workspace_create(bzq_workspace* out, bzq_plan p);
+bzq_status bzq_collision_ws(bzq_plan p, bzq_workspace w, const double* f_hat, double* Q_hat,
+                            void* stream);
+bzq_status bzq_step_ws(bzq_plan p, bzq_workspace w, double* f_hat, double dt, int n_steps,
+                       void* stream);
+size_t bzq_workspace_bytes(bzq_workspace w);
+bzq_status bzq_workspace_destroy(bzq_workspace w);
+
+/*
+ * Independent cells, simple form: Q_hats[i] = Q(f_hats[i]) under plans[i],
+ * enqueued cell after cell on `stream` with each plan's built-in workspace.
+ * Each result is bitwise identical to bzq_collision.
  */
 bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hats,
                                double* const* Q_hats, int count, void* stream);
 
+/*
+ * Independent cells, fused form.  A batch binds `count` cells (state arrays
+ * f_hats[i], device, complex128 N_i^3, owned by the caller and kept alive as
+ * long as the batch) to plans (which may repeat and may differ in N, gamma,
+ * kernel and precision).  Cells sharing a plan run in the same launches, up
+ * to 64 cells per launch; cells_per_launch = 0 lets an autotuner choose per
+ * plan (timing the candidates 1, 2, 4 ... 64 on these cells once, with the
+ * choice cached in the file $BZQ_TUNE_CACHE or ~/.cache/bzq_autotune.txt;
+ * workspaces are capped by $BZQ_BATCH_WS_MB, default 8192).  Creation is
+ * synchronous and allocates the workspaces.
+ *   bzq_batch_collision: Q_hats[i] = Q(f_hats[i]).
+ *   bzq_batch_step: n_steps Heun steps of every cell in place; use_graph != 0
+ *     captures one step of the whole batch into a HIP graph on first use (and
+ *     again when dt changes) and replays it.
+ * Every cell's result is bitwise identical to bzq_collision / bzq_step with
+ * its plan.  bzq_batch_group_info: out[4] = {N, cells, cells per launch,
+ * 1 if chosen by timing}.
+ */
+bzq_status bzq_batch_create(bzq_batch* out, const bzq_plan* plans, double* const* f_hats, int count,
+                            int cells_per_launch, void* stream);
+bzq_status bzq_batch_collision(bzq_batch b, double* const* Q_hats, void* stream);
+bzq_status bzq_batch_step(bzq_batch b, double dt, int n_steps, int use_graph, void* stream);
+int bzq_batch_groups(bzq_batch b);
+bzq_status bzq_batch_group_info(bzq_batch b, int group, int* out);
+size_t bzq_batch_device_bytes(bzq_batch b);
+bzq_status bzq_batch_destroy(bzq_batch b);
+
+/*
+ * Request server with continuous batching.  A request advances one cell by
+ * n_steps Heun steps of the power-law operator with the given parameters.
+ *   bzq_server_create: budget_bytes of device memory (>= 64 MiB) for cached
+ *     plans, workspaces and request state; `slots` (1..16) requests run
+ *     concurrently, each on its own stream.  A worker thread owns all device
+ *     work.
+ *   bzq_server_submit: copies f_host (host, complex128 N^3) and queues the
+ *     request; returns its id at once.  Thread-safe.
+ *   bzq_server_poll: 1 = done (result copied to f_out if not NULL, request
+ *     released), 0 = not yet, -1 = unknown id, -2 = failed (bzq_last_error
+ *     tells why; released).  times (optional, host double[3]) = arrival,
+ *     start and completion on the server's monotonic clock, seconds.
+ *   bzq_server_wait: blocks until request id is done or failed, or timeout.
+ *   bzq_server_stats: out[8] = submitted, completed, failed, queued, running,
+ *     device bytes in use, peak device bytes, plans evicted.
+ * Requests are admitted in arrival order when their plan (if not cached), a
+ * workspace and their state fit the budget; idle plans are evicted least
+ * recently used first; a request that cannot fit alone fails with ENOMEM.
+ * Each result is bitwise identical to bzq_step run alone.
+ */
+typedef struct {
+    int N;
+    double L, R, gamma, s;
+    int N_rho, M, precision;
+    double dt;
+    int n_steps;
+} bzq_request;
+
+bzq_status bzq_server_create(bzq_server* out, size_t budget_bytes, int slots);
+bzq_status bzq_server_submit(bzq_server s, const bzq_request* req, const double* f_host,
+                             unsigned long long* id);
+int bzq_server_poll(bzq_server s, unsigned long long id, double* f_out, double* times);
+bzq_status bzq_server_wait(bzq_server s, unsigned long long id, double timeout_s);
+bzq_status bzq_server_stats(bzq_server s, double* out);
+bzq_status bzq_server_destroy(bzq_server s);
+
 /* Device bytes held by the plan (tables + scratch), for admission control. */
 size_t bzq_plan_device_bytes(bzq_plan p);
+
+/* The same figure computed before creating a plan of this geometry. */
+size_t bzq_plan_bytes_estimate(int N, int N_rho, int M, int precision);
 
 /* Per-request state a caller needs besides a plan: f_hat and Q_hat for one
  * cell of size N (complex128 N^3 each). */

@@ -32,6 +32,14 @@ class BzqError(RuntimeError):
         self.code = code
 
 
+class BzqRequest(ctypes.Structure):
+    """Mirror of bzq_request (include/bzq.h)."""
+    _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("R", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("s", ctypes.c_double), ("N_rho", ctypes.c_int),
+                ("M", ctypes.c_int), ("precision", ctypes.c_int), ("dt", ctypes.c_double),
+                ("n_steps", ctypes.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it first (python -m paper_2004_11239_amd.build)")
@@ -50,6 +58,25 @@ def _load():
         "bzq_plan_info": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_pairs": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_weights": ([vp, i, ctypes.POINTER(d)], i),
+        "bzq_workspace_create": ([ctypes.POINTER(vp), vp], i),
+        "bzq_collision_ws": ([vp, vp, vp, vp, vp], i),
+        "bzq_step_ws": ([vp, vp, vp, d, i, vp], i),
+        "bzq_workspace_bytes": ([vp], sz),
+        "bzq_workspace_destroy": ([vp], i),
+        "bzq_batch_create": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i, i, vp], i),
+        "bzq_batch_collision": ([vp, ctypes.POINTER(vp), vp], i),
+        "bzq_batch_step": ([vp, d, i, i, vp], i),
+        "bzq_batch_groups": ([vp], i),
+        "bzq_batch_group_info": ([vp, i, ctypes.POINTER(i)], i),
+        "bzq_batch_device_bytes": ([vp], sz),
+        "bzq_batch_destroy": ([vp], i),
+        "bzq_server_create": ([ctypes.POINTER(vp), sz, i], i),
+        "bzq_server_submit": ([vp, ctypes.POINTER(BzqRequest), vp, ctypes.POINTER(ctypes.c_ulonglong)], i),
+        "bzq_server_poll": ([vp, ctypes.c_ulonglong, vp, ctypes.POINTER(d)], i),
+        "bzq_server_wait": ([vp, ctypes.c_ulonglong, d], i),
+        "bzq_server_stats": ([vp, ctypes.POINTER(d)], i),
+        "bzq_server_destroy": ([vp], i),
+        "bzq_plan_bytes_estimate": ([i, i, i, i], sz),
         "bzq_plan_set_timing": ([vp, i], i),
         "bzq_plan_stage_times": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_destroy": ([vp], i),
@@ -64,6 +91,11 @@ def _load():
 
 
 _lib = _load()
+EXPORTED_EXTRA = ("bzq_workspace_create", "bzq_collision_ws", "bzq_step_ws", "bzq_workspace_bytes",
+                  "bzq_workspace_destroy", "bzq_batch_create", "bzq_batch_collision", "bzq_batch_step",
+                  "bzq_batch_groups", "bzq_batch_group_info", "bzq_batch_device_bytes",
+                  "bzq_batch_destroy", "bzq_server_create", "bzq_server_submit", "bzq_server_poll",
+                  "bzq_server_wait", "bzq_server_stats", "bzq_server_destroy", "bzq_plan_bytes_estimate")
 EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_step", "bzq_moments",
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
@@ -217,3 +249,147 @@ def collision_batch(plans: Sequence[Plan], f_hats: Sequence[torch.Tensor], outs:
 
 def request_device_bytes(N: int) -> int:
     return int(_lib.bzq_request_device_bytes(int(N)))
+
+
+class Workspace:
+    """Extra scratch so that one plan can be evaluated on several streams at once."""
+
+    def __init__(self, plan: Plan):
+        h = ctypes.c_void_p()
+        _check(_lib.bzq_workspace_create(ctypes.byref(h), plan.handle))
+        self.plan = plan
+        self._h = h
+
+    def collision(self, f_hat, out=None, stream=None):
+        fp = _spectral(f_hat, self.plan.N, "f_hat")
+        if out is None:
+            out = torch.empty_like(f_hat)
+        _check(_lib.bzq_collision_ws(self.plan.handle, self._h, fp, _spectral(out, self.plan.N, "out"),
+                                     _stream(stream)))
+        return out
+
+    def step(self, f_hat, dt, n_steps=1, stream=None):
+        _check(_lib.bzq_step_ws(self.plan.handle, self._h, _spectral(f_hat, self.plan.N, "f_hat"),
+                                float(dt), int(n_steps), _stream(stream)))
+        return f_hat
+
+    def device_bytes(self):
+        return int(_lib.bzq_workspace_bytes(self._h))
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.bzq_workspace_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Fused evaluation of many independent cells (see bzq_batch_create)."""
+
+    def __init__(self, plans: Sequence[Plan], f_hats: Sequence[torch.Tensor], cells_per_launch: int = 0,
+                 stream=None):
+        n = len(plans)
+        if n != len(f_hats) or n == 0:
+            raise ValueError("plans and f_hats must be non-empty and of equal length")
+        self.plans = list(plans)
+        self.f_hats = list(f_hats)          # kept alive: the batch holds their pointers
+        P = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+        F = (ctypes.c_void_p * n)(*[_spectral(f, p.N, "f_hat") for p, f in zip(plans, f_hats)])
+        h = ctypes.c_void_p()
+        _check(_lib.bzq_batch_create(ctypes.byref(h), P, F, n, int(cells_per_launch), _stream(stream)))
+        self._h = h
+
+    def collision(self, outs: Sequence[torch.Tensor], stream=None):
+        n = len(self.plans)
+        Q = (ctypes.c_void_p * n)(*[_spectral(q, p.N, "out") for p, q in zip(self.plans, outs)])
+        _check(_lib.bzq_batch_collision(self._h, Q, _stream(stream)))
+        return outs
+
+    def step(self, dt: float, n_steps: int = 1, use_graph: bool = True, stream=None):
+        _check(_lib.bzq_batch_step(self._h, float(dt), int(n_steps), int(bool(use_graph)), _stream(stream)))
+
+    def groups(self):
+        out = []
+        for g in range(_lib.bzq_batch_groups(self._h)):
+            v = (ctypes.c_int * 4)()
+            _check(_lib.bzq_batch_group_info(self._h, g, v))
+            out.append({"N": v[0], "cells": v[1], "cells_per_launch": v[2], "tuned": bool(v[3])})
+        return out
+
+    def device_bytes(self):
+        return int(_lib.bzq_batch_device_bytes(self._h))
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.bzq_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server with continuous batching (see bzq_server_create)."""
+
+    def __init__(self, budget_bytes: int, slots: int = 4):
+        h = ctypes.c_void_p()
+        _check(_lib.bzq_server_create(ctypes.byref(h), int(budget_bytes), int(slots)))
+        self._h = h
+
+    def submit(self, f_hat_host, N, L, R, gamma, s, N_rho, M, precision="fp32", dt=0.01, n_steps=10):
+        import numpy as np
+        f = np.ascontiguousarray(f_hat_host, dtype=np.complex128)
+        if f.shape != (N, N, N):
+            raise ValueError("f_hat must be (N, N, N)")
+        req = BzqRequest(N, L, R, gamma, s, N_rho, M, _PREC[precision], dt, n_steps)
+        rid = ctypes.c_ulonglong()
+        _check(_lib.bzq_server_submit(self._h, ctypes.byref(req), f.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, rid: int, N: int):
+        """None if not finished, else (f_hat_result, (arrival, start, done))."""
+        import numpy as np
+        out = np.empty((N, N, N), dtype=np.complex128)
+        t = (ctypes.c_double * 3)()
+        r = _lib.bzq_server_poll(self._h, ctypes.c_ulonglong(rid), out.ctypes.data_as(ctypes.c_void_p), t)
+        if r == 0:
+            return None
+        if r == -1:
+            raise KeyError(rid)
+        if r == -2:
+            raise BzqError(2, _lib.bzq_last_error().decode())
+        return out, (t[0], t[1], t[2])
+
+    def wait(self, rid: int, timeout: float = 600.0):
+        _check(_lib.bzq_server_wait(self._h, ctypes.c_ulonglong(rid), float(timeout)))
+
+    def stats(self):
+        v = (ctypes.c_double * 8)()
+        _check(_lib.bzq_server_stats(self._h, v))
+        keys = ("submitted", "completed", "failed", "queued", "running", "device_bytes", "peak_device_bytes",
+                "evictions")
+        return {k: v[i] for i, k in enumerate(keys)}
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.bzq_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def plan_bytes_estimate(N: int, N_rho: int, M: int, precision="fp32") -> int:
+    return int(_lib.bzq_plan_bytes_estimate(int(N), int(N_rho), int(M), _PREC[precision]))

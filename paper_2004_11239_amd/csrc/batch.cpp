@@ -1,0 +1,334 @@
+// Batched executor: many independent homogeneous cells, each with its own
+// f_hat, advanced together.  Cells that share a plan (same N, L, R, gamma,
+// kernel, quadrature and precision) share its weight tables and run in the
+// same launches, stacked along the grid's third dimension (up to 64 cells per
+// launch); the kernels, chunking and accumulation order per cell are those of
+// a single evaluation, so every cell's result is bitwise identical to
+// bzq_collision / bzq_step on its own.
+//
+// Cells per launch are chosen per plan by a small autotuner (time one
+// evaluation of each candidate count on the batch's own data, keep the
+// fastest per-cell time) whose choices persist in a text cache keyed by the
+// plan geometry.  A whole Heun step of the batch can be captured once into a
+// HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include <sys/stat.h>
+
+#include "plan.hpp"
+
+namespace bzq {
+namespace {
+
+struct Group {
+  Plan* plan = nullptr;
+  std::vector<int> cells;   // indices into the batch's cell list
+  int cpl = 1;              // cells per launch
+  bool tuned = false;       // cpl came from timing (not from the cache or the caller)
+  Workspace* ws = nullptr;
+};
+
+std::string tune_key(const Plan& p) {
+  std::ostringstream k;
+  k << "N=" << p.N << " P=" << p.P << " prec=" << (p.fp32 ? "fp32" : "fp64") << " npairs=" << p.npairs
+    << " G=" << p.G << " S=" << p.S;
+  return k.str();
+}
+
+std::string tune_path() {
+  const char* e = std::getenv("BZQ_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h && *h ? h : "/tmp") + "/.cache/bzq_autotune.txt";
+}
+
+std::map<std::string, int> read_cache() {
+  std::map<std::string, int> m;
+  std::ifstream in(tune_path());
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t bar = line.rfind('|');
+    if (bar == std::string::npos) continue;
+    m[line.substr(0, bar)] = std::atoi(line.c_str() + bar + 1);
+  }
+  return m;
+}
+
+void write_cache(const std::map<std::string, int>& m) {
+  const std::string path = tune_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) (void)::mkdir(path.substr(0, slash).c_str(), 0755);
+  std::ofstream out(path, std::ios::trunc);
+  if (!out) return;   // a read-only home only loses the cache
+  for (const auto& kv : m) out << kv.first << "|" << kv.second << "\n";
+}
+
+size_t ws_budget_bytes() {
+  const char* e = std::getenv("BZQ_BATCH_WS_MB");
+  const size_t mb = e ? (size_t)std::atoll(e) : 8192;
+  return mb << 20;
+}
+
+}  // namespace
+}  // namespace bzq
+
+using namespace bzq;
+
+struct bzq_batch_s {
+  std::vector<double*> f;
+  std::vector<Group> groups;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;   // private stream the graph is recorded on
+  double graph_dt = 0.0;
+
+  ~bzq_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (capture) (void)hipStreamDestroy(capture);
+    for (auto& g : groups) delete g.ws;
+  }
+};
+
+namespace {
+
+PtrPack pack(const std::vector<double*>& ptrs, const std::vector<int>& idx, size_t from, int n) {
+  PtrPack pk{};
+  for (int i = 0; i < n; ++i) pk.p[i] = ptrs[idx[from + i]];
+  return pk;
+}
+
+// time one evaluation of `n` cells of group g with `cpl` cells per launch
+bzq_status time_candidate(Group& g, const std::vector<double*>& f, int cpl, hipStream_t st, float* ms_per_cell) {
+  Workspace w;
+  bzq_status s = workspace_init(w, *g.plan, cpl);
+  if (s != BZQ_OK) return s;
+  const int n = std::min<int>((int)g.cells.size(), 2 * cpl);
+  const size_t n3 = (size_t)g.plan->N * g.plan->N * g.plan->N;
+  hipEvent_t e0, e1;
+  BZQ_HIP_TRY(hipEventCreate(&e0));
+  BZQ_HIP_TRY(hipEventCreate(&e1));
+  auto run = [&]() -> bzq_status {
+    for (int c0 = 0; c0 < n; c0 += cpl) {
+      const int m = std::min(cpl, n - c0);
+      PtrPack out{};
+      for (int i = 0; i < m; ++i) out.p[i] = w.q1 + i * n3 * 2;
+      bzq_status r = enqueue_collision(*g.plan, w, pack(f, g.cells, c0, m), out, m, st);
+      if (r != BZQ_OK) return r;
+    }
+    return BZQ_OK;
+  };
+  const bool timing = g.plan->timing;
+  g.plan->timing = false;
+  s = run();   // warm-up
+  if (s == BZQ_OK) {
+    (void)hipEventRecord(e0, st);
+    s = run();
+    (void)hipEventRecord(e1, st);
+  }
+  g.plan->timing = timing;
+  float ms = 0;
+  if (s == BZQ_OK) {
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(&ms, e0, e1);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  *ms_per_cell = ms / n;
+  return s;
+}
+
+bzq_status autotune(Group& g, const std::vector<double*>& f, hipStream_t st) {
+  auto cache = read_cache();
+  const std::string key = tune_key(*g.plan);
+  auto it = cache.find(key);
+  const int ncell = (int)g.cells.size();
+  const size_t per_cell = g.plan->workspace_bytes_per_cell();
+  const int mem_cap = (int)std::max<size_t>(1, ws_budget_bytes() / per_cell);
+  if (it != cache.end() && it->second >= 1) {
+    g.cpl = std::max(1, std::min({it->second, ncell, kMaxCells, mem_cap}));
+    return BZQ_OK;
+  }
+  int best = 1;
+  float best_ms = 1e30f;
+  for (int c : {1, 2, 4, 8, 16, 32, 64}) {
+    if (c > ncell || c > mem_cap || c > kMaxCells) break;
+    float ms = 0;
+    bzq_status s = time_candidate(g, f, c, st, &ms);
+    if (s == BZQ_ENOMEM) break;
+    if (s != BZQ_OK) return s;
+    if (ms < best_ms * 0.97f) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  g.cpl = best;
+  g.tuned = true;
+  if (ncell >= 2 * best) {   // only a choice made with room to spare is worth caching
+    cache[key] = best;
+    write_cache(cache);
+  }
+  return BZQ_OK;
+}
+
+bzq_status enqueue_batch_step(bzq_batch_s* b, double dt, hipStream_t st) {
+  for (auto& g : b->groups) {
+    for (size_t c0 = 0; c0 < g.cells.size(); c0 += g.cpl) {
+      const int m = (int)std::min<size_t>(g.cpl, g.cells.size() - c0);
+      bzq_status s = enqueue_step(*g.plan, *g.ws, pack(b->f, g.cells, c0, m), m, dt, 1, st);
+      if (s != BZQ_OK) return s;
+    }
+  }
+  return BZQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bzq_status bzq_batch_create(bzq_batch* out, const bzq_plan* plans, double* const* f_hats, int count,
+                            int cells_per_launch, void* stream) {
+  if (!out) return fail(BZQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !plans || !f_hats) return fail(BZQ_EINVAL, "bad batch arguments");
+  if (cells_per_launch < 0 || cells_per_launch > kMaxCells) return fail(BZQ_EINVAL, "cells_per_launch must lie in [0, 64]");
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !f_hats[i]) return fail(BZQ_EINVAL, "NULL entry in batch");
+  hipStream_t st = (hipStream_t)stream;
+  auto* b = new bzq_batch_s();
+  b->f.assign(f_hats, f_hats + count);
+  std::map<const Plan*, int> gid;
+  for (int i = 0; i < count; ++i) {
+    auto it = gid.find(plans[i]);
+    if (it == gid.end()) {
+      gid[plans[i]] = (int)b->groups.size();
+      Group g;
+      g.plan = plans[i];
+      b->groups.push_back(g);
+      it = gid.find(plans[i]);
+    }
+    b->groups[it->second].cells.push_back(i);
+  }
+  for (auto& g : b->groups) {
+    bzq_status s = BZQ_OK;
+    if (cells_per_launch > 0)
+      g.cpl = std::min<int>(cells_per_launch, (int)g.cells.size());
+    else
+      s = autotune(g, b->f, st);
+    if (s == BZQ_OK) {
+      g.ws = new Workspace();
+      s = workspace_init(*g.ws, *g.plan, g.cpl);
+    }
+    if (s != BZQ_OK) {
+      delete b;
+      return s;
+    }
+  }
+  *out = b;
+  return BZQ_OK;
+}
+
+bzq_status bzq_batch_collision(bzq_batch b, double* const* Q_hats, void* stream) {
+  if (!b || !Q_hats) return fail(BZQ_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double*> q(Q_hats, Q_hats + b->f.size());
+  for (double* x : q)
+    if (!x) return fail(BZQ_EINVAL, "NULL output in batch");
+  for (auto& g : b->groups) {
+    for (size_t c0 = 0; c0 < g.cells.size(); c0 += g.cpl) {
+      const int m = (int)std::min<size_t>(g.cpl, g.cells.size() - c0);
+      bzq_status s = enqueue_collision(*g.plan, *g.ws, pack(b->f, g.cells, c0, m), pack(q, g.cells, c0, m), m, st);
+      if (s != BZQ_OK) return s;
+    }
+  }
+  return BZQ_OK;
+}
+
+bzq_status bzq_batch_step(bzq_batch b, double dt, int n_steps, int use_graph, void* stream) {
+  if (!b) return fail(BZQ_EINVAL, "NULL batch");
+  if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
+  hipStream_t st = (hipStream_t)stream;
+  if (!use_graph) {
+    for (int i = 0; i < n_steps; ++i) {
+      bzq_status s = enqueue_batch_step(b, dt, st);
+      if (s != BZQ_OK) return s;
+    }
+    return BZQ_OK;
+  }
+  if (!b->exec || b->graph_dt != dt) {
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    // record on a private stream (the legacy default stream cannot be
+    // captured); nothing runs while recording, the graph is replayed on `st`
+    if (!b->capture) BZQ_HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    std::vector<bool> timing;
+    for (auto& g : b->groups) { timing.push_back(g.plan->timing); g.plan->timing = false; }
+    BZQ_HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    bzq_status s = enqueue_batch_step(b, dt, b->capture);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(b->capture, &graph);
+    for (size_t i = 0; i < b->groups.size(); ++i) b->groups[i].plan->timing = timing[i];
+    if (s != BZQ_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(BZQ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    b->graph = graph;
+    BZQ_HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_dt = dt;
+  }
+  for (int i = 0; i < n_steps; ++i) BZQ_HIP_TRY(hipGraphLaunch(b->exec, st));
+  return BZQ_OK;
+}
+
+int bzq_batch_groups(bzq_batch b) { return b ? (int)b->groups.size() : 0; }
+
+bzq_status bzq_batch_group_info(bzq_batch b, int group, int* out) {
+  if (!b || !out || group < 0 || group >= (int)b->groups.size()) return fail(BZQ_EINVAL, "bad group");
+  const Group& g = b->groups[group];
+  out[0] = g.plan->N;
+  out[1] = (int)g.cells.size();
+  out[2] = g.cpl;
+  out[3] = g.tuned ? 1 : 0;
+  return BZQ_OK;
+}
+
+size_t bzq_batch_device_bytes(bzq_batch b) {
+  size_t n = 0;
+  if (b)
+    for (auto& g : b->groups) n += g.ws ? g.ws->arena.bytes : 0;
+  return n;
+}
+
+bzq_status bzq_batch_destroy(bzq_batch b) {
+  if (!b) return BZQ_OK;
+  (void)hipDeviceSynchronize();
+  delete b;
+  return BZQ_OK;
+}
+
+bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hats, double* const* Q_hats,
+                               int count, void* stream) {
+  if (count < 0 || (count > 0 && (!plans || !f_hats || !Q_hats))) return fail(BZQ_EINVAL, "bad batch arguments");
+  for (int i = 0; i < count; ++i)
+    if (!plans[i] || !f_hats[i] || !Q_hats[i]) return fail(BZQ_EINVAL, "NULL entry in batch");
+  for (int i = 0; i < count; ++i) {
+    bzq_status s = enqueue_collision(*plans[i], plans[i]->ws, single(f_hats[i]), single(Q_hats[i]), 1,
+                                     (hipStream_t)stream);
+    if (s != BZQ_OK) return s;
+  }
+  return BZQ_OK;
+}
+
+}  // extern "C"

@@ -1,5 +1,7 @@
 // The C ABI of include/bzq.h: plan construction (quadrature rules, weight
-// tables, scratch) and the host-side orchestration of the device pipeline.
+// tables), workspaces, and the host-side orchestration of the device pipeline
+// for single cells.  Batched cells live in batch.cpp, the request server in
+// server.cpp.
 //
 // A plan holds, for the operator of eq. realQ:
 //   * the antipodal quadrature pairs (rho_p, sigma_q+), sigma_q+ from the half
@@ -11,9 +13,9 @@
 //   * the real weight V_j(k) = 2 w_sigma Re(e^{-ix} F(k, rho, sigma)) / P^3,
 //     x = pi rho k.sigma / (2L), on the half spectrum, built on the device;
 //     Phi(rho) rho^2 w_rho = w_rho rho^{2+gamma} is applied per pair at run
-//     time so one table serves every gamma;
+//     time;
 //   * the separable phase tables e^{i pi rho n sigma_d / (2L)} for |n| <= N-2;
-//   * twiddles and the scratch of the chunked pipeline.
+//   * twiddles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,107 +25,126 @@
 #include <string>
 #include <vector>
 
-#include "../../include/bzq.h"
-#include "kernels.hpp"
+#include "plan.hpp"
 #include "quadrature.hpp"
 
-namespace {
+namespace bzq {
 
+namespace {
 thread_local std::string g_last_error;
+const long double kPi = 3.141592653589793238462643383279502884L;
+constexpr int kMomentBlocks = 256;
+
+bool supported_N(int N) { return N == 8 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64; }
+}  // namespace
 
 bzq_status fail(bzq_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
 }
 
-#define HIP_TRY(expr)                                                                        \
-  do {                                                                                       \
-    hipError_t e_ = (expr);                                                                  \
-    if (e_ != hipSuccess)                                                                    \
-      return fail(BZQ_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));          \
-  } while (0)
-
-const long double kPi = 3.141592653589793238462643383279502884L;
-
-bool supported_N(int N) {
-  return N == 8 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64;
+DeviceArena::~DeviceArena() {
+  for (void* p : allocs) (void)hipFree(p);
 }
 
-}  // namespace
-
-struct bzq_plan_s {
-  int N = 0, P = 0, n1 = 0, nn = 0, nh = 0, nhp = 0;
-  double L = 0, R = 0, gamma = 0, bc = 0, bs = 0, br = 0;
-  int N_rho = 0, M = 0, nj = 0;
-  bool fp32 = false;
-  int npairs = 0;     // antipodal pairs incl. a zero pad to make the count even
-  int npt = 0;        // pairs of pairs (packed into one complex transform)
-  int G = 0;          // pair-twos per chunk
-  int S = 0;          // accumulation splits of the last stage
-  std::vector<double> pair_host;  // [npairs][6] for introspection
-  size_t bytes = 0;
-  size_t esz = 0;     // bytes per real element (4 or 8)
-  // device
-  void* V = nullptr;            // [npairs][nh][n1] real
-  double* ph = nullptr;         // [npairs][3][2N-3] complex128
-  double* cp = nullptr;         // [npairs]
-  void* tw_pad = nullptr;       // P twiddles, compute precision
-  double* tw_grid = nullptr;    // N twiddles, FP64 (physical grid transforms)
-  void* fc = nullptr;           // (N-1)^3 complex, compute precision
-  void* fgrid = nullptr;        // P^3 real, compute precision
-  void* A = nullptr;            // G * P * nn complex
-  void* Bbuf = nullptr;         // G * P * nn complex
-  double* Qpart = nullptr;      // S * nh * n1 complex128
-  double* q1 = nullptr;         // N^3 complex128 each: step / moments scratch
-  double* q2 = nullptr;
-  double* fs = nullptr;
-  double* gfc = nullptr;        // (N-1)^3 complex128
-  double* gA = nullptr;         // N * nn complex128
-  double* gf = nullptr;         // N^3 real
-  double* gq = nullptr;         // N^3 real
-  double* part = nullptr;       // moment partials
-  int* flag = nullptr;
-  std::vector<void*> allocs;
-  // optional per-launch timing (HIP events recorded around every launch)
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_stage;      // stage of the launch bracketed by events 2i, 2i+1
-  size_t ev_used = 0;
-
-  ~bzq_plan_s() {
-    for (void* p : allocs) (void)hipFree(p);
-    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+bzq_status DeviceArena::alloc(void** out, size_t nbytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, nbytes ? nbytes : 16);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(BZQ_ENOMEM, "hipMalloc(" + std::to_string(nbytes) + ") failed: " + hipGetErrorString(e));
   }
-  template <typename Tp>
-  bzq_status alloc(Tp** out, size_t nbytes) {
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, nbytes ? nbytes : 16);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(BZQ_ENOMEM, "hipMalloc(" + std::to_string(nbytes) + ") failed: " + hipGetErrorString(e));
-    }
-    allocs.push_back(p);
-    bytes += nbytes;
-    *out = (Tp*)p;
-    return BZQ_OK;
-  }
-};
+  allocs.push_back(p);
+  bytes += nbytes;
+  *out = p;
+  return BZQ_OK;
+}
+
+Plan::~Plan() {
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
+size_t Plan::workspace_bytes_per_cell() const {
+  const size_t N3 = (size_t)N * N * N;
+  return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * nn * 2 * esz +
+         (size_t)G * P * 2 * nhp * 2 * esz + (size_t)S * nh * n1 * 16 + 3 * N3 * 16;
+}
+
+bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
+  if (cells < 1 || cells > kMaxCells) return fail(BZQ_EINVAL, "cells per launch must lie in [1, 64]");
+  w.plan = &p;
+  w.cells = cells;
+  w.cs.fc = (size_t)p.n1 * p.nn;
+  w.cs.fg = (size_t)p.P * p.P * p.P;
+  w.cs.a = (size_t)p.G * p.P * p.nn;
+  w.cs.b = (size_t)p.G * p.P * 2 * p.nhp;
+  w.cs.qp = (size_t)p.S * p.nh * p.n1;
+  w.cs.cells = cells;
+  const size_t N3 = (size_t)p.N * p.N * p.N;
+  bzq_status s;
+  if ((s = w.arena.get(&w.fc, cells * w.cs.fc * 2 * p.esz)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.fgrid, cells * w.cs.fg * p.esz)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.A, cells * w.cs.a * 2 * p.esz)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.B, cells * w.cs.b * 2 * p.esz)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.Qpart, cells * w.cs.qp * 16)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.q1, cells * N3 * 16)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.q2, cells * N3 * 16)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.fs, cells * N3 * 16)) != BZQ_OK) return s;
+  return BZQ_OK;
+}
+
+// Chunking of the pair loop: the two pipeline intermediates stay below 1 GiB
+// per cell (one chunk per evaluation up to N = 32); the splits S of the last
+// stage give enough workgroups to fill the chip but no more than there are
+// groups of pair-twos (4 per group in the register variant).
+void set_chunking(Plan& p) {
+  p.esz = p.fp32 ? 4 : 8;
+  p.nhp = (p.nh + 15) / 16 * 16;
+  const size_t per_pt = (size_t)p.P * (p.nn + 2 * p.nhp) * 2 * p.esz;
+  p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, (1024ull << 20) / per_pt));
+  const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
+  const int tq = reg_zfwd ? 16 : 8;
+  const int groups = reg_zfwd ? (p.G + 3) / 4 : p.G;
+  const int tiles = (p.nh + tq - 1) / tq;
+  p.S = std::max(1, std::min(groups, (2048 + tiles - 1) / tiles));
+}
+
+// Device bytes a plan will hold (tables, its workspace, grid scratch), from
+// its geometry alone; Lebedev rules are centrally symmetric, so the number of
+// antipodal pairs is N_rho M / 2 rounded up to even.
+size_t plan_footprint(int N, int N_rho, int M, int precision) {
+  Plan p;
+  p.N = N;
+  p.P = 3 * N / 2;
+  p.n1 = N - 1;
+  p.nn = p.n1 * p.n1;
+  p.nh = (p.nn + 1) / 2;
+  p.fp32 = precision == BZQ_FP32_ACC64;
+  const int nreal = N_rho * (M / 2);
+  p.npairs = nreal + (nreal & 1);
+  p.npt = p.npairs / 2;
+  set_chunking(p);
+  const size_t n3 = (size_t)N * N * N;
+  const size_t tables = (size_t)p.npairs * p.nh * p.n1 * p.esz + (size_t)p.npairs * 3 * (2 * N - 3) * 16 +
+                        (size_t)p.npairs * 8 + (size_t)p.P * 2 * p.esz + (size_t)N * 16;
+  const size_t grid = (size_t)p.n1 * p.nn * 16 + (size_t)N * p.nn * 16 + 2 * n3 * 8 + 256 * 8 * 8 + 16;
+  return tables + p.workspace_bytes_per_cell() + grid;
+}
 
 namespace {
 
-constexpr int kMomentBlocks = 256;
-
-bzq_status build_plan(bzq_plan_s* p, hipStream_t st) {
-  const int N = p->N, P = p->P, n1 = p->n1, nn = p->nn, nh = p->nh;
+bzq_status build_plan(Plan* p, hipStream_t st) {
+  const int N = p->N, P = p->P, nn = p->nn, nh = p->nh;
   // -- quadrature
   std::vector<double> rho, wr;
-  bzq::gauss_legendre(p->N_rho, p->R, rho, wr);
+  gauss_legendre(p->N_rho, p->R, rho, wr);
   std::vector<double> leb, half;
-  if (!bzq::lebedev_rule(p->M, leb)) return fail(BZQ_EINVAL, "M is not the size of an available Lebedev rule");
-  const int Mh = bzq::lebedev_half(leb, half);
+  if (!lebedev_rule(p->M, leb)) return fail(BZQ_EINVAL, "M is not the size of an available Lebedev rule");
+  const int Mh = lebedev_half(leb, half);
   if (Mh < 1) return fail(BZQ_EINVAL, "sphere rule is not centrally symmetric");
   std::vector<double> gt, gw;
-  if (!bzq::gauss_jacobi01(p->nj, p->bs, p->br, gt, gw)) return fail(BZQ_EINVAL, "Gauss-Jacobi rule failed");
+  if (!gauss_jacobi01(p->nj, p->bs, p->br, gt, gw)) return fail(BZQ_EINVAL, "Gauss-Jacobi rule failed");
   const int nreal = p->N_rho * Mh;
   p->npairs = nreal + (nreal & 1);
   p->npt = p->npairs / 2;
@@ -162,51 +183,29 @@ bzq_status build_plan(bzq_plan_s* p, hipStream_t st) {
         ph[o + 1] = (double)sinl(ang);
       }
   }
-  // -- chunking: the two pipeline intermediates stay below 1 GiB (one chunk
-  //    per evaluation up to N = 32; they stream through HBM either way)
-  p->esz = p->fp32 ? 4 : 8;
-  p->nhp = (nh + 15) / 16 * 16;
-  const size_t per_pt = (size_t)P * (nn + 2 * p->nhp) * 2 * p->esz;
-  p->G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p->npt, (1024ull << 20) / per_pt));
-  // splits of the last stage: enough workgroups to fill the chip, but no more
-  // than there are groups of pair-twos (4 per group in the register variant)
-  const bool reg_zfwd = p->fp32 ? true : (P <= 48);
-  const int tq = reg_zfwd ? 16 : 8;
-  const int groups = reg_zfwd ? (p->G + 3) / 4 : p->G;
-  const int tiles = (nh + tq - 1) / tq;
-  p->S = std::max(1, std::min(groups, (2048 + tiles - 1) / tiles));
-  // -- allocations
+  set_chunking(*p);
+  // -- tables
   bzq_status s;
-  const size_t vcount = (size_t)p->npairs * nh * n1;
-#define ALLOC(ptr, nbytes) if ((s = p->alloc(&(ptr), (nbytes))) != BZQ_OK) return s
-  ALLOC(p->V, vcount * p->esz);
-  ALLOC(p->ph, ph.size() * sizeof(double));
-  ALLOC(p->cp, cp.size() * sizeof(double));
-  ALLOC(p->tw_pad, (size_t)P * 2 * p->esz);
-  ALLOC(p->tw_grid, (size_t)N * 2 * sizeof(double));
-  ALLOC(p->fc, (size_t)n1 * nn * 2 * p->esz);
-  ALLOC(p->fgrid, (size_t)P * P * P * p->esz);
-  ALLOC(p->A, (size_t)p->G * P * nn * 2 * p->esz);
-  ALLOC(p->Bbuf, (size_t)p->G * P * 2 * p->nhp * 2 * p->esz);
-  ALLOC(p->Qpart, (size_t)p->S * nh * n1 * 2 * sizeof(double));
+  const size_t vcount = (size_t)p->npairs * nh * p->n1;
+  if ((s = p->tables.get(&p->V, vcount * p->esz)) != BZQ_OK) return s;
+  if ((s = p->tables.get(&p->ph, ph.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->tables.get(&p->cp, cp.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->tables.get(&p->tw_pad, (size_t)P * 2 * p->esz)) != BZQ_OK) return s;
+  if ((s = p->tables.get(&p->tw_grid, (size_t)N * 2 * sizeof(double))) != BZQ_OK) return s;
+  // -- the plan's own workspace and grid scratch
+  if ((s = workspace_init(p->ws, *p, 1)) != BZQ_OK) return s;
   const size_t n3 = (size_t)N * N * N;
-  ALLOC(p->q1, n3 * 2 * sizeof(double));
-  ALLOC(p->q2, n3 * 2 * sizeof(double));
-  ALLOC(p->fs, n3 * 2 * sizeof(double));
-  ALLOC(p->gfc, (size_t)n1 * nn * 2 * sizeof(double));
-  ALLOC(p->gA, (size_t)N * nn * 2 * sizeof(double));
-  ALLOC(p->gf, n3 * sizeof(double));
-  ALLOC(p->gq, n3 * sizeof(double));
-  ALLOC(p->part, (size_t)kMomentBlocks * 8 * sizeof(double));
-  ALLOC(p->flag, sizeof(int) * 4);
-#undef ALLOC
+  if ((s = p->grid_scratch.get(&p->gfc, (size_t)p->n1 * nn * 2 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->gA, (size_t)N * nn * 2 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->gf, n3 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->gq, n3 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->part, (size_t)kMomentBlocks * 8 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->flag, sizeof(int) * 4)) != BZQ_OK) return s;
+  DeviceArena tmp;
   double* d_pd = nullptr;
   double* d_gj = nullptr;
-  HIP_TRY(hipMalloc(&d_pd, pd.size() * sizeof(double)));
-  if (hipMalloc(&d_gj, 2 * gt.size() * sizeof(double)) != hipSuccess) {
-    (void)hipFree(d_pd);
-    return fail(BZQ_ENOMEM, "hipMalloc for Gauss-Jacobi nodes failed");
-  }
+  if ((s = tmp.get(&d_pd, pd.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = tmp.get(&d_gj, 2 * gt.size() * sizeof(double))) != BZQ_OK) return s;
   std::vector<double> gj(gt);
   gj.insert(gj.end(), gw.begin(), gw.end());
   // twiddles e^{-2 pi i m / n}
@@ -220,31 +219,87 @@ bzq_status build_plan(bzq_plan_s* p, hipStream_t st) {
     twg[2 * m + 1] = (double)-sinl(2 * kPi * m / N);
   }
   std::vector<float> twpf(twp.begin(), twp.end());
-  bzq_status rc = BZQ_OK;
-  auto copy = [&](void* dst, const void* src, size_t n) -> bool {
-    hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) { rc = fail(BZQ_EDEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e)); return false; }
-    return true;
-  };
-  bool ok = copy(p->ph, ph.data(), ph.size() * sizeof(double)) &&
-            copy(p->cp, cp.data(), cp.size() * sizeof(double)) &&
-            copy(d_pd, pd.data(), pd.size() * sizeof(double)) &&
-            copy(d_gj, gj.data(), gj.size() * sizeof(double)) &&
-            copy(p->tw_grid, twg.data(), twg.size() * sizeof(double)) &&
-            (p->fp32 ? copy(p->tw_pad, twpf.data(), twpf.size() * sizeof(float))
-                     : copy(p->tw_pad, twp.data(), twp.size() * sizeof(double)));
-  if (ok) {
-    hipError_t e = bzq::launch_table(p->V, d_pd, d_gj, p->nj, N, p->npairs, p->fp32, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) rc = fail(BZQ_EDEVICE, std::string("weight table: ") + hipGetErrorString(e));
-  }
-  (void)hipFree(d_pd);
-  (void)hipFree(d_gj);
-  return rc;
+  BZQ_HIP_TRY(hipMemcpyAsync(p->ph, ph.data(), ph.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(p->cp, cp.data(), cp.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(d_pd, pd.data(), pd.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(d_gj, gj.data(), gj.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(p->tw_grid, twg.data(), twg.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  if (p->fp32)
+    BZQ_HIP_TRY(hipMemcpyAsync(p->tw_pad, twpf.data(), twpf.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  else
+    BZQ_HIP_TRY(hipMemcpyAsync(p->tw_pad, twp.data(), twp.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(launch_table(p->V, d_pd, d_gj, p->nj, N, p->npairs, p->fp32, st));
+  BZQ_HIP_TRY(hipStreamSynchronize(st));
+  return BZQ_OK;
 }
 
-bzq_status create_common(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
-                         double br, int nj, int N_rho, int M, int precision, void* stream) {
+enum Stage { ST_PREP = 0, ST_ZINV = 1, ST_PLANE = 2, ST_ZFWD = 3, ST_FINAL = 4, ST_COUNT = 5 };
+
+// Record an event before (begin=true) or after a launch when timing is on.
+hipError_t mark(Plan& p, int stage, bool begin, hipStream_t st) {
+  if (!p.timing) return hipSuccess;
+  if (p.ev_used == p.ev_pool.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    p.ev_pool.push_back(e);
+  }
+  if (begin) p.ev_stage.push_back(stage);
+  return hipEventRecord(p.ev_pool[p.ev_used++], st);
+}
+
+#define TIMED(stage, expr)                                \
+  do {                                                    \
+    BZQ_HIP_TRY(mark(p, (stage), true, st));              \
+    BZQ_HIP_TRY(expr);                                    \
+    BZQ_HIP_TRY(mark(p, (stage), false, st));             \
+  } while (0)
+
+}  // namespace
+
+// Enqueue one evaluation of eq. realQ for `cells` cells of plan p.
+bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrPack& Q, int cells,
+                             hipStream_t st) {
+  if (cells < 1 || cells > w.cells) return fail(BZQ_EINVAL, "more cells than the workspace holds");
+  const Geometry g{p.N, p.P};
+  CellStrides cs = w.cs;
+  cs.cells = cells;
+  TIMED(ST_PREP, launch_ingest(f, w.fc, cs.fc, cells, p.N, p.fp32, st));
+  // f(v) on the padded grid, shared by every pair
+  TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
+  TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st));
+  TIMED(ST_PREP, launch_fill(w.Qpart, 0.0, cells * cs.qp * 2, st));
+  for (int c0 = 0; c0 < p.npt; c0 += p.G) {
+    const int n = std::min(p.G, p.npt - c0);
+    TIMED(ST_ZINV, launch_zinv(w.fc, p.ph, w.A, p.tw_pad, g, 2 * c0, n, ZINV_PAIRS, p.fp32, cs, st));
+    TIMED(ST_PLANE, launch_plane(w.A, w.B, w.fgrid, nullptr, p.tw_pad, g, n, PLANE_PRODUCT, p.fp32, cs, st));
+    TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, p.S, p.fp32, cs, st));
+  }
+  TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, p.S, st));
+  return BZQ_OK;
+}
+
+bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
+                        hipStream_t st) {
+  const size_t n3 = (size_t)p.N * p.N * p.N;
+  PtrPack q1{}, q2{}, fs{};
+  for (int c = 0; c < cells; ++c) {
+    q1.p[c] = w.q1 + c * n3 * 2;
+    q2.p[c] = w.q2 + c * n3 * 2;
+    fs.p[c] = w.fs + c * n3 * 2;
+  }
+  for (int i = 0; i < n_steps; ++i) {
+    bzq_status s;
+    if ((s = enqueue_collision(p, w, f, q1, cells, st)) != BZQ_OK) return s;
+    BZQ_HIP_TRY(launch_axpy_cells(fs, f, dt, q1, n3, cells, st));
+    if ((s = enqueue_collision(p, w, fs, q2, cells, st)) != BZQ_OK) return s;
+    BZQ_HIP_TRY(launch_heun_cells(f, q1, q2, 0.5 * dt, n3, cells, st));
+  }
+  return BZQ_OK;
+}
+
+bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
+                       double br, int nj, int N_rho, int M, int precision, void* stream) {
   if (!out) return fail(BZQ_EINVAL, "out is NULL");
   *out = nullptr;
   if (N < 8 || (N & 1)) return fail(BZQ_EINVAL, "N must be even and >= 8");
@@ -258,7 +313,7 @@ bzq_status create_common(bzq_plan* out, int N, double L, double R, double gamma,
   if (N_rho < 1 || N_rho > 4096) return fail(BZQ_EINVAL, "N_rho must lie in [1, 4096]");
   if (precision != BZQ_FP64 && precision != BZQ_FP32_ACC64) return fail(BZQ_EINVAL, "unknown precision");
   std::vector<double> tmp;
-  if (!bzq::lebedev_rule(M, tmp)) return fail(BZQ_EINVAL, "M is not the size of an available Lebedev rule");
+  if (!lebedev_rule(M, tmp)) return fail(BZQ_EINVAL, "M is not the size of an available Lebedev rule");
   if (!supported_N(N)) return fail(BZQ_EUNSUPPORTED, "no FFT schedule for this N (supported: 8 16 24 32 48 64)");
   bzq_plan_s* p = new bzq_plan_s();
   p->N = N;
@@ -279,56 +334,27 @@ bzq_status create_common(bzq_plan* out, int N, double L, double R, double gamma,
   return BZQ_OK;
 }
 
-enum Stage { ST_PREP = 0, ST_ZINV = 1, ST_PLANE = 2, ST_ZFWD = 3, ST_FINAL = 4, ST_COUNT = 5 };
+double power_kernel_constant(double s) { return (1.0 - s) * (2.0 - s) / (24.0 * (double)kPi); }
 
-// Record an event before (begin=true) or after a launch when timing is on.
-hipError_t mark(bzq_plan_s* p, int stage, bool begin, hipStream_t st) {
-  if (!p->timing) return hipSuccess;
-  if (p->ev_used == p->ev_pool.size()) {
-    hipEvent_t e;
-    hipError_t r = hipEventCreate(&e);
-    if (r != hipSuccess) return r;
-    p->ev_pool.push_back(e);
-  }
-  if (begin) p->ev_stage.push_back(stage);
-  return hipEventRecord(p->ev_pool[p->ev_used++], st);
-}
-
-#define TIMED(stage, expr)                              \
-  do {                                                  \
-    HIP_TRY(mark(p, (stage), true, st));                \
-    HIP_TRY(expr);                                      \
-    HIP_TRY(mark(p, (stage), false, st));               \
-  } while (0)
-
-// Enqueue one evaluation of eq. realQ: f_hat (device, complex128 N^3) -> Q_hat.
-bzq_status enqueue_collision(bzq_plan_s* p, const double* f_hat, double* Q_hat, hipStream_t st) {
-  const bzq::Geometry g{p->N, p->P};
-  TIMED(ST_PREP, bzq::launch_ingest(f_hat, p->fc, p->N, p->fp32, st));
-  // f(v) on the padded grid, shared by every pair
-  TIMED(ST_PREP, bzq::launch_zinv(p->fc, nullptr, p->A, p->tw_pad, g, 0, 1, bzq::ZINV_PLAIN, p->fp32, st));
-  TIMED(ST_PREP, bzq::launch_plane(p->A, nullptr, nullptr, p->fgrid, p->tw_pad, g, 1, bzq::PLANE_TO_GRID, p->fp32, st));
-  TIMED(ST_PREP, bzq::launch_fill(p->Qpart, 0.0, (size_t)p->S * p->nh * p->n1 * 2, st));
-  for (int c0 = 0; c0 < p->npt; c0 += p->G) {
-    const int n = std::min(p->G, p->npt - c0);
-    TIMED(ST_ZINV, bzq::launch_zinv(p->fc, p->ph, p->A, p->tw_pad, g, 2 * c0, n, bzq::ZINV_PAIRS, p->fp32, st));
-    TIMED(ST_PLANE, bzq::launch_plane(p->A, p->Bbuf, p->fgrid, nullptr, p->tw_pad, g, n, bzq::PLANE_PRODUCT, p->fp32, st));
-    TIMED(ST_ZFWD, bzq::launch_zfwd(p->Bbuf, p->V, p->ph, p->cp, p->Qpart, p->tw_pad, g, 2 * c0, n, p->S, p->fp32, st));
-  }
-  TIMED(ST_FINAL, bzq::launch_finalize(p->Qpart, Q_hat, p->N, p->S, st));
-  return BZQ_OK;
-}
+namespace {
 
 // f on the physical N^3 grid (FP64) into dst, layout [z][x][y]
-bzq_status enqueue_to_grid(bzq_plan_s* p, const double* f_hat, double* dst, hipStream_t st) {
-  const bzq::Geometry g{p->N, p->N};
-  HIP_TRY(bzq::launch_ingest(f_hat, p->gfc, p->N, false, st));
-  HIP_TRY(bzq::launch_zinv(p->gfc, nullptr, p->gA, p->tw_grid, g, 0, 1, bzq::ZINV_GRID_SIGN, false, st));
-  HIP_TRY(bzq::launch_plane(p->gA, nullptr, nullptr, dst, p->tw_grid, g, 1, bzq::PLANE_TO_GRID, false, st));
+bzq_status enqueue_to_grid(Plan& p, const double* f_hat, double* dst, hipStream_t st) {
+  const Geometry g{p.N, p.N};
+  CellStrides cs{};
+  cs.cells = 1;
+  BZQ_HIP_TRY(launch_ingest(single(f_hat), p.gfc, 0, 1, p.N, false, st));
+  BZQ_HIP_TRY(launch_zinv(p.gfc, nullptr, p.gA, p.tw_grid, g, 0, 1, ZINV_GRID_SIGN, false, cs, st));
+  BZQ_HIP_TRY(launch_plane(p.gA, nullptr, nullptr, dst, p.tw_grid, g, 1, PLANE_TO_GRID, false, cs, st));
   return BZQ_OK;
 }
 
 }  // namespace
+}  // namespace bzq
+
+using namespace bzq;
+
+struct bzq_workspace_s : bzq::Workspace {};
 
 extern "C" {
 
@@ -338,34 +364,60 @@ bzq_status bzq_plan_create(bzq_plan* out, int N, double L, double R, double gamm
     if (out) *out = nullptr;
     return fail(BZQ_EINVAL, "s must lie in [0, 1)");
   }
-  const double c = (1.0 - s) * (2.0 - s) / (24.0 * (double)kPi);
-  return create_common(out, N, L, R, gamma, c, s, 0.0, 64, N_rho, M, precision, stream);
+  return create_plan(out, N, L, R, gamma, power_kernel_constant(s), s, 0.0, 64, N_rho, M, precision, stream);
 }
 
 bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, double gamma, double b_c,
                                    double b_s, double b_r, int n_jacobi, int N_rho, int M, int precision,
                                    void* stream) {
-  return create_common(out, N, L, R, gamma, b_c, b_s, b_r, n_jacobi, N_rho, M, precision, stream);
+  return create_plan(out, N, L, R, gamma, b_c, b_s, b_r, n_jacobi, N_rho, M, precision, stream);
 }
 
 bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream) {
   if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
-  return enqueue_collision(p, f_hat, Q_hat, (hipStream_t)stream);
+  return enqueue_collision(*p, p->ws, single(f_hat), single(Q_hat), 1, (hipStream_t)stream);
 }
 
 bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream) {
   if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
-  hipStream_t st = (hipStream_t)stream;
-  const size_t n3 = (size_t)p->N * p->N * p->N;
-  for (int i = 0; i < n_steps; ++i) {
-    bzq_status s;
-    if ((s = enqueue_collision(p, f_hat, p->q1, st)) != BZQ_OK) return s;
-    HIP_TRY(bzq::launch_axpy(p->fs, f_hat, dt, p->q1, n3, st));
-    if ((s = enqueue_collision(p, p->fs, p->q2, st)) != BZQ_OK) return s;
-    HIP_TRY(bzq::launch_heun(f_hat, p->q1, p->q2, 0.5 * dt, n3, st));
+  return enqueue_step(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
+}
+
+bzq_status bzq_workspace_create(bzq_workspace* out, bzq_plan p) {
+  if (!out || !p) return fail(BZQ_EINVAL, "NULL argument");
+  *out = nullptr;
+  auto* w = new bzq_workspace_s();
+  bzq_status s = workspace_init(*w, *p, 1);
+  if (s != BZQ_OK) {
+    delete w;
+    return s;
   }
+  *out = w;
+  return BZQ_OK;
+}
+
+bzq_status bzq_collision_ws(bzq_plan p, bzq_workspace w, const double* f_hat, double* Q_hat, void* stream) {
+  if (!p || !w || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
+  if (w->plan != p) return fail(BZQ_EINVAL, "workspace was made for another plan");
+  if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
+  return enqueue_collision(*p, *w, single(f_hat), single(Q_hat), 1, (hipStream_t)stream);
+}
+
+bzq_status bzq_step_ws(bzq_plan p, bzq_workspace w, double* f_hat, double dt, int n_steps, void* stream) {
+  if (!p || !w || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
+  if (w->plan != p) return fail(BZQ_EINVAL, "workspace was made for another plan");
+  if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
+  return enqueue_step(*p, *w, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
+}
+
+size_t bzq_workspace_bytes(bzq_workspace w) { return w ? w->arena.bytes : 0; }
+
+bzq_status bzq_workspace_destroy(bzq_workspace w) {
+  if (!w) return BZQ_OK;
+  (void)hipDeviceSynchronize();
+  delete w;
   return BZQ_OK;
 }
 
@@ -375,25 +427,25 @@ bzq_status bzq_moments(bzq_plan p, const double* f_hat, const double* Q_hat, dou
   bzq_status s;
   const double* q = Q_hat;
   if (!q) {
-    if ((s = enqueue_collision(p, f_hat, p->q1, st)) != BZQ_OK) return s;
-    q = p->q1;
+    if ((s = enqueue_collision(*p, p->ws, single(f_hat), single(p->ws.q1), 1, st)) != BZQ_OK) return s;
+    q = p->ws.q1;
   }
-  if ((s = enqueue_to_grid(p, f_hat, p->gf, st)) != BZQ_OK) return s;
-  if ((s = enqueue_to_grid(p, q, p->gq, st)) != BZQ_OK) return s;
-  HIP_TRY(bzq::launch_moments(p->gf, nullptr, -1.0, p->L, p->N, p->part, kMomentBlocks, st));
+  if ((s = enqueue_to_grid(*p, f_hat, p->gf, st)) != BZQ_OK) return s;
+  if ((s = enqueue_to_grid(*p, q, p->gq, st)) != BZQ_OK) return s;
+  BZQ_HIP_TRY(launch_moments(p->gf, nullptr, -1.0, p->L, p->N, p->part, kMomentBlocks, st));
   std::vector<double> part((size_t)kMomentBlocks * 8);
   double f0[2];
-  HIP_TRY(hipMemcpyAsync(part.data(), p->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(f0, f_hat, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  BZQ_HIP_TRY(hipMemcpyAsync(part.data(), p->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(f0, f_hat, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  BZQ_HIP_TRY(hipStreamSynchronize(st));
   double sums[5] = {0, 0, 0, 0, 0}, fmax = -1e300;
   for (int b = 0; b < kMomentBlocks; ++b) {
     for (int k = 0; k < 5; ++k) sums[k] += part[b * 8 + k];
     fmax = std::max(fmax, part[b * 8 + 5]);
   }
-  HIP_TRY(bzq::launch_moments(p->gf, p->gq, 1e-14 * std::max(fmax, 0.0), p->L, p->N, p->part, kMomentBlocks, st));
-  HIP_TRY(hipMemcpyAsync(part.data(), p->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  BZQ_HIP_TRY(launch_moments(p->gf, p->gq, 1e-14 * std::max(fmax, 0.0), p->L, p->N, p->part, kMomentBlocks, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(part.data(), p->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  BZQ_HIP_TRY(hipStreamSynchronize(st));
   double ent = 0;
   for (int b = 0; b < kMomentBlocks; ++b) ent += part[b * 8 + 6];
   const double h3 = std::pow(2.0 * p->L / p->N, 3);
@@ -410,26 +462,21 @@ bzq_status bzq_check_finite(bzq_plan p, const double* f_hat, void* stream) {
   if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
   int h = 0;
-  HIP_TRY(hipMemcpyAsync(p->flag, &h, sizeof(int), hipMemcpyHostToDevice, st));
-  HIP_TRY(bzq::launch_finite(f_hat, (size_t)p->N * p->N * p->N * 2, p->flag, st));
-  HIP_TRY(hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  BZQ_HIP_TRY(hipMemcpyAsync(p->flag, &h, sizeof(int), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(launch_finite(f_hat, (size_t)p->N * p->N * p->N * 2, p->flag, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(&h, p->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  BZQ_HIP_TRY(hipStreamSynchronize(st));
   return h ? fail(BZQ_ENONFINITE, "f_hat holds NaN or Inf") : BZQ_OK;
 }
 
-bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hats, double* const* Q_hats,
-                               int count, void* stream) {
-  if (count < 0 || (count > 0 && (!plans || !f_hats || !Q_hats))) return fail(BZQ_EINVAL, "bad batch arguments");
-  for (int i = 0; i < count; ++i)
-    if (!plans[i] || !f_hats[i] || !Q_hats[i]) return fail(BZQ_EINVAL, "NULL entry in batch");
-  for (int i = 0; i < count; ++i) {
-    bzq_status s = enqueue_collision(plans[i], f_hats[i], Q_hats[i], (hipStream_t)stream);
-    if (s != BZQ_OK) return s;
-  }
-  return BZQ_OK;
+size_t bzq_plan_device_bytes(bzq_plan p) {
+  return p ? p->tables.bytes + p->ws.arena.bytes + p->grid_scratch.bytes : 0;
 }
 
-size_t bzq_plan_device_bytes(bzq_plan p) { return p ? p->bytes : 0; }
+size_t bzq_plan_bytes_estimate(int N, int N_rho, int M, int precision) {
+  if (N < 8 || (N & 1) || N_rho < 1 || M < 6) return 0;
+  return plan_footprint(N, N_rho, M, precision);
+}
 
 size_t bzq_request_device_bytes(int N) {
   return N > 0 ? 2ull * N * N * N * 2 * sizeof(double) : 0;
@@ -463,10 +510,10 @@ bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
   std::vector<double> tmp(cnt);
   if (p->fp32) {
     std::vector<float> tf(cnt);
-    HIP_TRY(hipMemcpy(tf.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
+    BZQ_HIP_TRY(hipMemcpy(tf.data(), src, cnt * sizeof(float), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < cnt; ++i) tmp[i] = tf[i];
   } else {
-    HIP_TRY(hipMemcpy(tmp.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    BZQ_HIP_TRY(hipMemcpy(tmp.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost));
   }
   for (int i3 = 0; i3 < p->n1; ++i3)
     for (int c = 0; c < p->nh; ++c) out[(size_t)c * p->n1 + i3] = tmp[(size_t)i3 * p->nh + c];
@@ -485,9 +532,9 @@ bzq_status bzq_plan_stage_times(bzq_plan p, double* out) {
   if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
   for (int i = 0; i < 2 * ST_COUNT; ++i) out[i] = 0.0;
   for (size_t i = 0; i < p->ev_stage.size(); ++i) {
-    HIP_TRY(hipEventSynchronize(p->ev_pool[2 * i + 1]));
+    BZQ_HIP_TRY(hipEventSynchronize(p->ev_pool[2 * i + 1]));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]));
+    BZQ_HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]));
     out[p->ev_stage[i]] += ms;
     out[ST_COUNT + p->ev_stage[i]] += 1.0;
   }

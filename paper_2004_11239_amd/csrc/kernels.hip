@@ -76,9 +76,11 @@ struct ColAddr {
 
 // ------------------------------------------------------------------ ingest
 template <typename T>
-__global__ void k_ingest(const double2* __restrict__ f, cx<T>* __restrict__ fc, int N) {
+__global__ void k_ingest(PtrPack fin, cx<T>* __restrict__ fc, size_t fc_stride, int N) {
   const int n1 = N - 1, h = N / 2;
   const int total = n1 * n1 * n1;
+  const double2* __restrict__ f = (const double2*)fin.p[blockIdx.y];
+  fc += blockIdx.y * fc_stride;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     const int i3 = e / (n1 * n1);
     const int i2 = (e / n1) % n1;
@@ -92,8 +94,10 @@ __global__ void k_ingest(const double2* __restrict__ f, cx<T>* __restrict__ fc, 
 template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_zinv(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
                                              cx<T>* __restrict__ A, const cx<T>* __restrict__ twg, int N,
-                                             int pair0, int mode) {
+                                             int pair0, int mode, CellStrides cs) {
   constexpr int LD = P + 1;
+  fc += blockIdx.z * cs.fc;
+  A += blockIdx.z * cs.a;
   __shared__ cx<T> buf[K1_TP * LD];
   __shared__ cx<T> tw[P];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
@@ -142,8 +146,12 @@ __global__ __launch_bounds__(NT) void k_zinv(const cx<T>* __restrict__ fc, const
 template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_plane(const cx<T>* __restrict__ A, cx<T>* __restrict__ B,
                                               const T* __restrict__ fgrid, T* __restrict__ gridout,
-                                              const cx<T>* __restrict__ twg, int N, int mode) {
+                                              const cx<T>* __restrict__ twg, int N, int mode, CellStrides cs) {
   constexpr int LD = P + 1;
+  A += blockIdx.z * cs.a;
+  if (B) B += blockIdx.z * cs.b;
+  if (fgrid) fgrid += blockIdx.z * cs.fg;
+  if (gridout) gridout += blockIdx.z * cs.fg;
   __shared__ cx<T> plane[P * LD];
   __shared__ cx<T> tw[P];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1;
@@ -191,8 +199,10 @@ template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const T* __restrict__ V,
                                              const double2* __restrict__ ph, const double* __restrict__ cp,
                                              double2* __restrict__ Qpart, const cx<T>* __restrict__ twg,
-                                             int N, int pair0, int npt, int S) {
+                                             int N, int pair0, int npt, int S, CellStrides cs) {
   constexpr int LD = P + 1;
+  B += blockIdx.z * cs.b;
+  Qpart += blockIdx.z * cs.qp;
   constexpr int ROWS = 2 * K3_TQ;
   constexpr int NMAX = (2 * P) / 3;                       // N for the padded length P
   constexpr int OPT = (K3_TQ * (NMAX - 1) + NT - 1) / NT;
@@ -290,8 +300,10 @@ __device__ __forceinline__ constexpr int posKc(int i) {
 // along axis 3; one thread per pencil c (i1 fastest)
 template <typename T, int N, int P, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
-                                                 cx<T>* __restrict__ A, int pair0) {
+                                                 cx<T>* __restrict__ A, int pair0, CellStrides cs) {
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
+  fc += blockIdx.z * cs.fc;
+  A += blockIdx.z * cs.a;
   const int c = blockIdx.x * NT + threadIdx.x;
   if (c >= nn) return;
   const int pt = blockIdx.y;
@@ -346,8 +358,15 @@ template <typename T, int N, int P, int MODE>
 __global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>* __restrict__ A,
                                                                   cx<T>* __restrict__ B,
                                                                   const T* __restrict__ fgrid,
-                                                                  T* __restrict__ gridout) {
+                                                                  T* __restrict__ gridout, CellStrides cs) {
   constexpr int n1 = N - 1, nn = n1 * n1, LD = P + 1;
+  A += blockIdx.z * cs.a;
+  if constexpr (MODE == PLANE_TO_GRID) {
+    gridout += blockIdx.z * cs.fg;
+  } else {
+    B += blockIdx.z * cs.b;
+    fgrid += blockIdx.z * cs.fg;
+  }
   constexpr int Z = PlaneCfg<T, P>::Z;
   __shared__ cx<T> sm[Z * n1 * LD];
   const int z0 = blockIdx.x * Z, pt = blockIdx.y;
@@ -429,8 +448,10 @@ struct ZfwdCfg {
 template <typename T, int N, int P>
 __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
     const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
-    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int npt, int S) {
+    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int npt, int S, CellStrides cs) {
   using C = ZfwdCfg<T, P>;
+  B += blockIdx.z * cs.b;
+  Qpart += blockIdx.z * cs.qp;
   constexpr int TQ = C::TQ, PT = C::PT, NT = C::NT;
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
   constexpr int OPT = (TQ * n1 + NT - 1) / NT;
@@ -529,8 +550,10 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
 }
 
 // ---------------------------------------------------------------- finalize
-__global__ void k_finalize(const double2* __restrict__ Qpart, double2* __restrict__ Q, int N, int S) {
+__global__ void k_finalize(const double2* __restrict__ Qpart, PtrPack qout, int N, int S, size_t qp_stride) {
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, cmid = (nn - 1) / 2;
+  Qpart += blockIdx.y * qp_stride;
+  double2* __restrict__ Q = (double2*)qout.p[blockIdx.y];
   const int total = N * N * N;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     const int a = e / (N * N), b = (e / N) % N, d = e % N;
@@ -635,6 +658,20 @@ __global__ void k_heun(double* f, const double* q1, const double* q2, double hh,
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     f[i] = f[i] + hh * (q1[i] + q2[i]);
 }
+__global__ void k_axpy_cells(PtrPack out, PtrPack x, double a, PtrPack y, size_t n) {
+  double* o = out.p[blockIdx.y];
+  const double* xx = x.p[blockIdx.y];
+  const double* yy = y.p[blockIdx.y];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    o[i] = xx[i] + a * yy[i];
+}
+__global__ void k_heun_cells(PtrPack f, PtrPack q1, PtrPack q2, double hh, size_t n) {
+  double* ff = f.p[blockIdx.y];
+  const double* a = q1.p[blockIdx.y];
+  const double* b = q2.p[blockIdx.y];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    ff[i] = ff[i] + hh * (a[i] + b[i]);
+}
 __global__ void k_finite(const double* x, size_t n, int* flag) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     if (!isfinite(x[i])) flag[0] = 1;
@@ -684,81 +721,82 @@ inline int grid_for(size_t n, int nt) {
 // ----------------------------------------------------- dispatch on (P, T)
 // N for a launch of length P: the padded length (P = 3N/2) or the grid (P = N)
 template <typename T, int P, int N>
-hipError_t zinv_reg_t(const void* fc, const double* ph, void* A, int pair0, int npt, int mode, hipStream_t st) {
+hipError_t zinv_reg_t(const void* fc, const double* ph, void* A, int pair0, int npt, int mode,
+                      const CellStrides& cs, hipStream_t st) {
   constexpr int nn = (N - 1) * (N - 1);
   constexpr int NT = 64;
-  dim3 grid((nn + NT - 1) / NT, npt);
+  dim3 grid((nn + NT - 1) / NT, npt, cs.cells);
   if (mode == ZINV_PAIRS)
     hipLaunchKernelGGL((k_zinv_reg<T, N, P, NT, ZINV_PAIRS>), grid, dim3(NT), 0, st, (const cx<T>*)fc,
-                       (const double2*)ph, (cx<T>*)A, pair0);
+                       (const double2*)ph, (cx<T>*)A, pair0, cs);
   else if (mode == ZINV_GRID_SIGN)
     hipLaunchKernelGGL((k_zinv_reg<T, N, P, NT, ZINV_GRID_SIGN>), grid, dim3(NT), 0, st, (const cx<T>*)fc,
-                       (const double2*)ph, (cx<T>*)A, pair0);
+                       (const double2*)ph, (cx<T>*)A, pair0, cs);
   else
     hipLaunchKernelGGL((k_zinv_reg<T, N, P, NT, ZINV_PLAIN>), grid, dim3(NT), 0, st, (const cx<T>*)fc,
-                       (const double2*)ph, (cx<T>*)A, pair0);
+                       (const double2*)ph, (cx<T>*)A, pair0, cs);
   return hipGetLastError();
 }
 
 template <typename T, int P, int N>
 hipError_t plane_reg_t(const void* A, void* B, const void* fgrid, void* gridout, int npt, int mode,
-                       hipStream_t st) {
+                       const CellStrides& cs, hipStream_t st) {
   using C = PlaneCfg<T, P>;
-  dim3 grid(P / C::Z, npt);
+  dim3 grid(P / C::Z, npt, cs.cells);
   if (mode == PLANE_TO_GRID)
     hipLaunchKernelGGL((k_plane_reg<T, N, P, PLANE_TO_GRID>), grid, dim3(C::NT), 0, st, (const cx<T>*)A,
-                       (cx<T>*)B, (const T*)fgrid, (T*)gridout);
+                       (cx<T>*)B, (const T*)fgrid, (T*)gridout, cs);
   else
     hipLaunchKernelGGL((k_plane_reg<T, N, P, PLANE_PRODUCT>), grid, dim3(C::NT), 0, st, (const cx<T>*)A,
-                       (cx<T>*)B, (const T*)fgrid, (T*)gridout);
+                       (cx<T>*)B, (const T*)fgrid, (T*)gridout, cs);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int N, int pair0, int npt,
-                  int mode, hipStream_t st) {
+                  int mode, const CellStrides& cs, hipStream_t st) {
   if constexpr (RegFit<T, P>::value && isPad<P>())
-    if (N == padN<P>()) return zinv_reg_t<T, P, padN<P>()>(fc, ph, A, pair0, npt, mode, st);
+    if (N == padN<P>()) return zinv_reg_t<T, P, padN<P>()>(fc, ph, A, pair0, npt, mode, cs, st);
   if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
-    if (N == P) return zinv_reg_t<T, P, P>(fc, ph, A, pair0, npt, mode, st);
+    if (N == P) return zinv_reg_t<T, P, P>(fc, ph, A, pair0, npt, mode, cs, st);
   const int nn = (N - 1) * (N - 1);
-  dim3 grid((nn + K1_TP - 1) / K1_TP, npt);
+  dim3 grid((nn + K1_TP - 1) / K1_TP, npt, cs.cells);
   hipLaunchKernelGGL((k_zinv<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)fc,
-                     (const double2*)ph, (cx<T>*)A, (const cx<T>*)tw, N, pair0, mode);
+                     (const double2*)ph, (cx<T>*)A, (const cx<T>*)tw, N, pair0, mode, cs);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, const void* tw, int N,
-                   int npt, int mode, hipStream_t st) {
+                   int npt, int mode, const CellStrides& cs, hipStream_t st) {
   if constexpr (RegFit<T, P>::value && isPad<P>())
-    if (N == padN<P>()) return plane_reg_t<T, P, padN<P>()>(A, B, fgrid, gridout, npt, mode, st);
+    if (N == padN<P>()) return plane_reg_t<T, P, padN<P>()>(A, B, fgrid, gridout, npt, mode, cs, st);
   if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
-    if (N == P) return plane_reg_t<T, P, P>(A, B, fgrid, gridout, npt, mode, st);
+    if (N == P) return plane_reg_t<T, P, P>(A, B, fgrid, gridout, npt, mode, cs, st);
   constexpr int NT = PlaneThreads<P>::value;
-  dim3 grid(P, npt);
+  dim3 grid(P, npt, cs.cells);
   hipLaunchKernelGGL((k_plane<T, P, NT>), grid, dim3(NT), 0, st, (const cx<T>*)A, (cx<T>*)B,
-                     (const T*)fgrid, (T*)gridout, (const cx<T>*)tw, N, mode);
+                     (const T*)fgrid, (T*)gridout, (const cx<T>*)tw, N, mode, cs);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
-                  const void* tw, int N, int pair0, int npt, int S, hipStream_t st) {
+                  const void* tw, int N, int pair0, int npt, int S, const CellStrides& cs, hipStream_t st) {
   if constexpr (RegFit<T, P>::value && isPad<P>()) {
     using C = ZfwdCfg<T, P>;
     constexpr int NN = padN<P>();
     constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
-    dim3 grid((nh + C::TQ - 1) / C::TQ, S);
+    dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
     hipLaunchKernelGGL((k_zfwd_reg<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
-                       (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S);
+                       (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S, cs);
     return hipGetLastError();
   }
   const int nn = (N - 1) * (N - 1), nh = (nn + 1) / 2;
-  dim3 grid((nh + K3_TQ - 1) / K3_TQ, S);
+  dim3 grid((nh + K3_TQ - 1) / K3_TQ, S, cs.cells);
   hipLaunchKernelGGL((k_zfwd<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)B,
                      (const T*)V, (const double2*)ph, cp, (double2*)Qpart, (const cx<T>*)tw, N, pair0,
-                     npt, S);
+                     npt, S, cs);
   return hipGetLastError();
 }
 
@@ -767,54 +805,69 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
 
 }  // namespace
 
-hipError_t launch_ingest(const double* f, void* fc, int N, bool fp32, hipStream_t st) {
+hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells, int N, bool fp32,
+                         hipStream_t st) {
   const size_t n = (size_t)(N - 1) * (N - 1) * (N - 1);
+  dim3 grid(grid_for(n, 256), cells);
   if (fp32)
-    hipLaunchKernelGGL(k_ingest<float>, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double2*)f,
-                       (cx<float>*)fc, N);
+    hipLaunchKernelGGL(k_ingest<float>, grid, dim3(256), 0, st, f, (cx<float>*)fc, fc_stride, N);
   else
-    hipLaunchKernelGGL(k_ingest<double>, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double2*)f,
-                       (cx<double>*)fc, N);
+    hipLaunchKernelGGL(k_ingest<double>, grid, dim3(256), 0, st, f, (cx<double>*)fc, fc_stride, N);
   return hipGetLastError();
 }
 
 hipError_t launch_zinv(const void* fc, const double* ph, void* A, const void* tw, Geometry g, int pair0,
-                       int npt, int mode, bool fp32, hipStream_t st) {
+                       int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st) {
 #define CASE(PP)                                                                            \
   case PP:                                                                                  \
-    return fp32 ? zinv_t<float, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, st)             \
-                : zinv_t<double, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, st);
+    return fp32 ? zinv_t<float, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, cs, st)         \
+                : zinv_t<double, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, cs, st);
   switch (g.P) { BZQ_ALL_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
-                        Geometry g, int npt, int mode, bool fp32, hipStream_t st) {
+                        Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st) {
 #define CASE(PP)                                                                              \
   case PP:                                                                                    \
-    return fp32 ? plane_t<float, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, st)           \
-                : plane_t<double, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, st);
+    return fp32 ? plane_t<float, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, cs, st)       \
+                : plane_t<double, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, cs, st);
   switch (g.P) { BZQ_ALL_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
-                       const void* tw, Geometry g, int pair0, int npt, int S, bool fp32, hipStream_t st) {
+                       const void* tw, Geometry g, int pair0, int npt, int S, bool fp32,
+                       const CellStrides& cs, hipStream_t st) {
 #define CASE(PP)                                                                                 \
   case PP:                                                                                       \
-    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, st)            \
-                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, st);
+    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, cs, st)        \
+                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, cs, st);
   switch (g.P) { BZQ_PAD_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_finalize(const double* Qpart, double* Q, int N, int S, hipStream_t st) {
+hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,
+                           hipStream_t st) {
   const size_t n = (size_t)N * N * N;
-  hipLaunchKernelGGL(k_finalize, dim3(grid_for(n, 256)), dim3(256), 0, st, (const double2*)Qpart,
-                     (double2*)Q, N, S);
+  dim3 grid(grid_for(n, 256), cells);
+  hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, st, (const double2*)Qpart, Q, N, S, qp_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_cells(const PtrPack& out, const PtrPack& x, double a, const PtrPack& y, size_t n,
+                             int cells, hipStream_t st) {
+  dim3 grid(grid_for(2 * n, 256), cells);
+  hipLaunchKernelGGL(k_axpy_cells, grid, dim3(256), 0, st, out, x, a, y, 2 * n);
+  return hipGetLastError();
+}
+hipError_t launch_heun_cells(const PtrPack& f, const PtrPack& q1, const PtrPack& q2, double hh, size_t n,
+                             int cells, hipStream_t st) {
+  dim3 grid(grid_for(2 * n, 256), cells);
+  hipLaunchKernelGGL(k_heun_cells, grid, dim3(256), 0, st, f, q1, q2, hh, 2 * n);
   return hipGetLastError();
 }
 

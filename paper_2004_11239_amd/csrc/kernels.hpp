@@ -15,29 +15,53 @@ struct Geometry {
   int P;       // FFT length per axis (3N/2, or N for the physical grid)
 };
 
+// Independent cells of one launch (blockIdx.z, or blockIdx.y for the
+// element-wise kernels): element strides between consecutive cells' buffers.
+struct CellStrides {
+  size_t fc;   // compact spectrum
+  size_t fg;   // f on the padded grid (or the physical grid)
+  size_t a;    // first intermediate
+  size_t b;    // second intermediate
+  size_t qp;   // partial accumulators (complex128)
+  int cells;
+};
+
+// Per-cell device pointers passed by value (at most kMaxCells per launch).
+constexpr int kMaxCells = 64;
+struct PtrPack {
+  double* p[kMaxCells];
+};
+
 // Compact spectral copy: fc[i1][i2][i3] (centred, (N-1)^3) from the FFT-order
 // complex128 array f (N^3).  fp32 selects the element type of fc.
-hipError_t launch_ingest(const double* f, void* fc, int N, bool fp32, hipStream_t st);
+hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells, int N, bool fp32,
+                         hipStream_t st);
 
 // Step 1 of the pipeline: modulate (mode ZINV_PAIRS) and inverse-transform along
 // axis 3; writes A[pt][z][c] for pt < npt, z < P, c < (N-1)^2.
 hipError_t launch_zinv(const void* fc, const double* phase, void* A, const void* tw, Geometry g,
-                       int pair0, int npt, int mode, bool fp32, hipStream_t st);
+                       int pair0, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st);
 
 // Step 2: per (pt, z) plane: inverse along axes 2 and 1, product with the
 // physical f (mode PLANE_PRODUCT) or output of the real grid (PLANE_TO_GRID),
 // forward along axes 1 and 2.
 hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
-                        Geometry g, int npt, int mode, bool fp32, hipStream_t st);
+                        Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st);
 
 // Step 3: forward along axis 3, split the two packed pairs, apply the stored
 // weights and the phase e^{i a k.sigma}, accumulate in FP64 into Qpart[s].
 hipError_t launch_zfwd(const void* B, const void* V, const double* phase, const double* cp,
                        double* Qpart, const void* tw, Geometry g, int pair0, int npt, int S,
-                       bool fp32, hipStream_t st);
+                       bool fp32, const CellStrides& cs, hipStream_t st);
 
 // Sum of the S partial accumulators and Hermitian completion into Q (N^3 FFT order).
-hipError_t launch_finalize(const double* Qpart, double* Q, int N, int S, hipStream_t st);
+hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,
+                           hipStream_t st);
+// per cell: out = x + a y and f += h (q1 + q2)  (n complex128 each)
+hipError_t launch_axpy_cells(const PtrPack& out, const PtrPack& x, double a, const PtrPack& y, size_t n,
+                             int cells, hipStream_t st);
+hipError_t launch_heun_cells(const PtrPack& f, const PtrPack& q1, const PtrPack& q2, double hh, size_t n,
+                             int cells, hipStream_t st);
 
 // Real weight table V[pair][c][i3] (FP64 arithmetic, stored as float or double).
 hipError_t launch_table(void* V, const double* pairdat, const double* gj, int nj, int N,

@@ -1,0 +1,116 @@
+// Internal structures shared by the C ABI (capi.cpp), the batched executor
+// (batch.cpp) and the request server (server.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bzq.h"
+#include "kernels.hpp"
+
+namespace bzq {
+
+bzq_status fail(bzq_status s, const std::string& msg);
+
+#define BZQ_HIP_TRY(expr)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return ::bzq::fail(BZQ_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+// Device allocations owned by one object, released together.
+struct DeviceArena {
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  ~DeviceArena();
+  bzq_status alloc(void** out, size_t nbytes);
+  template <typename Tp>
+  bzq_status get(Tp** out, size_t nbytes) {
+    void* p = nullptr;
+    bzq_status s = alloc(&p, nbytes);
+    *out = (Tp*)p;
+    return s;
+  }
+};
+
+struct Plan;
+
+// Scratch of the evaluation pipeline for up to `cells` cells per launch.  A
+// plan's tables are read-only; every stream that evaluates concurrently needs
+// its own workspace.
+struct Workspace {
+  const Plan* plan = nullptr;
+  int cells = 0;
+  CellStrides cs{};
+  void* fc = nullptr;        // cells x (N-1)^3 complex, compute precision
+  void* fgrid = nullptr;     // cells x P^3 real
+  void* A = nullptr;         // cells x G x P x nn complex
+  void* B = nullptr;         // cells x G x P x 2 nhp complex
+  double* Qpart = nullptr;   // cells x S x nh x n1 complex128
+  double* q1 = nullptr;      // cells x N^3 complex128 (Heun stages)
+  double* q2 = nullptr;
+  double* fs = nullptr;
+  DeviceArena arena;
+};
+
+struct Plan {
+  int N = 0, P = 0, n1 = 0, nn = 0, nh = 0, nhp = 0;
+  double L = 0, R = 0, gamma = 0, bc = 0, bs = 0, br = 0;
+  int N_rho = 0, M = 0, nj = 0;
+  bool fp32 = false;
+  int npairs = 0;   // antipodal pairs incl. a zero pad to an even count
+  int npt = 0;      // pairs of pairs (packed into one complex transform)
+  int G = 0;        // pair-twos per chunk
+  int S = 0;        // accumulation splits of the last stage
+  size_t esz = 0;   // bytes per real element (4 or 8)
+  std::vector<double> pair_host;  // [npairs][6] for introspection
+  // tables (read-only after creation)
+  void* V = nullptr;            // [npairs][n1][nh] real weights
+  double* ph = nullptr;         // [npairs][3][2N-3] complex128 phases
+  double* cp = nullptr;         // [npairs] w_rho rho^{2+gamma}
+  void* tw_pad = nullptr;       // P twiddles (LDS kernels), compute precision
+  double* tw_grid = nullptr;    // N twiddles, FP64
+  DeviceArena tables;
+  // the plan's own workspace (one cell) and FP64 physical-grid scratch
+  Workspace ws;
+  double* gfc = nullptr;
+  double* gA = nullptr;
+  double* gf = nullptr;
+  double* gq = nullptr;
+  double* part = nullptr;
+  int* flag = nullptr;
+  DeviceArena grid_scratch;
+  // optional per-launch timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_stage;
+  size_t ev_used = 0;
+  ~Plan();
+  size_t workspace_bytes_per_cell() const;
+};
+
+bzq_status workspace_init(Workspace& w, const Plan& p, int cells);
+void set_chunking(Plan& p);
+size_t plan_footprint(int N, int N_rho, int M, int precision);
+bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
+                       double br, int nj, int N_rho, int M, int precision, void* stream);
+double power_kernel_constant(double s);
+
+// Enqueue Q = Q(f) for `cells` cells sharing plan p, using workspace w.
+bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrPack& Q, int cells,
+                             hipStream_t st);
+// Enqueue n_steps Heun steps in place for `cells` cells.
+bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
+                        hipStream_t st);
+
+inline PtrPack single(const double* p) {
+  PtrPack pk{};
+  pk.p[0] = const_cast<double*>(p);
+  return pk;
+}
+
+}  // namespace bzq
+
+struct bzq_plan_s : bzq::Plan {};

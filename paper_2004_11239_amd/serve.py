@@ -1,0 +1,108 @@
+"""Poisson-arrival driver for the request server (continuous batching).
+
+Each request advances one homogeneous cell by `n_steps` Heun steps of the
+collision operator; sizes, kernels and initial data are drawn per request.
+Requests are submitted at their arrival times from a feeder thread while the
+main thread collects completions; latency is completion minus arrival on the
+server's clock.
+
+    python -m paper_2004_11239_amd.serve --rates 2,10,100 --duration 10
+
+Prints one JSON line per rate.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import threading
+import time
+
+import numpy as np
+
+from . import bzq
+
+
+def _percentile(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else float("nan")
+
+
+def run(rate_hz: float, duration_s: float, seed: int = 0, budget_gb: float = 64.0, slots: int = 4,
+        precision: str = "fp32", n_steps: int = 10, dt: float = 0.01, L: float = 8.0, R: float = 4.0,
+        M: int = 110, sizes=(16, 32, 48, 64), gammas=(-1.0, 0.0), ss=(0.25, 0.75), drain_s: float = 600.0,
+        server=None):
+    import workloads
+
+    stream = workloads.request_stream(rate_hz, duration_s, seed, sizes=sizes, gammas=gammas, ss=ss)
+    # inputs are prepared before the clock starts
+    inputs = [workloads.to_spectral(workloads.random_mixture(ms).sample(N, L)) for (_, N, _, _, ms) in stream]
+    own = server is None
+    if own:
+        server = bzq.Server(int(budget_gb * (1 << 30)), slots)
+    # resident plans for every parameter set of the stream (not timed)
+    warm = {}
+    for (_, N, g, s, _) in stream:
+        if (N, g, s) not in warm:
+            warm[(N, g, s)] = server.submit(np.zeros((N, N, N), np.complex128), N, L, R, g, s, N, M,
+                                            precision, dt, 0)
+    for (N, g, s), rid in warm.items():
+        server.wait(rid)
+        server.poll(rid, N)
+    ids = [None] * len(stream)
+    t0 = time.perf_counter()
+
+    def feeder():
+        for i, (t, N, g, s, _) in enumerate(stream):
+            delay = t - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids[i] = server.submit(inputs[i], N, L, R, g, s, N, M, precision, dt, n_steps)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    lat, done_t, first_arrival = [], [], None
+    remaining = set(range(len(stream)))
+    deadline = time.perf_counter() + duration_s + drain_s
+    while remaining and time.perf_counter() < deadline:
+        progressed = False
+        for i in list(remaining):
+            if ids[i] is None:
+                continue
+            r = server.poll(ids[i], stream[i][1])
+            if r is None:
+                continue
+            _, (ta, ts, td) = r
+            lat.append(td - ta)
+            done_t.append(td)
+            first_arrival = ta if first_arrival is None else min(first_arrival, ta)
+            remaining.discard(i)
+            progressed = True
+        if not progressed:
+            time.sleep(0.0005)
+    th.join()
+    stats = server.stats()
+    if own:
+        server.destroy()
+    span = (max(done_t) - first_arrival) if done_t else float("nan")
+    return {"rate_req_s": rate_hz, "requests": len(stream), "completed": len(lat),
+            "p50_s": _percentile(lat, 50), "p99_s": _percentile(lat, 99),
+            "throughput_req_s": len(lat) / span if done_t else 0.0,
+            "peak_device_gb": stats["peak_device_bytes"] / 1e9, "evictions": stats["evictions"],
+            "slots": slots, "precision": precision, "n_steps": n_steps}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--rates", default="2,10,100")
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    for r in args.rates.split(","):
+        print(json.dumps(run(float(r), args.duration, args.seed, args.budget_gb, args.slots, args.precision)),
+              flush=True)
+
+
+if __name__ == "__main__":
+    main()

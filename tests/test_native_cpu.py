@@ -1,0 +1,103 @@
+"""CPU-side checks of the native library (no GPU needed).
+
+* every function declared in include/bzq.h is exported by libbzq.so;
+* argument errors are reported before any device work (status codes, NULL
+  plan, message text);
+* the device FFT building blocks and the plan's quadrature rules, compiled
+  for the host, against direct long-double evaluation and closed forms.
+"""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2004_11239_amd", "libbzq.so")
+CSRC = os.path.join(ROOT, "paper_2004_11239_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        if not os.path.exists(HIPCC):
+            pytest.skip("library not built and hipcc not available")
+        from paper_2004_11239_amd.build import build
+        build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "bzq.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bzq_\w+)\s*\(", text)))
+
+
+def test_header_symbols_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_argument_validation_without_device(lib):
+    f = lib.bzq_plan_create
+    f.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    lib.bzq_last_error.restype = ctypes.c_char_p
+    lib.bzq_status_string.restype = ctypes.c_char_p
+    h = ctypes.c_void_p(1234)
+    cases = [
+        ((15, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 1),     # odd N
+        ((4, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 1),      # N < 8
+        ((16, -1.0, 4.0, 0.0, 0.5, 16, 38, 0), 1),    # L <= 0
+        ((16, 8.0, 0.0, 0.0, 0.5, 16, 38, 0), 1),     # R <= 0
+        ((16, 8.0, 4.0, -3.5, 0.5, 16, 38, 0), 1),    # gamma out of range
+        ((16, 8.0, 4.0, 0.0, 1.0, 16, 38, 0), 1),     # s = 1 (nu = 2)
+        ((16, 8.0, 4.0, 0.0, -0.1, 16, 38, 0), 1),    # s < 0
+        ((16, 8.0, 4.0, 0.0, 0.5, 0, 38, 0), 1),      # N_rho < 1
+        ((16, 8.0, 4.0, 0.0, 0.5, 16, 37, 0), 1),     # no Lebedev rule of size 37
+        ((16, 8.0, 4.0, 0.0, 0.5, 16, 38, 7), 1),     # unknown precision
+        ((12, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),     # valid but no FFT schedule
+        ((128, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),
+    ]
+    for args, code in cases:
+        h.value = 1234
+        assert f(ctypes.byref(h), *args, None) == code, args
+        assert h.value is None
+        assert len(lib.bzq_last_error()) > 0
+    assert lib.bzq_status_string(1) == b"invalid argument"
+    lib.bzq_request_device_bytes.restype = ctypes.c_size_t
+    assert lib.bzq_request_device_bytes(32) == 2 * 32 ** 3 * 16
+    lib.bzq_collision.argtypes = [ctypes.c_void_p] * 4
+    assert lib.bzq_collision(None, None, None, None) == 1
+    lib.bzq_plan_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.bzq_plan_destroy(None) == 0
+
+
+def _compile_and_run(src, extra, tmp_path):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "check")
+    cmd = [HIPCC, "-O1", "-std=c++17", "-x", "hip", "--offload-host-only", f"-I{CSRC}",
+           os.path.join(ROOT, "tests", "native", src)] + extra + ["-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    print(r.stdout[-3000:])
+    return r
+
+
+def test_fft_building_blocks_on_host(tmp_path):
+    r = _compile_and_run("fft_host_check.cpp", [], tmp_path)
+    assert r.returncode == 0, r.stdout
+
+
+def test_plan_quadrature_on_host(tmp_path):
+    r = _compile_and_run("quad_host_check.cpp", [os.path.join(CSRC, "quadrature.cpp")], tmp_path)
+    assert r.returncode == 0, r.stdout
