@@ -128,6 +128,44 @@ def traffic_from_profiles(kernel_tag: str):
         return None
 
 
+# ------------------------------------------------------- batched and served
+def batch_bench(bzq, torch, n_cells, steps, seed=0):
+    """Independent cells, N drawn from {16, 24, 32} (50/30/20 %), N_rho = N,
+    M = 110, gamma = 0, s = 0.5, FP32 bulk; one graph-captured Heun step of the
+    whole batch per step."""
+    import workloads
+    t0 = time.perf_counter()
+    cells = workloads.cell_batch(n_cells, seed)
+    plans = {N: bzq.Plan(N, 8.0, 4.0, 0.0, 0.5, N, 110, precision="fp32") for N in (16, 24, 32)}
+    fs = [torch.from_numpy(f).to("cuda") for _, f in cells]
+    batch = bzq.Batch([plans[N] for N, _ in cells], fs, cells_per_launch=0)
+    setup = time.perf_counter() - t0
+    batch.step(0.01, 1, use_graph=True)          # capture + warm-up
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    batch.step(0.01, steps, use_graph=True)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    out = {"workload": f"{n_cells} cells, N in {{16,24,32}} (50/30/20%), N_rho=N, M=110, gamma=0, s=0.5, "
+                       f"FP32 bulk / FP64 accumulate, graph-captured Heun step",
+           "cells_steps_per_s": round(n_cells * steps / (ms * 1e-3), 2),
+           "q_evals_per_s": round(2 * n_cells * steps / (ms * 1e-3), 2),
+           "ms_per_step": round(ms / steps, 2), "steps": steps,
+           "groups": batch.groups(), "setup_s": round(setup, 1),
+           "workspace_gb": round(batch.device_bytes() / 1e9, 2)}
+    batch.destroy()
+    return out
+
+
+def serve_bench(rates, duration):
+    from paper_2004_11239_amd import serve
+    return [serve.run(r, duration, seed=0, budget_gb=64, slots=4, precision="fp32", n_steps=10)
+            for r in rates]
+
+
 # ---------------------------------------------------------------- CPU oracle
 def cpu_baseline(cfg, fhat_np, n_modes=256, seed=0):
     import numpy as np
@@ -160,6 +198,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--large", action="store_true", help="also time the N=64 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
+    ap.add_argument("--serve-rates", default="2", help="request rates (req/s) of the served form ('': skip)")
+    ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run 3 device-to-device copies of MIB MiB (reference kernel for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -259,6 +300,11 @@ def main():
             torch.cuda.empty_cache()
         large["err_fp32_vs_fp64"] = float(np.linalg.norm(qs["fp32"] - qs["fp64"]) / np.linalg.norm(qs["fp64"]))
         out["large_N64"] = large
+    if args.batch_cells > 0:
+        out["batched"] = batch_bench(bzq, torch, args.batch_cells, 2)
+        torch.cuda.empty_cache()
+    if args.serve_rates:
+        out["served"] = serve_bench([float(r) for r in args.serve_rates.split(",")], args.serve_duration)
     if not args.no_cpu_baseline:
         ks, qo, t, cb = cpu_baseline(cfg, fhat)
         idx = tuple(np.mod(ks, cfg["N"]).T)

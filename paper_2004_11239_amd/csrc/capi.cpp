@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -102,12 +103,15 @@ void set_chunking(Plan& p) {
   p.esz = p.fp32 ? 4 : 8;
   p.nhp = (p.nh + 15) / 16 * 16;
   const size_t per_pt = (size_t)p.P * (p.nn + 2 * p.nhp) * 2 * p.esz;
-  p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, (1024ull << 20) / per_pt));
+  const char* env = std::getenv("BZQ_CHUNK_MB");
+  const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
+  p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
   const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
-  const int tq = reg_zfwd ? 16 : 8;
-  const int groups = reg_zfwd ? (p.G + 3) / 4 : p.G;
+  const int tq = reg_zfwd ? (p.fp32 ? 32 : 16) : 8;
+  const int pt_group = reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
+  const int groups = (p.G + pt_group - 1) / pt_group;
   const int tiles = (p.nh + tq - 1) / tq;
-  p.S = std::max(1, std::min(groups, (2048 + tiles - 1) / tiles));
+  p.S = std::max(1, std::min(groups, (1024 + tiles - 1) / tiles));
 }
 
 // Device bytes a plan will hold (tables, its workspace, grid scratch), from

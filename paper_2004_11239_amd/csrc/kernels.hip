@@ -438,10 +438,11 @@ __global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>*
 // and walks over groups of PT pair-twos; the kept modes of each transform go
 // through LDS to the epilogue threads, which own fixed output modes and keep
 // their FP64 sums in registers for the whole launch.
+// TQ pencils of T make one 128-byte line of the weight table per mode
 template <typename T, int P>
 struct ZfwdCfg {
-  static constexpr int TQ = 16;
-  static constexpr int PT = 4;
+  static constexpr int TQ = 128 / (int)sizeof(T);
+  static constexpr int PT = sizeof(T) == 4 ? 2 : 4;
   static constexpr int NT = 2 * TQ * PT;
 };
 
@@ -549,31 +550,59 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
   }
 }
 
+
 // ---------------------------------------------------------------- finalize
-__global__ void k_finalize(const double2* __restrict__ Qpart, PtrPack qout, int N, int S, size_t qp_stride) {
+// Four lanes per half-spectrum mode (c, i3) sum interleaved quarters of the S
+// partial accumulators; lane 0 adds the four quarter sums in fixed order and
+// writes Q(k) and, conjugated, Q(-k).  The centre pencil (k1 = k2 = 0) is
+// written from k3 >= 0 only, so Q(-k) is exactly conj Q(k) everywhere.  The
+// remaining threads zero the Nyquist planes.
+__global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qpart, PtrPack qout, int N, int S,
+                                                  size_t qp_stride) {
+  __shared__ double2 red[256];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, cmid = (nn - 1) / 2;
   Qpart += blockIdx.y * qp_stride;
   double2* __restrict__ Q = (double2*)qout.p[blockIdx.y];
-  const int total = N * N * N;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-    const int a = e / (N * N), b = (e / N) % N, d = e % N;
-    if (a == h || b == h || d == h) { Q[e] = double2{0.0, 0.0}; continue; }
-    const int k1 = a < h ? a : a - N, k2 = b < h ? b : b - N, k3 = d < h ? d : d - N;
-    int c = (k2 + h - 1) * n1 + (k1 + h - 1);
-    int i3 = k3 + h - 1;
-    bool conj = false;
-    if (c > cmid || (c == cmid && k3 < 0)) {
-      c = nn - 1 - c;
-      i3 = n1 - 1 - i3;
-      conj = true;
-    }
+  const int nmain = nh * n1;
+  const int nnyq = 3 * N * N - 3 * N + 1;
+  const int lane = threadIdx.x & 3;
+  const int slotw = threadIdx.x >> 2;                  // 64 modes per block
+  const int nblk_main = (nmain + 63) / 64;
+  if ((int)blockIdx.x < nblk_main) {
+    const int e = blockIdx.x * 64 + slotw;
     double x = 0.0, y = 0.0;
-    for (int s = 0; s < S; ++s) {
-      const double2 v = Qpart[((size_t)s * n1 + i3) * nh + c];
-      x += v.x;
-      y += v.y;
+    if (e < nmain) {
+      const int i3 = e / nh, c = e - i3 * nh;
+      for (int s = lane; s < S; s += 4) {
+        const double2 v = Qpart[((size_t)s * n1 + i3) * nh + c];
+        x += v.x;
+        y += v.y;
+      }
     }
-    Q[e] = double2{x, conj ? -y : y};
+    red[threadIdx.x] = double2{x, y};
+    __syncthreads();
+    if (lane == 0 && e < nmain) {
+      const int i3 = e / nh, c = e - i3 * nh;
+      const int i2 = c / n1, i1 = c - i2 * n1;
+      const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
+      if (c == cmid && k3 < 0) return;
+      const double2 a0 = red[threadIdx.x], a1 = red[threadIdx.x + 1], a2 = red[threadIdx.x + 2],
+                    a3 = red[threadIdx.x + 3];
+      const double sx = ((a0.x + a1.x) + a2.x) + a3.x, sy = ((a0.y + a1.y) + a2.y) + a3.y;
+      const int a = (k1 + N) % N, b = (k2 + N) % N, d = (k3 + N) % N;
+      const int am = (N - k1) % N, bm = (N - k2) % N, dm = (N - k3) % N;
+      Q[((size_t)a * N + b) * N + d] = double2{sx, sy};
+      if (k1 != 0 || k2 != 0 || k3 != 0) Q[((size_t)am * N + bm) * N + dm] = double2{sx, -sy};
+    }
+    return;
+  }
+  // Nyquist entries: plane a = h, then b = h (a != h), then d = h (a, b != h)
+  for (int r0 = (blockIdx.x - nblk_main) * 256 + threadIdx.x; r0 < nnyq; r0 += (gridDim.x - nblk_main) * 256) {
+    int r = r0, a, b, d;
+    if (r < N * N) { a = h; b = r / N; d = r % N; }
+    else if ((r -= N * N) < N * (N - 1)) { a = r / N; a += a >= h; b = h; d = r % N; }
+    else { r -= N * (N - 1); a = r / (N - 1); a += a >= h; b = r % (N - 1); b += b >= h; d = h; }
+    Q[((size_t)a * N + b) * N + d] = double2{0.0, 0.0};
   }
 }
 
@@ -852,8 +881,9 @@ hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const dou
 
 hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,
                            hipStream_t st) {
-  const size_t n = (size_t)N * N * N;
-  dim3 grid(grid_for(n, 256), cells);
+  const size_t nh = ((size_t)(N - 1) * (N - 1) + 1) / 2;
+  const size_t nmain = nh * (N - 1), nnyq = 3 * (size_t)N * N - 3 * N + 1;
+  dim3 grid((unsigned)((nmain + 63) / 64 + (nnyq + 255) / 256), cells);
   hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, st, (const double2*)Qpart, Q, N, S, qp_stride);
   return hipGetLastError();
 }
