@@ -120,7 +120,8 @@ def traffic_from_profiles(kernel_tag: str):
                 for kv in line.split()[1:]:
                     k, v = kv.split("=")
                     vals[k] = v
-    if vals.get("kernel_hash") != kernel_hash() or vals.get("kernel") != kernel_tag:
+    # kernel names are written with '_' for blanks so that the line splits on whitespace
+    if vals.get("kernel_hash") != kernel_hash() or vals.get("kernel") != kernel_tag.replace(" ", "_"):
         return None
     try:
         return float(vals["bytes_per_launch"])
@@ -167,7 +168,7 @@ def serve_bench(rates, duration):
 
 
 # ---------------------------------------------------------------- CPU oracle
-def cpu_baseline(cfg, fhat_np, n_modes=256, seed=0):
+def cpu_baseline(cfg, fhat_np, n_modes=1536, seed=0):
     import numpy as np
     import oracle
     try:
@@ -181,7 +182,7 @@ def cpu_baseline(cfg, fhat_np, n_modes=256, seed=0):
     rng = np.random.default_rng(seed)
     ks = modes[rng.choice(len(modes), size=n_modes, replace=False)]
     t0 = time.perf_counter()
-    q = oracle.collision_direct(fhat_np, d, k_out=ks, k_block=n_modes)
+    q = oracle.collision_direct(fhat_np, d, k_out=ks, k_block=256)
     t = time.perf_counter() - t0
     value = n_modes / (t * len(modes))
     return ks, q, t, {"value": value, "unit": "Q evals/s", "cores": int(max(blas_threads, 8)),
@@ -199,7 +200,7 @@ def main():
     ap.add_argument("--large", action="store_true", help="also time the N=64 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
-    ap.add_argument("--serve-rates", default="2", help="request rates (req/s) of the served form ('': skip)")
+    ap.add_argument("--serve-rates", default="2,20", help="request rates (req/s) of the served form ('': skip)")
     ap.add_argument("--serve-duration", type=float, default=5.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run 3 device-to-device copies of MIB MiB (reference kernel for "
@@ -246,7 +247,7 @@ def main():
     avg_plane_s = plane_ms * 1e-3 / plane_n
     pts_per_launch = (npairs // 2) / (plane_n / evals32)
     achieved = fm["plane_per_pt"] * pts_per_launch / avg_plane_s / 1e12
-    kern_tag = "k_plane<float,48>"
+    kern_tag = f"k_plane_reg<float, {cfg['N']}, {3 * cfg['N'] // 2}, 0>"
     traffic = traffic_from_profiles(kern_tag)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK["fp32"], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK["fp32"], 4), "traffic": traffic,
