@@ -9,7 +9,7 @@ Q evaluations per second of the FP32-bulk / FP64-accumulate path; the plain
 FP64 path is timed beside it, and both are checked against each other and
 against the CPU oracle on a mode sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--large] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-large] [--no-cpu-baseline]
 
 Prints one JSON line.  Inputs are resident in HBM before the timed region.
 """
@@ -167,6 +167,22 @@ def serve_bench(rates, duration):
             for r in rates]
 
 
+def whole_path(N, npairs, esz, per_eval_ms):
+    """Whole-evaluation roofline: the method's own HBM bytes (weight table, f in,
+    Q out) and its flops (flop_model) against the MI355X peaks; the binding
+    roof is the larger of the two times."""
+    fm = flop_model(N, npairs)
+    tb = table_bytes(N, npairs, esz) + 2 * N ** 3 * 16
+    t = per_eval_ms * 1e-3
+    peak = PEAK["fp32"] if esz == 4 else PEAK["fp64"]
+    t_roof = max(tb / HBM_PEAK, fm["total"] / (peak * 1e12))
+    return {"alg_gflop_per_eval": round(fm["total"] / 1e9, 3),
+            "tflops_whole_path": round(fm["total"] / t / 1e12, 3),
+            "alg_bytes_per_eval": tb, "hbm_gbps_alg": round(tb / t / 1e9, 1),
+            "t_roof_ms": round(t_roof * 1e3, 4), "frac_of_roof": round(t_roof / t, 4),
+            "binding_roof": "valu" if fm["total"] / (peak * 1e12) > tb / HBM_PEAK else "hbm"}
+
+
 # ---------------------------------------------------------------- CPU oracle
 def cpu_baseline(cfg, fhat_np, n_modes=1536, seed=0):
     import numpy as np
@@ -197,7 +213,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--large", action="store_true", help="also time the N=64 workload")
+    ap.add_argument("--no-large", dest="large", action="store_false",
+                    help="skip the N=64 workload (timed by default beside the headline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
     ap.add_argument("--serve-rates", default="2,20", help="request rates (req/s) of the served form ('': skip)")
@@ -254,11 +271,7 @@ def main():
             "kernel": kern_tag, "avg_launch_ms": round(avg_plane_s * 1e3, 5),
             "alg_flop_per_launch": fm["plane_per_pt"] * pts_per_launch}
     per_eval_ms = ms32 / evals32
-    whole = {"alg_gflop_per_eval": round(fm["total"] / 1e9, 3),
-             "tflops_whole_path": round(fm["total"] / (per_eval_ms * 1e-3) / 1e12, 3),
-             "frac_of_fp32_peak": round(fm["total"] / (per_eval_ms * 1e-3) / 1e12 / PEAK["fp32"], 4),
-             "table_bytes_per_eval": table_bytes(cfg["N"], npairs, 4),
-             "table_gbps": round(table_bytes(cfg["N"], npairs, 4) / (per_eval_ms * 1e-3) / 1e9, 1)}
+    whole = whole_path(cfg["N"], npairs, 4, ms32 / evals32)
     stage_ms = {k: round(v[0] / evals32, 4) for k, v in st32.items()}
 
     out = {
@@ -295,7 +308,9 @@ def main():
         for prec in ("fp32", "fp64"):
             p, ms, wall, st, q = time_steps(bzq, torch, cl, prec, fl, 2, 1)
             large[prec] = {"evals_per_s": round(4 / (ms * 1e-3), 3), "ms_per_eval": round(ms / 4, 3),
-                           "stage_ms_per_eval": {k: round(v[0] / 4, 3) for k, v in st.items()}}
+                           "stage_ms_per_eval": {k: round(v[0] / 4, 3) for k, v in st.items()},
+                           "whole_path": whole_path(cl["N"], p.info()["npairs"], 4 if prec == "fp32" else 8,
+                                                    ms / 4)}
             qs[prec] = q.cpu().numpy()
             del p
             torch.cuda.empty_cache()
