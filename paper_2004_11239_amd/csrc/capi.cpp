@@ -106,9 +106,13 @@ void set_chunking(Plan& p) {
   const char* env = std::getenv("BZQ_CHUNK_MB");
   const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
   p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
+  // z-forward kernels: FP32 P >= 48 pipelined (32 pencils, one pair-two per
+  // step), other register kernels (32 or 16 pencils, 2 or 4 pair-twos per
+  // step), LDS kernels for FP64 P > 48 (8 pencils, one pair-two)
+  const bool pipe = p.fp32 && p.P >= 48;
   const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
   const int tq = reg_zfwd ? (p.fp32 ? 32 : 16) : 8;
-  const int pt_group = reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
+  const int pt_group = pipe ? 1 : reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
   const int groups = (p.G + pt_group - 1) / pt_group;
   const int tiles = (p.nh + tq - 1) / tq;
   p.S = std::max(1, std::min(groups, (1024 + tiles - 1) / tiles));

@@ -320,4 +320,24 @@ __host__ __device__ __forceinline__ void fft_reg(cx<T>* x) {
   }
 }
 
+// Half of a length-P transform, P = 2Q, by one decimation-in-frequency step:
+// with u[n] = (x[n] + (-1)^PAR x[n+Q]) w_P^{PAR n}, n < Q, the outputs of
+// parity PAR are X[2j + PAR] = DFT_Q(u)[j].  `get(n)` returns input n (n is a
+// compile-time constant after unrolling, so structurally zero inputs fold
+// away).  On return u[j] = X[2j + PAR].
+template <int P, int SIGN, int PAR, typename T, typename Get>
+__host__ __device__ __forceinline__ void dft_half_dif(Get get, cx<T>* u) {
+  constexpr int Q = P / 2;
+#pragma unroll
+  for (int n = 0; n < Q; ++n) {
+    const cx<T> a = get(n), b = get(n + Q);
+    if constexpr (PAR == 0) {
+      u[n] = cadd(a, b);
+    } else {
+      u[n] = twiddle_mul<P, SIGN>(csub(a, b), n);
+    }
+  }
+  fft_reg<Q, SIGN>(u);
+}
+
 }  // namespace bzq

@@ -56,6 +56,14 @@ __device__ __forceinline__ int posK(int i, int h, int P) {
   return k >= 0 ? k : k + P;
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads issued before
+// it stay in flight (used where weights for the next step are prefetched).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> to_cx(double2 v) {
   return {(T)v.x, (T)v.y};
@@ -432,6 +440,339 @@ __global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>*
 }
 
 
+// ----------------------------------- two waves per pencil (FP32, P = 72, 96)
+// A whole FP32 pencil of 72 or 96 complex values takes most of the register
+// file, which leaves one wave per SIMD and exposes every memory wait.  These
+// kernels split each transform between two waves of one workgroup by a
+// single decimation step in frequency: the wave of parity PAR computes the
+// outputs 2j + PAR with a length-P/2 transform (dft_half_dif).  The parity is
+// uniform over a wave, so every wave runs straight-line code with
+// compile-time twiddles.
+template <int P>
+struct HalfCfg {
+  static constexpr int Q = P / 2;
+  static constexpr int WPP = (P + 63) / 64;   // waves per parity (one lane per column)
+  static constexpr int NT = 2 * 64 * WPP;
+};
+
+// centred index of position m of a length-P axis holding the N-1 modes
+// (m < N/2 or m > P - N/2), or -1 for a zero-padding position
+template <int N, int P>
+__device__ __forceinline__ constexpr int keptK(int m) {
+  return m < N / 2 ? m + N / 2 - 1 : (m > P - N / 2 ? m - P + N / 2 - 1 : -1);
+}
+
+// rows (axis 2) inverse: outputs y = 2j + PAR of row i1 into LDS
+template <typename T, int N, int P, int PAR>
+__device__ __forceinline__ void half_rows_inv(const cx<T>* __restrict__ Ain, cx<T>* row) {
+  constexpr int n1 = N - 1, Q = P / 2;
+  cx<T> u[Q];
+  dft_half_dif<P, +1, PAR>(
+      [&](int n) -> cx<T> {
+        const int i2 = keptK<N, P>(n);
+        return i2 >= 0 ? Ain[(size_t)i2 * n1] : cx<T>{0, 0};
+      },
+      u);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) row[2 * j + PAR] = u[j];
+}
+
+// column y (axis 1): inverse to the outputs x = 2j + PAR, product with f at
+// those x, then the length-P/2 forward transform of this parity's samples:
+// E[k] (PAR 0) or w_P^{-k} O[k] (PAR 1) of X[k] = E[k] + w^{-k} O[k]
+template <typename T, int N, int P, int PAR>
+__device__ __forceinline__ void half_cols(const cx<T>* col, const T* __restrict__ fz, cx<T>* u) {
+  constexpr int Q = P / 2, LD = P + 1;
+  dft_half_dif<P, +1, PAR>(
+      [&](int n) -> cx<T> {
+        const int i1 = keptK<N, P>(n);
+        return i1 >= 0 ? col[i1 * LD] : cx<T>{0, 0};
+      },
+      u);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) u[j] = cscale(u[j], fz[(size_t)(2 * j + PAR) * P]);
+  fft_reg<Q, -1>(u);
+  if constexpr (PAR == 1) {
+#pragma unroll
+    for (int k = 1; k < Q; ++k) u[k] = twiddle_mul<P, -1>(u[k], k);
+  }
+}
+
+// after the exchange: u[i] = X[PAR Q/2 + i], u[Q/2 + i] = X[Q + PAR Q/2 + i];
+// the kept ones go to row k1 of the plane
+template <typename T, int N, int P, int PAR>
+__device__ __forceinline__ void half_cols_store(const cx<T>* u, cx<T>* col) {
+  constexpr int Q = P / 2, QH = Q / 2, LD = P + 1;
+#pragma unroll
+  for (int i = 0; i < QH; ++i) {
+    const int k1a = keptK<N, P>(PAR * QH + i);
+    if (k1a >= 0) col[k1a * LD] = u[i];
+    const int k1b = keptK<N, P>(Q + PAR * QH + i);
+    if (k1b >= 0) col[k1b * LD] = u[QH + i];
+  }
+}
+
+// rows (axis 2) forward: kept outputs of parity PAR of row k1 into B
+template <typename T, int N, int P, int PAR>
+__device__ __forceinline__ void half_rows_fwd(const cx<T>* row, cx<T>* __restrict__ Bout, int k1) {
+  constexpr int n1 = N - 1, nn = n1 * n1, Q = P / 2;
+  constexpr int nhp = ((nn + 1) / 2 + 15) / 16 * 16, cmid = (nn - 1) / 2;
+  cx<T> u[Q];
+  dft_half_dif<P, -1, PAR>([&](int n) -> cx<T> { return row[n]; }, u);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int k2 = keptK<N, P>(2 * j + PAR);
+    if (k2 >= 0) {
+      const int c = k2 * n1 + k1;
+      Bout[c <= cmid ? c : nhp + (nn - 1 - c)] = u[j];
+      if (c == cmid) Bout[nhp + cmid] = u[j];
+    }
+  }
+}
+
+// One (pair-two, z) plane per workgroup, as k_plane_reg (mode PLANE_PRODUCT).
+// The column pass assembles the forward transform from its two parities by
+// one decimation step in time, X[k] = E[k] + w^{-k} O[k] and
+// X[k + P/2] = E[k] - w^{-k} O[k]: parity 0 hands E[k], k >= P/4, to parity 1
+// and parity 1 hands w^{-k} O[k], k < P/4, to parity 0 through LDS.
+template <typename T, int N, int P>
+__global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __restrict__ A,
+                                                                 cx<T>* __restrict__ B,
+                                                                 const T* __restrict__ fgrid,
+                                                                 CellStrides cs) {
+  using C = HalfCfg<P>;
+  constexpr int n1 = N - 1, nn = n1 * n1, LD = P + 1, Q = C::Q, QH = Q / 2;
+  static_assert(Q * P <= n1 * LD, "exchange buffer must fit the plane buffer");
+  A += blockIdx.z * cs.a;
+  B += blockIdx.z * cs.b;
+  fgrid += blockIdx.z * cs.fg;
+  __shared__ cx<T> sm[n1 * LD];
+  const int z = blockIdx.x, pt = blockIdx.y;
+  const int par = __builtin_amdgcn_readfirstlane((int)threadIdx.x / (64 * C::WPP));
+  const int l = (int)threadIdx.x - par * 64 * C::WPP;
+  if (l < n1) {
+    const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + l;
+    if (par == 0) half_rows_inv<T, N, P, 0>(Ain, sm + l * LD);
+    else half_rows_inv<T, N, P, 1>(Ain, sm + l * LD);
+  }
+  __syncthreads();
+  cx<T> u[Q];
+  const bool col = l < P;
+  if (col) {
+    const T* fz = fgrid + (size_t)z * P * P + l;
+    if (par == 0) half_cols<T, N, P, 0>(sm + l, fz, u);
+    else half_cols<T, N, P, 1>(sm + l, fz, u);
+  }
+  __syncthreads();
+  cx<T>* xa = sm;            // E[QH + i] from parity 0, [i][column]
+  cx<T>* xb = sm + QH * P;   // w^{-i} O[i] from parity 1
+  if (col) {
+    if (par == 0) {
+#pragma unroll
+      for (int i = 0; i < QH; ++i) xa[i * P + l] = u[QH + i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < QH; ++i) xb[i * P + l] = u[i];
+    }
+  }
+  __syncthreads();
+  if (col) {
+    if (par == 0) {
+#pragma unroll
+      for (int i = 0; i < QH; ++i) {
+        const cx<T> e = u[i], t = xb[i * P + l];
+        u[i] = cadd(e, t);
+        u[QH + i] = csub(e, t);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < QH; ++i) {
+        const cx<T> e = xa[i * P + l], t = u[QH + i];
+        u[i] = cadd(e, t);
+        u[QH + i] = csub(e, t);
+      }
+    }
+  }
+  __syncthreads();
+  if (col) {
+    if (par == 0) half_cols_store<T, N, P, 0>(u, sm + l);
+    else half_cols_store<T, N, P, 1>(u, sm + l);
+  }
+  __syncthreads();
+  if (l < n1) {
+    cx<T>* Bout = B + ((size_t)pt * P + z) * 2 * (((nn + 1) / 2 + 15) / 16 * 16);
+    if (par == 0) half_rows_fwd<T, N, P, 0>(sm + l * LD, Bout, l);
+    else half_rows_fwd<T, N, P, 1>(sm + l * LD, Bout, l);
+  }
+}
+
+template <typename T, int N, int P, int PAR>
+__device__ __forceinline__ void zfwd_half_fft(const cx<T>* __restrict__ Bin, cx<T> (*Wp)[64], int r) {
+  constexpr int n1 = N - 1, nn = n1 * n1, Q = P / 2;
+  constexpr int nhp = ((nn + 1) / 2 + 15) / 16 * 16;
+  cx<T> u[Q];
+  dft_half_dif<P, -1, PAR>([&](int n) -> cx<T> { return Bin[(size_t)n * 2 * nhp]; }, u);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int i3 = keptK<N, P>(2 * j + PAR);
+    if (i3 >= 0) Wp[i3][r] = u[j];
+  }
+}
+
+// Forward FFT along axis 3 with the weighting and accumulation overlapped:
+// producer waves transform the tile's 2 TQ pencils (TQ half-spectrum pencils
+// and their mirrors) of pair-two i+1 into one half of a double-buffered LDS
+// tile while consumer waves apply the weights of pair-two i from the other
+// half and keep their FP64 sums in registers (and fetch the weights of
+// pair-two i+1).  One barrier per pair-two.  A workgroup owns tile
+// blockIdx.x and the pair-twos s, s + S, s + 2S ... (s = blockIdx.y).
+// Producers: two waves of parities 0/1 (P > 48, dft_half_dif) or one wave
+// with whole register transforms.
+template <int P>
+struct ZfwdPipeCfg {
+  static constexpr int TQ = 32;
+  static constexpr int PW = P > 48 ? 2 : 1;
+  static constexpr int CW = 2;
+  static constexpr int NT = 64 * (PW + CW);
+};
+
+template <typename T, int N, int P, int PAR>
+__device__ __forceinline__ void zfwd_produce(const cx<T>* __restrict__ Bin, cx<T> (*Wb)[64], int r) {
+  if constexpr (PAR < 0) {
+    constexpr int nhp = (((N - 1) * (N - 1) + 1) / 2 + 15) / 16 * 16;
+    cx<T> v[P];
+#pragma unroll
+    for (int z = 0; z < P; ++z) v[z] = Bin[(size_t)z * 2 * nhp];
+    fft_reg<P, -1>(v);
+#pragma unroll
+    for (int i3 = 0; i3 < N - 1; ++i3) Wb[i3][r] = v[posKc<N, P>(i3)];
+  } else {
+    zfwd_half_fft<T, N, P, PAR>(Bin, Wb, r);
+  }
+}
+
+template <typename T, int N, int P>
+__global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
+    const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
+    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int npt, int S, CellStrides cs) {
+  using C = ZfwdPipeCfg<P>;
+  constexpr int TQ = C::TQ, PW = C::PW, NC = 64 * C::CW;
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  constexpr int nhp = (nh + 15) / 16 * 16;
+  constexpr int OPT = (TQ * n1 + NC - 1) / NC;
+  B += blockIdx.z * cs.b;
+  Qpart += blockIdx.z * cs.qp;
+  __shared__ cx<T> W[2][n1][2 * TQ];
+  __shared__ double2 E12[2][2][TQ];
+  __shared__ double2 E3[2][2][n1];
+  __shared__ double CPV[2][2];
+  const int c0 = blockIdx.x * TQ, s = blockIdx.y;
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int nmine = s < npt ? (npt - 1 - s) / S + 1 : 0;
+  if (wv < PW) {
+    // ---- producers
+    const int r = lane;
+    const int q = r < TQ ? r : r - TQ;
+    const bool have = c0 + q < nh;
+    const int cpen = r < TQ ? c0 + q : nn - 1 - (c0 + q);
+    const int slot = r < TQ ? c0 + q : nhp + c0 + q;
+    for (int i = 0; i <= nmine; ++i) {
+      if (i < nmine) {
+        const int pt = s + i * S, b = i & 1;
+        const int jA = pair0 + 2 * pt;
+        if (have) {
+          const cx<T>* Bin = B + (size_t)pt * P * 2 * nhp + slot;
+          if constexpr (PW == 1) zfwd_produce<T, N, P, -1>(Bin, W[b], r);
+          else if (wv == 0) zfwd_produce<T, N, P, 0>(Bin, W[b], r);
+          else zfwd_produce<T, N, P, 1>(Bin, W[b], r);
+        }
+        if (wv == 0) {
+          if (r < TQ && have) {
+            const int i2 = cpen / n1, i1 = cpen - i2 * n1;
+            const int k1 = i1 - h + 1, k2 = i2 - h + 1;
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+              const double2* pj = ph + (size_t)(jA + w) * 3 * PL + (N - 2);
+              const cx<double> e = cmul(d2c(pj[k1]), d2c(pj[PL + k2]));
+              E12[b][w][r] = double2{e.x, e.y};
+            }
+          }
+          if (r < 2) CPV[b][r] = cp[jA + r];
+        }
+        if (wv == PW - 1) {
+          for (int e = r; e < 2 * n1; e += 64) {
+            const int w = e / n1, i3 = e - w * n1;
+            const double2* pj = ph + (size_t)(jA + w) * 3 * PL + (N - 2);
+            E3[b][w][i3] = pj[2 * PL + i3 - h + 1];
+          }
+        }
+      }
+      lds_barrier();
+    }
+  } else {
+    // ---- consumers: output modes o = t + bb NC of the tile (i3 = o / TQ, pencil c0 + o % TQ)
+    const int t = (int)threadIdx.x - 64 * PW;
+    double accx[OPT], accy[OPT];
+    T va[OPT], vb[OPT];
+#pragma unroll
+    for (int bb = 0; bb < OPT; ++bb) accx[bb] = accy[bb] = 0.0;
+    for (int i = 0; i <= nmine; ++i) {
+      if (i > 0) {
+        const int b = (i - 1) & 1;
+        const double cA = CPV[b][0], cB = CPV[b][1];
+#pragma unroll
+        for (int bb = 0; bb < OPT; ++bb) {
+          const int o = t + bb * NC;
+          const int i3 = o / TQ, qq = o - i3 * TQ;
+          if (o < TQ * n1 && c0 + qq < nh) {
+            const cx<T> w1 = W[b][i3][qq];
+            const cx<T> w2 = W[b][n1 - 1 - i3][TQ + qq];
+            // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
+            const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
+            const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
+            const double vA = cA * (double)va[bb];
+            const double vB = cB * (double)vb[bb];
+            const cx<double> eA = cmul(d2c(E12[b][0][qq]), d2c(E3[b][0][i3]));
+            const cx<double> eB = cmul(d2c(E12[b][1][qq]), d2c(E3[b][1][i3]));
+            const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
+            accx[bb] += vA * tA.x + vB * tB.x;
+            accy[bb] += vA * tA.y + vB * tB.y;
+          }
+        }
+      }
+      if (i < nmine) {
+        // weights of the pair-two the producers are transforming now
+        const int jA = pair0 + 2 * (s + i * S);
+        const T* VA = V + (size_t)jA * nh * n1;
+        const T* VB = VA + (size_t)nh * n1;
+#pragma unroll
+        for (int bb = 0; bb < OPT; ++bb) {
+          const int o = t + bb * NC;
+          const int i3 = o / TQ, qq = o - i3 * TQ;
+          const bool ok = o < TQ * n1 && c0 + qq < nh;
+          const size_t vi = (size_t)i3 * nh + c0 + qq;
+          va[bb] = ok ? VA[vi] : T(0);
+          vb[bb] = ok ? VB[vi] : T(0);
+        }
+      }
+      lds_barrier();
+    }
+#pragma unroll
+    for (int bb = 0; bb < OPT; ++bb) {
+      const int o = t + bb * NC;
+      const int i3 = o / TQ, qq = o - i3 * TQ;
+      if (o < TQ * n1 && c0 + qq < nh) {
+        const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + qq;
+        double2 v = Qpart[qi];
+        v.x += accx[bb];
+        v.y += accy[bb];
+        Qpart[qi] = v;
+      }
+    }
+  }
+}
+
 // Forward FFT along axis 3 with one thread per (pencil, pair-two), then the
 // split of the two packed pairs, the weights and the FP64 accumulation.
 // A workgroup owns TQ half-spectrum pencils c0..c0+TQ-1 (and their mirrors)
@@ -781,6 +1122,22 @@ hipError_t plane_reg_t(const void* A, void* B, const void* fgrid, void* gridout,
   return hipGetLastError();
 }
 
+template <typename T, int P, int N>
+hipError_t plane_half_t(const void* A, void* B, const void* fgrid, int npt, const CellStrides& cs,
+                        hipStream_t st) {
+  dim3 grid(P, npt, cs.cells);
+  hipLaunchKernelGGL((k_plane_half<T, N, P>), grid, dim3(HalfCfg<P>::NT), 0, st, (const cx<T>*)A, (cx<T>*)B,
+                     (const T*)fgrid, cs);
+  return hipGetLastError();
+}
+
+// FP32 pencils of 72 and 96 points use the two-wave kernels
+template <typename T, int P>
+constexpr bool useHalf() { return sizeof(T) == 4 && (P == 72 || P == 96); }
+// FP32 z-forward stage with overlapped transform and weighting
+template <typename T, int P>
+constexpr bool usePipe() { return sizeof(T) == 4 && (P == 48 || P == 72 || P == 96); }
+
 template <typename T, int P>
 hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int N, int pair0, int npt,
                   int mode, const CellStrides& cs, hipStream_t st) {
@@ -798,6 +1155,8 @@ hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int
 template <typename T, int P>
 hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, const void* tw, int N,
                    int npt, int mode, const CellStrides& cs, hipStream_t st) {
+  if constexpr (useHalf<T, P>())
+    if (N == padN<P>() && mode == PLANE_PRODUCT) return plane_half_t<T, P, padN<P>()>(A, B, fgrid, npt, cs, st);
   if constexpr (RegFit<T, P>::value && isPad<P>())
     if (N == padN<P>()) return plane_reg_t<T, P, padN<P>()>(A, B, fgrid, gridout, npt, mode, cs, st);
   if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
@@ -812,6 +1171,15 @@ hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, con
 template <typename T, int P>
 hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
                   const void* tw, int N, int pair0, int npt, int S, const CellStrides& cs, hipStream_t st) {
+  if constexpr (usePipe<T, P>()) {
+    using C = ZfwdPipeCfg<P>;
+    constexpr int NN = padN<P>();
+    constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
+    dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
+    hipLaunchKernelGGL((k_zfwd_pipe<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
+                       (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S, cs);
+    return hipGetLastError();
+  }
   if constexpr (RegFit<T, P>::value && isPad<P>()) {
     using C = ZfwdCfg<T, P>;
     constexpr int NN = padN<P>();

@@ -44,6 +44,74 @@ double check_twiddles() {
   return err;
 }
 
+// half transforms by one decimation step in frequency: outputs of parity PAR
+template <int P, int SIGN, int PAR>
+double check_half() {
+  std::mt19937_64 g(P * 11 + SIGN * 3 + PAR);
+  std::uniform_real_distribution<double> ud(-1, 1);
+  cx<double> x[P];
+  for (int i = 0; i < P; ++i) x[i] = {ud(g), ud(g)};
+  cx<double> u[P / 2];
+  dft_half_dif<P, SIGN, PAR>([&](int n) { return x[n]; }, u);
+  double err = 0;
+  for (int j = 0; j < P / 2; ++j) {
+    const int k = 2 * j + PAR;
+    C acc = 0;
+    for (int n = 0; n < P; ++n) {
+      long double a = SIGN * 2.0L * 3.141592653589793238462643383279502884L * ((long double)n * k) / P;
+      acc += C(x[n].x, x[n].y) * C(cosl(a), sinl(a));
+    }
+    err = std::fmax(err, (double)std::abs(C(u[j].x, u[j].y) - acc));
+  }
+  return err;
+}
+
+// forward transform assembled from its two parities by one decimation step in
+// time, with the exchange of halves used by the plane kernel: parity 0 holds
+// E = DFT_Q(x[2j]), parity 1 holds w^{-k} O[k], O = DFT_Q(x[2j+1]); after the
+// exchange u0[i] = X[i], u0[Q/2+i] = X[Q+i], u1[i] = X[Q/2+i], u1[Q/2+i] = X[Q+Q/2+i]
+template <int P>
+double check_dit_exchange() {
+  constexpr int Q = P / 2, QH = Q / 2;
+  std::mt19937_64 g(P * 13 + 5);
+  std::uniform_real_distribution<double> ud(-1, 1);
+  cx<double> x[P], u0[Q], u1[Q];
+  for (int i = 0; i < P; ++i) x[i] = {ud(g), ud(g)};
+  for (int j = 0; j < Q; ++j) { u0[j] = x[2 * j]; u1[j] = x[2 * j + 1]; }
+  fft_reg<Q, -1>(u0);
+  fft_reg<Q, -1>(u1);
+  for (int k = 1; k < Q; ++k) u1[k] = twiddle_mul<P, -1>(u1[k], k);
+  cx<double> xa[QH], xb[QH];
+  for (int i = 0; i < QH; ++i) { xa[i] = u0[QH + i]; xb[i] = u1[i]; }
+  for (int i = 0; i < QH; ++i) {
+    const cx<double> e0 = u0[i], t0 = xb[i];
+    u0[i] = cadd(e0, t0); u0[QH + i] = csub(e0, t0);
+    const cx<double> e1 = xa[i], t1 = u1[QH + i];
+    u1[i] = cadd(e1, t1); u1[QH + i] = csub(e1, t1);
+  }
+  double err = 0;
+  for (int k = 0; k < P; ++k) {
+    C acc = 0;
+    for (int n = 0; n < P; ++n) {
+      long double a = -2.0L * 3.141592653589793238462643383279502884L * ((long double)n * k) / P;
+      acc += C(x[n].x, x[n].y) * C(cosl(a), sinl(a));
+    }
+    const int half = k < Q ? 0 : 1, kk = k % Q;
+    const cx<double> got = kk < QH ? (half ? u0[QH + kk] : u0[kk]) : (half ? u1[QH + kk - QH] : u1[kk - QH]);
+    err = std::fmax(err, (double)std::abs(C(got.x, got.y) - acc));
+  }
+  return err;
+}
+
+#define HALF(P)                                                                                       \
+  {                                                                                                   \
+    double e = std::fmax(std::fmax(check_half<P, -1, 0>(), check_half<P, -1, 1>()),                  \
+                         std::fmax(check_half<P, +1, 0>(), check_half<P, +1, 1>()));                  \
+    double d = check_dit_exchange<P>();                                                               \
+    std::printf("P=%d half=%.3e dit-exchange=%.3e\n", P, e, d);                                       \
+    worst = std::fmax(worst, std::fmax(e, d) / std::sqrt((double)P));                                 \
+  }
+
 #define RUN(P)                                                                          \
   {                                                                                     \
     double e1 = check_fft_reg<P, -1>(), e2 = check_fft_reg<P, +1>(), e3 = check_twiddles<P>(); \
@@ -54,6 +122,7 @@ double check_twiddles() {
 int main() {
   double worst = 0;
   RUN(8) RUN(12) RUN(16) RUN(24) RUN(32) RUN(36) RUN(48) RUN(64) RUN(72) RUN(96)
+  HALF(48) HALF(72) HALF(96)
   std::printf("worst %.3e\n", worst);
   return worst < 1e-14 ? 0 : 1;
 }
