@@ -324,8 +324,10 @@ __host__ __device__ __forceinline__ void fft_reg(cx<T>* x) {
 // with u[n] = (x[n] + (-1)^PAR x[n+Q]) w_P^{PAR n}, n < Q, the outputs of
 // parity PAR are X[2j + PAR] = DFT_Q(u)[j].  `get(n)` returns input n (n is a
 // compile-time constant after unrolling, so structurally zero inputs fold
-// away).  On return u[j] = X[2j + PAR].
-template <int P, int SIGN, int PAR, typename T, typename Get>
+// away).  On return u[j] = X[2j + PAR].  With GROUP > 0 the inputs are
+// fetched GROUP pairs at a time (a scheduling barrier after each group), which
+// bounds the registers held by loads in flight.
+template <int P, int SIGN, int PAR, int GROUP = 0, typename T, typename Get>
 __host__ __device__ __forceinline__ void dft_half_dif(Get get, cx<T>* u) {
   constexpr int Q = P / 2;
 #pragma unroll
@@ -336,6 +338,10 @@ __host__ __device__ __forceinline__ void dft_half_dif(Get get, cx<T>* u) {
     } else {
       u[n] = twiddle_mul<P, SIGN>(csub(a, b), n);
     }
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (GROUP > 0)
+      if ((n + 1) % GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+#endif
   }
   fft_reg<Q, SIGN>(u);
 }

@@ -64,6 +64,21 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Non-temporal access for the plane stage, which streams the first
+// intermediate in and the second out (each element is touched once there);
+// measured faster than ordinary accesses for that stage, while the z stages
+// are faster with ordinary ones.
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ cx<T> ld_nt(const cx<T>* p) {
+  const vec2<T> v = __builtin_nontemporal_load(reinterpret_cast<const vec2<T>*>(p));
+  return cx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_nt(cx<T>* p, cx<T> v) {
+  __builtin_nontemporal_store(vec2<T>{v.x, v.y}, reinterpret_cast<vec2<T>*>(p));
+}
 template <typename T>
 __device__ __forceinline__ cx<T> to_cx(double2 v) {
   return {(T)v.x, (T)v.y};
@@ -387,7 +402,7 @@ __global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>*
 #pragma unroll
     for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
 #pragma unroll
-    for (int i2 = 0; i2 < n1; ++i2) v[posKc<N, P>(i2)] = Ain[(size_t)i2 * n1];
+    for (int i2 = 0; i2 < n1; ++i2) v[posKc<N, P>(i2)] = ld_nt(Ain + (size_t)i2 * n1);
     fft_reg<P, +1>(v);
     cx<T>* row = sm + (zz * n1 + i1) * LD;
 #pragma unroll
@@ -433,8 +448,8 @@ __global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>*
     for (int k2 = 0; k2 < n1; ++k2) {
       const int c = k2 * n1 + k1;
       const cx<T> w = v[posKc<N, P>(k2)];
-      Bout[c <= cmid ? c : nhp + (nn - 1 - c)] = w;
-      if (c == cmid) Bout[nhp + cmid] = w;
+      st_nt(Bout + (c <= cmid ? c : nhp + (nn - 1 - c)), w);
+      if (c == cmid) st_nt(Bout + nhp + cmid, w);
     }
   }
 }
@@ -470,7 +485,7 @@ __device__ __forceinline__ void half_rows_inv(const cx<T>* __restrict__ Ain, cx<
   dft_half_dif<P, +1, PAR>(
       [&](int n) -> cx<T> {
         const int i2 = keptK<N, P>(n);
-        return i2 >= 0 ? Ain[(size_t)i2 * n1] : cx<T>{0, 0};
+        return i2 >= 0 ? ld_nt(Ain + (size_t)i2 * n1) : cx<T>{0, 0};
       },
       u);
 #pragma unroll
@@ -524,8 +539,8 @@ __device__ __forceinline__ void half_rows_fwd(const cx<T>* row, cx<T>* __restric
     const int k2 = keptK<N, P>(2 * j + PAR);
     if (k2 >= 0) {
       const int c = k2 * n1 + k1;
-      Bout[c <= cmid ? c : nhp + (nn - 1 - c)] = u[j];
-      if (c == cmid) Bout[nhp + cmid] = u[j];
+      st_nt(Bout + (c <= cmid ? c : nhp + (nn - 1 - c)), u[j]);
+      if (c == cmid) st_nt(Bout + nhp + cmid, u[j]);
     }
   }
 }
