@@ -545,6 +545,52 @@ __device__ __forceinline__ void half_rows_fwd(const cx<T>* row, cx<T>* __restric
   }
 }
 
+// Modulation and inverse FFT along axis 3 with two waves per 64 pencils: both
+// waves form the modulated pencil (63 values), the wave of parity PAR
+// transforms it to the heights z = 2j + PAR (dft_half_dif).
+template <typename T, int N, int P, int PAR>
+__device__ __forceinline__ void zinv_half_body(const cx<T>* __restrict__ fcc, const double2* __restrict__ phA,
+                                               const double2* __restrict__ phB, cx<double> eA12,
+                                               cx<double> eB12, cx<T>* __restrict__ Aout) {
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3, Q = P / 2;
+  cx<T> u[Q];
+  dft_half_dif<P, +1, PAR>(
+      [&](int n) -> cx<T> {
+        const int i3 = keptK<N, P>(n);
+        if (i3 < 0) return cx<T>{0, 0};
+        const int k3 = i3 - h + 1;
+        const cx<T> f = fcc[(size_t)i3 * nn];
+        const cx<double> eA = cmul(eA12, d2c(phA[2 * PL - 2 * k3]));
+        const cx<double> eB = cmul(eB12, d2c(phB[2 * PL - 2 * k3]));
+        const cx<T> m = {(T)(eA.x - eB.y), (T)(eA.y + eB.x)};     // E_A + i E_B
+        return cmul(f, m);
+      },
+      u);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) Aout[(size_t)(2 * j + PAR) * nn] = u[j];
+}
+
+template <typename T, int N, int P>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void k_zinv_half(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
+                                                   cx<T>* __restrict__ A, int pair0, CellStrides cs) {
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
+  fc += blockIdx.z * cs.fc;
+  A += blockIdx.z * cs.a;
+  const int par = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (c >= nn) return;
+  const int pt = blockIdx.y;
+  const int i2 = c / n1, i1 = c - i2 * n1;
+  const int k1 = i1 - h + 1, k2 = i2 - h + 1;
+  const double2* phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
+  const double2* phB = phA + 3 * PL;
+  const cx<double> eA12 = cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2]));
+  const cx<double> eB12 = cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2]));
+  cx<T>* Aout = A + (size_t)pt * P * nn + c;
+  if (par == 0) zinv_half_body<T, N, P, 0>(fc + c, phA, phB, eA12, eB12, Aout);
+  else zinv_half_body<T, N, P, 1>(fc + c, phA, phB, eA12, eB12, Aout);
+}
+
 // One (pair-two, z) plane per workgroup, as k_plane_reg (mode PLANE_PRODUCT).
 // The column pass assembles the forward transform from its two parities by
 // one decimation step in time, X[k] = E[k] + w^{-k} O[k] and
@@ -1156,6 +1202,14 @@ constexpr bool usePipe() { return sizeof(T) == 4 && (P == 48 || P == 72 || P == 
 template <typename T, int P>
 hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int N, int pair0, int npt,
                   int mode, const CellStrides& cs, hipStream_t st) {
+  if constexpr (useHalf<T, P>())
+    if (N == padN<P>() && mode == ZINV_PAIRS) {
+      constexpr int NN = padN<P>(), nn = (NN - 1) * (NN - 1);
+      dim3 grid((nn + 63) / 64, npt, cs.cells);
+      hipLaunchKernelGGL((k_zinv_half<T, NN, P>), grid, dim3(128), 0, st, (const cx<T>*)fc, (const double2*)ph,
+                         (cx<T>*)A, pair0, cs);
+      return hipGetLastError();
+    }
   if constexpr (RegFit<T, P>::value && isPad<P>())
     if (N == padN<P>()) return zinv_reg_t<T, P, padN<P>()>(fc, ph, A, pair0, npt, mode, cs, st);
   if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
