@@ -161,9 +161,9 @@ def batch_bench(bzq, torch, n_cells, steps, seed=0):
     return out
 
 
-def serve_bench(rates, duration):
+def serve_bench(rates, duration, precision="fp32"):
     from paper_2004_11239_amd import serve
-    return [serve.run(r, duration, seed=0, budget_gb=64, slots=4, precision="fp32", n_steps=10)
+    return [serve.run(r, duration, seed=0, budget_gb=64, slots=4, precision=precision, n_steps=10)
             for r in rates]
 
 
@@ -206,6 +206,29 @@ def cpu_baseline(cfg, fhat_np, n_modes=1536, seed=0):
                       "sample": f"{n_modes} of {len(modes)} output modes of one evaluation at the "
                                 f"medium workload in {t:.1f} s (direct weighted sum, FP64, weight "
                                 f"table included); value = sample / (time x modes)"}
+
+
+def cpu_fft_baseline(cfg, fhat_np, n_nodes=32, reps=5, seed=0):
+    """The same fast algorithm on the host (oracle.collision_fft: one pair of FP64
+    FFTs of P^3 per quadrature node, no pairing or packing), timed on a sample of
+    nodes with their weights precomputed (as the GPU plan's are) and scaled to
+    whole evaluations."""
+    import numpy as np
+    import oracle
+    d = oracle.Discretization.power(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"],
+                                    cfg["N_rho"], cfg["M"])
+    J = cfg["N_rho"] * cfg["M"]
+    nodes = np.sort(np.random.default_rng(seed).choice(J, size=n_nodes, replace=False))
+    T = oracle.weight_table(d, oracle.mode_vectors(cfg["N"]), nodes=nodes)
+    workers = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.collision_fft(fhat_np, d, nodes=nodes, T=T, workers=workers)
+    t = (time.perf_counter() - t0) / reps
+    return {"value": n_nodes / (t * J), "unit": "Q evals/s", "cores": workers, "kind": "cpu_fft",
+            "sample": f"{n_nodes} of {J} quadrature nodes of one evaluation at the medium workload, "
+                      f"{reps} repetitions, {t:.3f} s each (scipy.fft, FP64, weights precomputed); "
+                      f"value = sample / (time x nodes)"}
 
 
 def main():
@@ -320,7 +343,9 @@ def main():
         out["batched"] = batch_bench(bzq, torch, args.batch_cells, 2)
         torch.cuda.empty_cache()
     if args.serve_rates:
-        out["served"] = serve_bench([float(r) for r in args.serve_rates.split(",")], args.serve_duration)
+        rates = [float(r) for r in args.serve_rates.split(",")]
+        out["served"] = serve_bench(rates, args.serve_duration)
+        out["served_fp64"] = serve_bench(rates, args.serve_duration, precision="fp64")
     if not args.no_cpu_baseline:
         ks, qo, t, cb = cpu_baseline(cfg, fhat)
         idx = tuple(np.mod(ks, cfg["N"]).T)
@@ -328,6 +353,7 @@ def main():
             "fp32": float(np.linalg.norm(q32n[idx] - qo) / np.linalg.norm(qo)),
             "fp64": float(np.linalg.norm(q64n[idx] - qo) / np.linalg.norm(qo))}
         out["cpu_baseline"] = cb
+        out["cpu_fft_baseline"] = cpu_fft_baseline(cfg, fhat)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))

@@ -108,6 +108,13 @@ bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* s
  * device array f_hat. */
 bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream);
 
+/* The same with the classical fourth-order Runge-Kutta method, the time
+ * integrator of the paper's experiments (Section 5): four evaluations per step,
+ *   k1 = Q(f), k2 = Q(f + dt/2 k1), k3 = Q(f + dt/2 k2), k4 = Q(f + dt k3),
+ *   f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4),
+ * in place on the device array f_hat (FP64 state and stage sums). */
+bzq_status bzq_step_rk4(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream);
+
 /*
  * FP64 diagnostics of f on the N^3 grid v_j = -L + j 2L/N (Section 1):
  *   out[0] mass (2L)^3 Re f_0 (Remark 4.1)

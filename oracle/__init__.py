@@ -10,7 +10,8 @@ Contents
   quadrature  Gauss-Legendre in |q|, Lebedev on S^2, Gauss-Jacobi in t (eq. approxG)
   angular     the angular weight F (eq. FF) and its independent pins
   collision   the direct weighted sum (eq. sum with eq. approxG; eq. realQ regrouped)
-  physics     moments, entropy dissipation, Heun step of the Galerkin ODE
+  physics     moments, entropy dissipation, Heun and RK4 steps of the Galerkin ODE
+  fast_fft    the fast algorithm (eq. realQ) with FFTs, for the CPU throughput baseline
   bkw         the BKW exact solution and its closed-form Q (Section 5.1)
 
 Every function here is pinned by a CPU test against something other than
@@ -22,5 +23,6 @@ from .angular import (AngularKernel, PAPER_KERNELS, bkw_lambda, cutoff_kernel, p
                       F_eps_split)
 from .collision import (Discretization, collision_direct, mode_vectors, quadrature_nodes,
                         weight_table)
-from .physics import entropy_dissipation, heun_step, moments, to_physical
+from .physics import entropy_dissipation, heun_step, moments, rk4_step, to_physical
+from .fast_fft import collision_fft
 from . import bkw, quadrature

@@ -79,9 +79,12 @@ def quadrature_nodes(d: Discretization):
     return rho_j, sig_j, wr_j * ws_j * rho_j ** (2.0 + d.gamma)
 
 
-def weight_table(d: Discretization, k_out: np.ndarray) -> np.ndarray:
-    """T_j(k) = w_p w_q rho_p^{2+gamma} F(k, rho_p, sigma_q) for all nodes j, modes k: [J, nk]."""
+def weight_table(d: Discretization, k_out: np.ndarray, nodes=None) -> np.ndarray:
+    """T_j(k) = w_p w_q rho_p^{2+gamma} F(k, rho_p, sigma_q) for all nodes j (or the
+    listed ones), modes k: [J, nk]."""
     rho, sig, wq = quadrature_nodes(d)
+    if nodes is not None:
+        rho, sig, wq = rho[nodes], sig[nodes], wq[nodes]
     a = math.pi * rho / (2.0 * d.L)
     kf = k_out.astype(np.float64)
     kd = sig @ kf.T                                               # [J, nk]

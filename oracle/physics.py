@@ -6,7 +6,9 @@
 * H-functional dissipation D = \\int Q ln f <= 0 (Section 1, H-theorem), summed
   over grid points where f exceeds 1e-14 max f;
 * the Galerkin ODE d f_k / dt = Q_k (Section 2) advanced by Heun's method
-  (explicit trapezoid): f* = f + dt Q(f), f <- f + dt/2 (Q(f) + Q(f*)).
+  (explicit trapezoid): f* = f + dt Q(f), f <- f + dt/2 (Q(f) + Q(f*)), or by
+  the classical fourth-order Runge-Kutta method the paper's experiments use
+  (Section 5).
 
 Test infrastructure only: nothing in the GPU product path imports this file.
 """
@@ -54,8 +56,22 @@ def entropy_dissipation(qhat: np.ndarray, f_samples: np.ndarray, L: float) -> fl
     return float((2.0 * L / N) ** 3 * np.sum(q[mask] * np.log(f_samples[mask])))
 
 
-def heun_step(fhat: np.ndarray, d: Discretization, dt: float, **kw) -> np.ndarray:
-    q1 = collision_direct(fhat, d, **kw)
+def heun_step(fhat: np.ndarray, d: Discretization, dt: float, collide=None, **kw) -> np.ndarray:
+    """One Heun step; `collide(f)` replaces Q (default: the direct sum with d)."""
+    Q = collide if collide is not None else (lambda g: collision_direct(g, d, **kw))
+    q1 = Q(fhat)
     fs = fhat + dt * q1
-    q2 = collision_direct(fs, d, **kw)
+    q2 = Q(fs)
     return fhat + 0.5 * dt * (q1 + q2)
+
+
+def rk4_step(fhat: np.ndarray, d: Discretization, dt: float, collide=None, **kw) -> np.ndarray:
+    """One classical Runge-Kutta step:
+    k1 = Q(f), k2 = Q(f + dt/2 k1), k3 = Q(f + dt/2 k2), k4 = Q(f + dt k3),
+    f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4)."""
+    Q = collide if collide is not None else (lambda g: collision_direct(g, d, **kw))
+    k1 = Q(fhat)
+    k2 = Q(fhat + 0.5 * dt * k1)
+    k3 = Q(fhat + 0.5 * dt * k2)
+    k4 = Q(fhat + dt * k3)
+    return fhat + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)

@@ -50,6 +50,7 @@ def _load():
         "bzq_plan_create_general": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, i, vp], i),
         "bzq_collision": ([vp, vp, vp, vp], i),
         "bzq_step": ([vp, vp, d, i, vp], i),
+        "bzq_step_rk4": ([vp, vp, d, i, vp], i),
         "bzq_moments": ([vp, vp, vp, ctypes.POINTER(d), vp], i),
         "bzq_check_finite": ([vp, vp, vp], i),
         "bzq_collision_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp], i),
@@ -96,7 +97,7 @@ EXPORTED_EXTRA = ("bzq_workspace_create", "bzq_collision_ws", "bzq_step_ws", "bz
                   "bzq_batch_groups", "bzq_batch_group_info", "bzq_batch_device_bytes",
                   "bzq_batch_destroy", "bzq_server_create", "bzq_server_submit", "bzq_server_poll",
                   "bzq_server_wait", "bzq_server_stats", "bzq_server_destroy", "bzq_plan_bytes_estimate")
-EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_step", "bzq_moments",
+EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_step", "bzq_step_rk4", "bzq_moments",
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
             "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error")
@@ -166,10 +167,16 @@ class Plan:
         _check(_lib.bzq_collision(self.handle, fp, qp, _stream(stream)))
         return out
 
-    def step(self, f_hat: torch.Tensor, dt: float, n_steps: int = 1, stream=None):
-        """n_steps Heun steps of d f/dt = Q(f, f), in place."""
+    def step(self, f_hat: torch.Tensor, dt: float, n_steps: int = 1, stream=None, method: str = "heun"):
+        """n_steps steps of d f/dt = Q(f, f), in place: Heun's method (default)
+        or the classical fourth-order Runge-Kutta method (method="rk4")."""
         fp = _spectral(f_hat, self.N, "f_hat")
-        _check(_lib.bzq_step(self.handle, fp, float(dt), int(n_steps), _stream(stream)))
+        if method == "heun":
+            _check(_lib.bzq_step(self.handle, fp, float(dt), int(n_steps), _stream(stream)))
+        elif method == "rk4":
+            _check(_lib.bzq_step_rk4(self.handle, fp, float(dt), int(n_steps), _stream(stream)))
+        else:
+            raise ValueError("method must be 'heun' or 'rk4'")
         return f_hat
 
     def moments(self, f_hat: torch.Tensor, Q_hat: Optional[torch.Tensor] = None, stream=None):

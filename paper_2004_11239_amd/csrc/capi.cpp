@@ -306,6 +306,35 @@ bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, doub
   return BZQ_OK;
 }
 
+// Classical fourth-order Runge-Kutta: k1 = Q(f), k2 = Q(f + dt/2 k1),
+// k3 = Q(f + dt/2 k2), k4 = Q(f + dt k3), f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4);
+// q1 holds the current stage's Q, q2 the running sum, fs the stage argument.
+bzq_status enqueue_step_rk4(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
+                            hipStream_t st) {
+  const size_t n3 = (size_t)p.N * p.N * p.N;
+  PtrPack q{}, acc{}, fs{};
+  for (int c = 0; c < cells; ++c) {
+    q.p[c] = w.q1 + c * n3 * 2;
+    acc.p[c] = w.q2 + c * n3 * 2;
+    fs.p[c] = w.fs + c * n3 * 2;
+  }
+  for (int i = 0; i < n_steps; ++i) {
+    bzq_status s;
+    if ((s = enqueue_collision(p, w, f, q, cells, st)) != BZQ_OK) return s;
+    BZQ_HIP_TRY(launch_axpy_cells(acc, f, dt / 6.0, q, n3, cells, st));
+    BZQ_HIP_TRY(launch_axpy_cells(fs, f, 0.5 * dt, q, n3, cells, st));
+    if ((s = enqueue_collision(p, w, fs, q, cells, st)) != BZQ_OK) return s;
+    BZQ_HIP_TRY(launch_axpy_cells(acc, acc, dt / 3.0, q, n3, cells, st));
+    BZQ_HIP_TRY(launch_axpy_cells(fs, f, 0.5 * dt, q, n3, cells, st));
+    if ((s = enqueue_collision(p, w, fs, q, cells, st)) != BZQ_OK) return s;
+    BZQ_HIP_TRY(launch_axpy_cells(acc, acc, dt / 3.0, q, n3, cells, st));
+    BZQ_HIP_TRY(launch_axpy_cells(fs, f, dt, q, n3, cells, st));
+    if ((s = enqueue_collision(p, w, fs, q, cells, st)) != BZQ_OK) return s;
+    BZQ_HIP_TRY(launch_axpy_cells(f, acc, dt / 6.0, q, n3, cells, st));
+  }
+  return BZQ_OK;
+}
+
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
                        double br, int nj, int N_rho, int M, int precision, void* stream) {
   if (!out) return fail(BZQ_EINVAL, "out is NULL");
@@ -391,6 +420,12 @@ bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* str
   if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
   return enqueue_step(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
+}
+
+bzq_status bzq_step_rk4(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream) {
+  if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
+  if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
+  return enqueue_step_rk4(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
 }
 
 bzq_status bzq_workspace_create(bzq_workspace* out, bzq_plan p) {

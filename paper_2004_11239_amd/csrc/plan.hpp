@@ -105,6 +105,10 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
 bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
                         hipStream_t st);
 
+// Enqueue n_steps classical Runge-Kutta (RK4) steps in place for `cells` cells.
+bzq_status enqueue_step_rk4(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
+                            hipStream_t st);
+
 inline PtrPack single(const double* p) {
   PtrPack pk{};
   pk.p[0] = const_cast<double*>(p);

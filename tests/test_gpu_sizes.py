@@ -137,7 +137,7 @@ def test_moments_converge_with_N(bzq):
     assert errs[2][1] < errs[0][1]
 
 
-@pytest.mark.parametrize("name", ["b5", "b8"])
+@pytest.mark.parametrize("name", ["b5", "b6", "b7", "b8"])
 def test_bkw_against_closed_form(bzq, name):
     """Table 2 setup (N = N_rho = 32, R = 6, L = (3+sqrt 2)R/4, t = 6.5): the
     L-infinity error of Q against eq. QQ falls as the sphere rule is refined and
@@ -159,3 +159,34 @@ def test_bkw_against_closed_form(bzq, name):
     assert errs[38] > errs[110] > 0.5 * errs[302]
     assert errs[110] < 1e-4
     assert errs[302] < 2e-5
+
+
+def test_table2_sphere_rule_sweep(bzq):
+    """The study of Table 2 with Lebedev rules in place of spherical designs:
+    L-infinity error of Q against eq. QQ for b5-b8 over the available sphere
+    rules (N = N_rho = 32, R = 6, L = (3+sqrt 2)R/4, t = 6.5).  Printed as a
+    table; the error must fall by orders of magnitude from the coarsest rule to
+    the finest, for every kernel, singular or not."""
+    R = 6.0
+    L = (3 + math.sqrt(2)) * R / 4
+    N = 32
+    K = bkw.K_of_t(6.5, 1.0 / 6.0)
+    f = workloads.to_spectral(workloads.bkw_profile_on_grid(N, L, K))
+    qext = bkw.on_grid(bkw.Q_bkw, N, L, K, 1.0 / 6.0)
+    Ms = (6, 14, 26, 38, 50, 74, 86, 110, 146, 170, 194, 230, 266, 302)
+    table = {}
+    for name in ("b5", "b6", "b7", "b8"):
+        kern = oracle.PAPER_KERNELS[name]
+        row = []
+        for M in Ms:
+            plan = bzq.Plan(N, L, R, 0.0, 0.0, 32, M, precision="fp64", kernel=(kern.c, kern.s, kern.r))
+            Q = _host(plan.collision(_dev(f)))
+            plan.destroy()
+            row.append(float(np.max(np.abs(oracle.to_physical(Q, L) - qext))))
+        table[name] = row
+    print("M      " + " ".join(f"{m:>9d}" for m in Ms))
+    for name, row in table.items():
+        print(f"{name:6s} " + " ".join(f"{e:9.2e}" for e in row))
+    for name, row in table.items():
+        assert row[-1] < 1e-3 * row[0], name
+        assert min(row[-3:]) < 2e-7, name

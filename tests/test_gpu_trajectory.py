@@ -124,3 +124,51 @@ def test_invariants_along_200_steps(bzq):
     assert abs(rec64[-1]["entropy_dissipation"]) < abs(rec64[0]["entropy_dissipation"])
     f32, _ = trajs["fp32"]
     assert _rel(f32, f64) < 1e-5
+
+
+@pytest.fixture(scope="module")
+def oracle_rk4():
+    """Oracle RK4 trajectory, N = 8, 12 steps of dt = 0.1; checkpoints 0, 4, 12."""
+    N, L, R, s, N_rho, M, dt = 8, 8.0, 4.0, 0.25, 6, 14, 0.1
+    d = oracle.Discretization.power(N, L, R, -1.0, s, N_rho, M)
+    T = oracle.weight_table(d, oracle.mode_vectors(N))
+    f = workloads.to_spectral(workloads.two_maxwellians(9).sample(N, L))
+    out = {0: f.copy()}
+    for n in range(1, 13):
+        f = oracle.rk4_step(f, d, dt, T=T)
+        if n in (4, 12):
+            out[n] = f.copy()
+    return (N, L, R, s, N_rho, M, dt), out
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_rk4_trajectory_matches_oracle(bzq, oracle_rk4, prec, tol):
+    (N, L, R, s, N_rho, M, dt), ref = oracle_rk4
+    plan = bzq.Plan(N, L, R, -1.0, s, N_rho, M, precision=prec)
+    g = _dev(ref[0])
+    done = 0
+    for n in (4, 12):
+        plan.step(g, dt, n - done, method="rk4")
+        done = n
+        got = _host(g)
+        assert _rel(got, ref[n]) < tol, (prec, n, _rel(got, ref[n]))
+
+
+def test_bkw_rk4_beats_heun_at_large_steps(bzq):
+    """Four steps of dt = 0.25 from the BKW profile at t0 = 6.5: the fourth-order
+    method lands on the closed form f(K(7.5)) more closely than Heun's method."""
+    R = 6.0
+    L = (3 + math.sqrt(2)) * R / 4
+    N, N_rho, M, dt, nsteps, t0 = 32, 32, 302, 0.25, 4, 6.5
+    lam = 1.0 / 6.0
+    f0 = workloads.to_spectral(workloads.bkw_profile_on_grid(N, L, bkw.K_of_t(t0, lam)))
+    exact = bkw.on_grid(bkw.f_bkw, N, L, bkw.K_of_t(t0 + nsteps * dt, lam))
+    plan = bzq.Plan(N, L, R, 0.0, 0.5, N_rho, M, precision="fp64")
+    errs = {}
+    for method in ("heun", "rk4"):
+        g = _dev(f0)
+        plan.step(g, dt, nsteps, method=method)
+        errs[method] = float(np.max(np.abs(oracle.to_physical(_host(g), L) - exact)))
+    print("BKW, 4 steps of 0.25:", errs)
+    assert errs["rk4"] < errs["heun"]
+    assert errs["rk4"] < 1e-6

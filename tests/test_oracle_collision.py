@@ -170,3 +170,17 @@ def test_bkw_closed_form_sphere_convergence():
     assert errs[38] > errs[110] > 0.9 * errs[302]
     assert errs[302] < 1e-4
     assert errs[38] > 1e-3
+
+
+@pytest.mark.parametrize("N,gamma,s,N_rho,M", [(8, 0.0, 0.5, 6, 14), (16, -1.0, 0.25, 4, 26)])
+def test_fft_form_equals_direct_sum(N, gamma, s, N_rho, M):
+    """The FFT evaluation of eq. realQ (zero padding to 3N/2) equals the direct
+    weighted sum: dealiasing is exact and the convolution is the truncated one."""
+    L = 8.0
+    d = oracle.Discretization.power(N, L, 4.0, gamma, s, N_rho, M)
+    f = workloads.to_spectral(workloads.random_mixture(N).sample(N, L))
+    modes = oracle.mode_vectors(N)
+    T = oracle.weight_table(d, modes)
+    q_direct = oracle.collision_direct(f, d, T=T)
+    q_fft = oracle.collision_fft(f, d, T=T)
+    assert np.linalg.norm(q_fft - q_direct) <= 1e-13 * np.linalg.norm(q_direct)
