@@ -246,14 +246,17 @@ bzq_status bzq_plan_pairs(bzq_plan p, double* out);
 bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out);
 
 /*
- * Kernel timing for measurement: with timing enabled, every launch the plan
- * enqueues is bracketed by HIP events on the caller's stream.
+ * Kernel timing for measurement: the launches of the stages selected by
+ * `enable` are each bracketed by HIP events on the caller's stream (enable:
+ * 0 = off, 1 = every stage, otherwise a mask with bit s set for stage s, e.g.
+ * 4 = the plane stage only, which keeps the events off the other launches;
+ * the prep stage cannot be selected alone).
  * bzq_plan_stage_times (synchronous) returns into host out[10] the summed
- * milliseconds of the launches of each stage {0 prep (ingest, f on the padded
- * grid, accumulator clear), 1 modulate + inverse FFT along axis 3, 2 plane
- * transforms and product, 3 forward FFT along axis 3 + weighting and
+ * milliseconds of the timed launches of each stage {0 prep (ingest, f on the
+ * padded grid, accumulator clear), 1 modulate + inverse FFT along axis 3,
+ * 2 plane transforms and product, 3 forward FFT along axis 3 + weighting and
  * accumulation, 4 finalisation} followed by the launch count of each stage,
- * and clears the record.  Enabling or disabling clears it too.
+ * and clears the record.  Setting the mask clears it too.
  */
 bzq_status bzq_plan_set_timing(bzq_plan p, int enable);
 bzq_status bzq_plan_stage_times(bzq_plan p, double* out);

@@ -218,8 +218,18 @@ class Plan:
 
     STAGES = ("prep", "zinv", "plane", "zfwd", "finalize")
 
-    def set_timing(self, enable: bool):
-        _check(_lib.bzq_plan_set_timing(self.handle, int(bool(enable))))
+    def set_timing(self, enable, stages=None):
+        """Per-launch HIP events on the timed stages (all stages, or the listed
+        stage names: prep, zinv, plane, zfwd, finalize)."""
+        if not enable:
+            mask = 0
+        elif stages is None:
+            mask = 1
+        else:
+            mask = sum(1 << self.STAGES.index(n) for n in stages)
+            if mask == 1:
+                raise ValueError("the prep stage cannot be timed alone")
+        _check(_lib.bzq_plan_set_timing(self.handle, int(mask)))
 
     def stage_times(self) -> dict:
         """{stage: (total_ms, launches)} since timing was enabled (synchronous)."""

@@ -243,9 +243,9 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
 
 enum Stage { ST_PREP = 0, ST_ZINV = 1, ST_PLANE = 2, ST_ZFWD = 3, ST_FINAL = 4, ST_COUNT = 5 };
 
-// Record an event before (begin=true) or after a launch when timing is on.
+// Record an event before (begin=true) or after a launch of a timed stage.
 hipError_t mark(Plan& p, int stage, bool begin, hipStream_t st) {
-  if (!p.timing) return hipSuccess;
+  if (!(p.timing >> stage & 1)) return hipSuccess;
   if (p.ev_used == p.ev_pool.size()) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
@@ -565,7 +565,8 @@ bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
 
 bzq_status bzq_plan_set_timing(bzq_plan p, int enable) {
   if (!p) return fail(BZQ_EINVAL, "NULL plan");
-  p->timing = enable != 0;
+  if (enable < 0) return fail(BZQ_EINVAL, "timing mask must be >= 0");
+  p->timing = enable == 1 ? (1 << ST_COUNT) - 1 : enable;
   p->ev_stage.clear();
   p->ev_used = 0;
   return BZQ_OK;

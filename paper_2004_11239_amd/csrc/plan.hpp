@@ -83,7 +83,7 @@ struct Plan {
   int* flag = nullptr;
   DeviceArena grid_scratch;
   // optional per-launch timing
-  bool timing = false;
+  int timing = 0;   // bit s set: bracket the launches of stage s with events
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_stage;
   size_t ev_used = 0;
