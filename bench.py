@@ -78,6 +78,7 @@ def time_steps(bzq, torch, cfg, prec, fhat_np, steps, warmup):
     plan = bzq.Plan(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"], cfg["N_rho"], cfg["M"],
                     precision=prec)
     f0 = torch.from_numpy(fhat_np).to("cuda")
+    plan.autotune(f0)                           # kernel schedule (cached after the first run)
     f = f0.clone()
     for _ in range(warmup):
         plan.step(f, DT, 1)
@@ -149,6 +150,8 @@ def batch_bench(bzq, torch, n_cells, steps, seed=0):
     cells = workloads.cell_batch(n_cells, seed)
     plans = {N: bzq.Plan(N, 8.0, 4.0, 0.0, 0.5, N, 110, precision="fp32") for N in (16, 24, 32)}
     fs = [torch.from_numpy(f).to("cuda") for _, f in cells]
+    for N, p in plans.items():                 # kernel schedule per plan, tuned on one of its cells
+        p.autotune(fs[next(i for i, (n, _) in enumerate(cells) if n == N)])
     batch = bzq.Batch([plans[N] for N, _ in cells], fs, cells_per_launch=0)
     setup = time.perf_counter() - t0
     batch.step(0.01, 1, use_graph=True)          # capture + warm-up
@@ -327,6 +330,7 @@ def main():
                    "gamma": cfg["gamma"], "s": cfg["s"], "precision": "fp32 bulk, fp64 accumulate",
                    "antipodal_pairs": npairs},
         "roofline": roof,
+        "schedule": {"fp32": p32.schedule(), "fp64": p64.schedule()},
         "fp64": {"value": round(value64, 3), "ms_per_step": round(ms64 / steps64, 4),
                  "stage_ms_per_eval": {k: round(v[0] / (2 * steps64), 4) for k, v in st64.items()}},
         "err_fp32_vs_fp64": err32_64,
@@ -344,6 +348,7 @@ def main():
             st.pop("plane_timed_region")
             large[prec] = {"evals_per_s": round(4 / (ms * 1e-3), 3), "ms_per_eval": round(ms / 4, 3),
                            "stage_ms_per_eval": {k: round(v[0] / 4, 3) for k, v in st.items()},
+                           "schedule": p.schedule(),
                            "whole_path": whole_path(cl["N"], p.info()["npairs"], 4 if prec == "fp32" else 8,
                                                     ms / 4)}
             qs[prec] = q.cpu().numpy()

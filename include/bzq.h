@@ -246,6 +246,30 @@ bzq_status bzq_plan_pairs(bzq_plan p, double* out);
 bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out);
 
 /*
+ * Schedule of a plan: the kernel variant of each pipeline stage {0 modulation
+ * and FFT along axis 3, 1 plane transforms and product, 2 FFT along axis 3,
+ * weighting and accumulation}: 1 = one whole pencil per lane, 2 = two waves
+ * per pencil (stages 0, 1) or the pipelined producer/consumer kernel (stage 2),
+ * available for N = 32, 48, 64; 0 = the default variant.  s_target is the
+ * number of workgroups the last stage aims at (512, 1024 or 2048).  Every
+ * schedule evaluates eq. realQ; schedules differ in rounding order only
+ * (results agree within the precision's tolerance) and one schedule always
+ * gives bitwise identical results.
+ *   bzq_plan_set_schedule: host sched[4] = {v0, v1, v2, s_target}; EINVAL for a
+ *     variant this plan does not have.  No work may be pending on the plan.
+ *   bzq_plan_schedule: host out[5] = {v0, v1, v2 as used, s_target, splits}.
+ *   bzq_plan_autotune: times evaluations of f_hat (device, as bzq_collision)
+ *     under the variants of one stage at a time (and the three s_target values
+ *     for the last stage), keeps the fastest and records it in the tuning cache
+ *     ($BZQ_TUNE_CACHE or ~/.cache/bzq_autotune.txt; key: N, P, precision,
+ *     pairs, chunk).  With use_cache != 0 a recorded schedule is applied without
+ *     timing.  Synchronous; uses the plan's own workspace.
+ */
+bzq_status bzq_plan_set_schedule(bzq_plan p, const int* sched);
+bzq_status bzq_plan_schedule(bzq_plan p, int* out);
+bzq_status bzq_plan_autotune(bzq_plan p, const double* f_hat, int use_cache, void* stream);
+
+/*
  * Kernel timing for measurement: the launches of the stages selected by
  * `enable` are each bracketed by HIP events on the caller's stream (enable:
  * 0 = off, 1 = every stage, otherwise a mask with bit s set for stage s, e.g.

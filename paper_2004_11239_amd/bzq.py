@@ -51,6 +51,9 @@ def _load():
         "bzq_collision": ([vp, vp, vp, vp], i),
         "bzq_step": ([vp, vp, d, i, vp], i),
         "bzq_step_rk4": ([vp, vp, d, i, vp], i),
+        "bzq_plan_set_schedule": ([vp, vp], i),
+        "bzq_plan_schedule": ([vp, vp], i),
+        "bzq_plan_autotune": ([vp, vp, i, vp], i),
         "bzq_moments": ([vp, vp, vp, ctypes.POINTER(d), vp], i),
         "bzq_check_finite": ([vp, vp, vp], i),
         "bzq_collision_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp], i),
@@ -100,7 +103,8 @@ EXPORTED_EXTRA = ("bzq_workspace_create", "bzq_collision_ws", "bzq_step_ws", "bz
 EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_step", "bzq_step_rk4", "bzq_moments",
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
-            "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error")
+            "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error",
+            "bzq_plan_set_schedule", "bzq_plan_schedule", "bzq_plan_autotune")
 
 
 def lib():
@@ -230,6 +234,23 @@ class Plan:
             if mask == 1:
                 raise ValueError("the prep stage cannot be timed alone")
         _check(_lib.bzq_plan_set_timing(self.handle, int(mask)))
+
+    def schedule(self) -> dict:
+        """Kernel variant per stage (as used), the last stage's workgroup target and splits."""
+        out = (ctypes.c_int * 5)()
+        _check(_lib.bzq_plan_schedule(self.handle, out))
+        return {"zinv": out[0], "plane": out[1], "zfwd": out[2], "s_target": out[3], "splits": out[4]}
+
+    def set_schedule(self, zinv: int = 0, plane: int = 0, zfwd: int = 0, s_target: int = 1024):
+        arr = (ctypes.c_int * 4)(int(zinv), int(plane), int(zfwd), int(s_target))
+        _check(_lib.bzq_plan_set_schedule(self.handle, arr))
+        return self.schedule()
+
+    def autotune(self, f_hat: torch.Tensor, use_cache: bool = True, stream=None) -> dict:
+        """Time the kernel variants on f_hat and keep the fastest schedule (synchronous)."""
+        fp = _spectral(f_hat, self.N, "f_hat")
+        _check(_lib.bzq_plan_autotune(self.handle, fp, int(bool(use_cache)), _stream(stream)))
+        return self.schedule()
 
     def stage_times(self) -> dict:
         """{stage: (total_ms, launches)} since timing was enabled (synchronous)."""

@@ -41,36 +41,8 @@ struct Group {
 std::string tune_key(const Plan& p) {
   std::ostringstream k;
   k << "N=" << p.N << " P=" << p.P << " prec=" << (p.fp32 ? "fp32" : "fp64") << " npairs=" << p.npairs
-    << " G=" << p.G << " S=" << p.S;
+    << " G=" << p.G << " S=" << p.S << " sched=" << p.var[0] << p.var[1] << p.var[2];
   return k.str();
-}
-
-std::string tune_path() {
-  const char* e = std::getenv("BZQ_TUNE_CACHE");
-  if (e && *e) return e;
-  const char* h = std::getenv("HOME");
-  return std::string(h && *h ? h : "/tmp") + "/.cache/bzq_autotune.txt";
-}
-
-std::map<std::string, int> read_cache() {
-  std::map<std::string, int> m;
-  std::ifstream in(tune_path());
-  std::string line;
-  while (std::getline(in, line)) {
-    const size_t bar = line.rfind('|');
-    if (bar == std::string::npos) continue;
-    m[line.substr(0, bar)] = std::atoi(line.c_str() + bar + 1);
-  }
-  return m;
-}
-
-void write_cache(const std::map<std::string, int>& m) {
-  const std::string path = tune_path();
-  const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) (void)::mkdir(path.substr(0, slash).c_str(), 0755);
-  std::ofstream out(path, std::ios::trunc);
-  if (!out) return;   // a read-only home only loses the cache
-  for (const auto& kv : m) out << kv.first << "|" << kv.second << "\n";
 }
 
 size_t ws_budget_bytes() {
@@ -150,7 +122,7 @@ bzq_status time_candidate(Group& g, const std::vector<double*>& f, int cpl, hipS
 }
 
 bzq_status autotune(Group& g, const std::vector<double*>& f, hipStream_t st) {
-  auto cache = read_cache();
+  auto cache = tune_cache_read();
   const std::string key = tune_key(*g.plan);
   auto it = cache.find(key);
   const int ncell = (int)g.cells.size();
@@ -177,7 +149,7 @@ bzq_status autotune(Group& g, const std::vector<double*>& f, hipStream_t st) {
   g.tuned = true;
   if (ncell >= 2 * best) {   // only a choice made with room to spare is worth caching
     cache[key] = best;
-    write_cache(cache);
+    tune_cache_write(cache);
   }
   return BZQ_OK;
 }

@@ -23,8 +23,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "plan.hpp"
 #include "quadrature.hpp"
@@ -69,7 +74,7 @@ Plan::~Plan() {
 size_t Plan::workspace_bytes_per_cell() const {
   const size_t N3 = (size_t)N * N * N;
   return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * nn * 2 * esz +
-         (size_t)G * P * 2 * nhp * 2 * esz + (size_t)S * nh * n1 * 16 + 3 * N3 * 16;
+         (size_t)G * P * 2 * nhp * 2 * esz + (size_t)S_cap * nh * n1 * 16 + 3 * N3 * 16;
 }
 
 bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
@@ -80,7 +85,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   w.cs.fg = (size_t)p.P * p.P * p.P;
   w.cs.a = (size_t)p.G * p.P * p.nn;
   w.cs.b = (size_t)p.G * p.P * 2 * p.nhp;
-  w.cs.qp = (size_t)p.S * p.nh * p.n1;
+  w.cs.qp = (size_t)p.S_cap * p.nh * p.n1;
   w.cs.cells = cells;
   const size_t N3 = (size_t)p.N * p.N * p.N;
   bzq_status s;
@@ -95,10 +100,58 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   return BZQ_OK;
 }
 
+namespace {
+std::string tune_path() {
+  const char* e = std::getenv("BZQ_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = std::getenv("HOME");
+  return std::string(h && *h ? h : "/tmp") + "/.cache/bzq_autotune.txt";
+}
+}  // namespace
+
+std::map<std::string, int> tune_cache_read() {
+  std::map<std::string, int> m;
+  std::ifstream in(tune_path());
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t bar = line.rfind('|');
+    if (bar == std::string::npos) continue;
+    m[line.substr(0, bar)] = std::atoi(line.c_str() + bar + 1);
+  }
+  return m;
+}
+
+void tune_cache_write(const std::map<std::string, int>& m) {
+  const std::string path = tune_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) (void)::mkdir(path.substr(0, slash).c_str(), 0755);
+  std::ofstream out(path, std::ios::trunc);
+  if (!out) return;   // a read-only home only loses the cache
+  for (const auto& kv : m) out << kv.first << "|" << kv.second << "\n";
+}
+
+int effective_variant(const Plan& p, int stage) {
+  return p.var[stage] ? p.var[stage] : stage_default_variant(stage, p.P, p.fp32);
+}
+
+// Splits of the z-forward stage for kernel variant zv: about s_target
+// workgroups of tq pencils, at most one per group of pair-twos.  Pipelined
+// kernel: 32 pencils, one pair-two per step; other register kernels: 32 or 16
+// pencils, 2 or 4 pair-twos per step; LDS kernels (FP64 P > 48): 8 pencils.
+int zfwd_splits(const Plan& p, int zv, int s_target) {
+  const bool pipe = zv == 2 && (p.P == 48 || p.P == 72 || p.P == 96);
+  const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
+  const int tq = pipe ? 32 : reg_zfwd ? (p.fp32 ? 32 : 16) : 8;
+  const int pt_group = pipe ? 1 : reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
+  const int groups = (p.G + pt_group - 1) / pt_group;
+  const int tiles = (p.nh + tq - 1) / tq;
+  return std::max(1, std::min(groups, (s_target + tiles - 1) / tiles));
+}
+
 // Chunking of the pair loop: the two pipeline intermediates stay below 1 GiB
 // per cell (one chunk per evaluation up to N = 32); the splits S of the last
-// stage give enough workgroups to fill the chip but no more than there are
-// groups of pair-twos (4 per group in the register variant).
+// stage give about s_target workgroups (enough to fill the chip) but no more
+// than there are groups of pair-twos.  S_cap bounds S over every schedule.
 void set_chunking(Plan& p) {
   p.esz = p.fp32 ? 4 : 8;
   p.nhp = (p.nh + 15) / 16 * 16;
@@ -106,16 +159,10 @@ void set_chunking(Plan& p) {
   const char* env = std::getenv("BZQ_CHUNK_MB");
   const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
   p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
-  // z-forward kernels: FP32 P >= 48 pipelined (32 pencils, one pair-two per
-  // step), other register kernels (32 or 16 pencils, 2 or 4 pair-twos per
-  // step), LDS kernels for FP64 P > 48 (8 pencils, one pair-two)
-  const bool pipe = p.fp32 && p.P >= 48;
-  const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
-  const int tq = reg_zfwd ? (p.fp32 ? 32 : 16) : 8;
-  const int pt_group = pipe ? 1 : reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
-  const int groups = (p.G + pt_group - 1) / pt_group;
-  const int tiles = (p.nh + tq - 1) / tq;
-  p.S = std::max(1, std::min(groups, (1024 + tiles - 1) / tiles));
+  p.S = zfwd_splits(p, effective_variant(p, 2), p.s_target);
+  p.S_cap = p.S;
+  for (int v = 1; v <= 2; ++v)
+    if (stage_variants(2, p.P, p.fp32) >> v & 1) p.S_cap = std::max(p.S_cap, zfwd_splits(p, v, 2048));
 }
 
 // Device bytes a plan will hold (tables, its workspace, grid scratch), from
@@ -276,12 +323,15 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
   // f(v) on the padded grid, shared by every pair
   TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
   TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st));
-  TIMED(ST_PREP, launch_fill(w.Qpart, 0.0, cells * cs.qp * 2, st));
+  // the S partial accumulators of every cell start at zero
+  TIMED(ST_PREP, launch_fill(w.Qpart, 0.0, ((cells - 1) * cs.qp + (size_t)p.S * p.nh * p.n1) * 2, st));
   for (int c0 = 0; c0 < p.npt; c0 += p.G) {
     const int n = std::min(p.G, p.npt - c0);
-    TIMED(ST_ZINV, launch_zinv(w.fc, p.ph, w.A, p.tw_pad, g, 2 * c0, n, ZINV_PAIRS, p.fp32, cs, st));
-    TIMED(ST_PLANE, launch_plane(w.A, w.B, w.fgrid, nullptr, p.tw_pad, g, n, PLANE_PRODUCT, p.fp32, cs, st));
-    TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, p.S, p.fp32, cs, st));
+    TIMED(ST_ZINV, launch_zinv(w.fc, p.ph, w.A, p.tw_pad, g, 2 * c0, n, ZINV_PAIRS, p.fp32, cs, st, p.var[0]));
+    TIMED(ST_PLANE, launch_plane(w.A, w.B, w.fgrid, nullptr, p.tw_pad, g, n, PLANE_PRODUCT, p.fp32, cs, st,
+                                 p.var[1]));
+    TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, p.S, p.fp32, cs, st,
+                               p.var[2]));
   }
   TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, p.S, st));
   return BZQ_OK;
@@ -420,6 +470,125 @@ bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* str
   if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
   return enqueue_step(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
+}
+
+namespace {
+
+constexpr int kSTargets[3] = {512, 1024, 2048};
+
+int encode_schedule(const Plan& p) {
+  int t = 0;
+  while (t < 2 && kSTargets[t] != p.s_target) ++t;
+  return p.var[0] | p.var[1] << 2 | p.var[2] << 4 | t << 6;
+}
+void decode_schedule(Plan& p, int code) {
+  p.var[0] = code & 3;
+  p.var[1] = code >> 2 & 3;
+  p.var[2] = code >> 4 & 3;
+  p.s_target = kSTargets[std::min(2, code >> 6 & 3)];
+}
+std::string schedule_key(const Plan& p) {
+  std::ostringstream k;
+  k << "schedule N=" << p.N << " P=" << p.P << " prec=" << (p.fp32 ? "fp32" : "fp64")
+    << " npairs=" << p.npairs << " G=" << p.G;
+  return k.str();
+}
+
+// Best of two timed evaluations (after one untimed) with the plan's current
+// schedule, in milliseconds.
+bzq_status time_schedule(Plan& p, const double* f_hat, double* Q, hipStream_t st, float* best) {
+  hipEvent_t e0, e1;
+  BZQ_HIP_TRY(hipEventCreate(&e0));
+  BZQ_HIP_TRY(hipEventCreate(&e1));
+  bzq_status s = enqueue_collision(p, p.ws, single(f_hat), single(Q), 1, st);
+  *best = 1e30f;
+  for (int r = 0; r < 2 && s == BZQ_OK; ++r) {
+    (void)hipEventRecord(e0, st);
+    s = enqueue_collision(p, p.ws, single(f_hat), single(Q), 1, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess) s = fail(BZQ_EDEVICE, "timing an evaluation failed");
+    float ms = 0.f;
+    if (s == BZQ_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) *best = std::min(*best, ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return s;
+}
+
+}  // namespace
+
+bzq_status bzq_plan_set_schedule(bzq_plan p, const int* sched) {
+  if (!p || !sched) return fail(BZQ_EINVAL, "NULL argument");
+  for (int st = 0; st < 3; ++st) {
+    const int v = sched[st];
+    if (v < 0 || v > 2 || (v && !(stage_variants(st, p->P, p->fp32) >> v & 1)))
+      return fail(BZQ_EINVAL, "kernel variant not available for this plan");
+  }
+  if (sched[3] != kSTargets[0] && sched[3] != kSTargets[1] && sched[3] != kSTargets[2])
+    return fail(BZQ_EINVAL, "s_target must be 512, 1024 or 2048");
+  const int G = p->G, S_cap = p->S_cap;
+  for (int st = 0; st < 3; ++st) p->var[st] = sched[st];
+  p->s_target = sched[3];
+  set_chunking(*p);
+  if (p->G != G || p->S_cap != S_cap) return fail(BZQ_EDEVICE, "schedule changed the workspace geometry");
+  return BZQ_OK;
+}
+
+bzq_status bzq_plan_schedule(bzq_plan p, int* out) {
+  if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
+  for (int st = 0; st < 3; ++st) out[st] = effective_variant(*p, st);
+  out[3] = p->s_target;
+  out[4] = p->S;
+  return BZQ_OK;
+}
+
+bzq_status bzq_plan_autotune(bzq_plan p, const double* f_hat, int use_cache, void* stream) {
+  if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  const std::string key = schedule_key(*p);
+  if (use_cache) {
+    auto cache = tune_cache_read();
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      decode_schedule(*p, it->second);
+      set_chunking(*p);
+      return BZQ_OK;
+    }
+  }
+  double* Q = p->ws.q1;   // scratch output (the workspace is idle between calls)
+  float best = 0.f;
+  bzq_status s = time_schedule(*p, f_hat, Q, st, &best);
+  if (s != BZQ_OK) return s;
+  // one stage at a time, the others kept at their best so far
+  for (int stage = 0; stage < 3; ++stage) {
+    const unsigned avail = stage_variants(stage, p->P, p->fp32);
+    for (int v = 1; v <= 2; ++v) {
+      for (int t = 0; t < 3; ++t) {
+        if (!(avail >> v & 1)) continue;
+        if (stage < 2 && t != 1) continue;   // s_target matters to the z-forward only
+        const int old_v = p->var[stage], old_t = p->s_target;
+        if (effective_variant(*p, stage) == v && (stage < 2 || kSTargets[t] == old_t)) continue;
+        p->var[stage] = v;
+        if (stage == 2) p->s_target = kSTargets[t];
+        set_chunking(*p);
+        float ms = 0.f;
+        if ((s = time_schedule(*p, f_hat, Q, st, &ms)) != BZQ_OK) return s;
+        if (ms < 0.98f * best) {
+          best = ms;
+        } else {
+          p->var[stage] = old_v;
+          p->s_target = old_t;
+          set_chunking(*p);
+        }
+      }
+    }
+  }
+  for (int stage = 0; stage < 3; ++stage) p->var[stage] = effective_variant(*p, stage);
+  set_chunking(*p);
+  auto cache = tune_cache_read();
+  cache[key] = encode_schedule(*p);
+  tune_cache_write(cache);
+  return BZQ_OK;
 }
 
 bzq_status bzq_step_rk4(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream) {

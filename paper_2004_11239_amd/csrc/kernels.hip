@@ -571,7 +571,7 @@ __device__ __forceinline__ void zinv_half_body(const cx<T>* __restrict__ fcc, co
 }
 
 template <typename T, int N, int P>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void k_zinv_half(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_zinv_half(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
                                                    cx<T>* __restrict__ A, int pair0, CellStrides cs) {
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
   fc += blockIdx.z * cs.fc;
@@ -1193,17 +1193,30 @@ hipError_t plane_half_t(const void* A, void* B, const void* fgrid, int npt, cons
 }
 
 // FP32 pencils of 72 and 96 points use the two-wave kernels
+// Kernel variants of the three pipeline stages: 1 = one whole pencil per lane
+// (register kernels; LDS kernels where a pencil does not fit the register
+// file), 2 = two waves per pencil (z-inverse, plane) and the pipelined
+// z-forward, for P = 48, 72, 96.  0 selects the default below (the faster one
+// in measurements at 32^3 and 64^3); plans can be autotuned to another.
+template <int P>
+constexpr bool hasTwo() { return P == 48 || P == 72 || P == 96; }
 template <typename T, int P>
-constexpr bool useHalf() { return sizeof(T) == 4 && (P == 72 || P == 96); }
-// FP32 z-forward stage with overlapped transform and weighting
-template <typename T, int P>
-constexpr bool usePipe() { return sizeof(T) == 4 && (P == 48 || P == 72 || P == 96); }
+constexpr int defaultVariant(int stage) {
+  if constexpr (sizeof(T) == 4) {
+    if (stage == 2) return P == 48 || P == 72 || P == 96 ? 2 : 1;   // z-forward
+    return P == 72 || P == 96 ? 2 : 1;                               // z-inverse, plane
+  }
+  if (stage == 1) return P == 72 || P == 96 ? 2 : 1;                 // FP64 plane
+  if (stage == 2) return P == 48 ? 2 : 1;                            // FP64 z-forward
+  return 1;
+}
 
 template <typename T, int P>
 hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int N, int pair0, int npt,
-                  int mode, const CellStrides& cs, hipStream_t st) {
-  if constexpr (useHalf<T, P>())
-    if (N == padN<P>() && mode == ZINV_PAIRS) {
+                  int mode, int variant, const CellStrides& cs, hipStream_t st) {
+  const int v = variant ? variant : defaultVariant<T, P>(0);
+  if constexpr (hasTwo<P>())
+    if (v == 2 && N == padN<P>() && mode == ZINV_PAIRS) {
       constexpr int NN = padN<P>(), nn = (NN - 1) * (NN - 1);
       dim3 grid((nn + 63) / 64, npt, cs.cells);
       hipLaunchKernelGGL((k_zinv_half<T, NN, P>), grid, dim3(128), 0, st, (const cx<T>*)fc, (const double2*)ph,
@@ -1223,9 +1236,10 @@ hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int
 
 template <typename T, int P>
 hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, const void* tw, int N,
-                   int npt, int mode, const CellStrides& cs, hipStream_t st) {
-  if constexpr (useHalf<T, P>())
-    if (N == padN<P>() && mode == PLANE_PRODUCT) return plane_half_t<T, P, padN<P>()>(A, B, fgrid, npt, cs, st);
+                   int npt, int mode, int variant, const CellStrides& cs, hipStream_t st) {
+  const int v = variant ? variant : defaultVariant<T, P>(1);
+  if constexpr (hasTwo<P>())
+    if (v == 2 && N == padN<P>() && mode == PLANE_PRODUCT) return plane_half_t<T, P, padN<P>()>(A, B, fgrid, npt, cs, st);
   if constexpr (RegFit<T, P>::value && isPad<P>())
     if (N == padN<P>()) return plane_reg_t<T, P, padN<P>()>(A, B, fgrid, gridout, npt, mode, cs, st);
   if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
@@ -1239,16 +1253,19 @@ hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, con
 
 template <typename T, int P>
 hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
-                  const void* tw, int N, int pair0, int npt, int S, const CellStrides& cs, hipStream_t st) {
-  if constexpr (usePipe<T, P>()) {
-    using C = ZfwdPipeCfg<P>;
-    constexpr int NN = padN<P>();
-    constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
-    dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
-    hipLaunchKernelGGL((k_zfwd_pipe<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
-                       (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S, cs);
-    return hipGetLastError();
-  }
+                  const void* tw, int N, int pair0, int npt, int S, int variant, const CellStrides& cs,
+                  hipStream_t st) {
+  const int v = variant ? variant : defaultVariant<T, P>(2);
+  if constexpr (hasTwo<P>())
+    if (v == 2) {
+      using C = ZfwdPipeCfg<P>;
+      constexpr int NN = padN<P>();
+      constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
+      dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
+      hipLaunchKernelGGL((k_zfwd_pipe<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
+                         (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S, cs);
+      return hipGetLastError();
+    }
   if constexpr (RegFit<T, P>::value && isPad<P>()) {
     using C = ZfwdCfg<T, P>;
     constexpr int NN = padN<P>();
@@ -1283,22 +1300,23 @@ hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells
 }
 
 hipError_t launch_zinv(const void* fc, const double* ph, void* A, const void* tw, Geometry g, int pair0,
-                       int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st) {
-#define CASE(PP)                                                                            \
-  case PP:                                                                                  \
-    return fp32 ? zinv_t<float, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, cs, st)         \
-                : zinv_t<double, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, cs, st);
+                       int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st, int variant) {
+#define CASE(PP)                                                                                 \
+  case PP:                                                                                       \
+    return fp32 ? zinv_t<float, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, variant, cs, st)      \
+                : zinv_t<double, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, variant, cs, st);
   switch (g.P) { BZQ_ALL_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
-                        Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st) {
-#define CASE(PP)                                                                              \
-  case PP:                                                                                    \
-    return fp32 ? plane_t<float, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, cs, st)       \
-                : plane_t<double, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, cs, st);
+                        Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st,
+                        int variant) {
+#define CASE(PP)                                                                                   \
+  case PP:                                                                                         \
+    return fp32 ? plane_t<float, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, variant, cs, st)   \
+                : plane_t<double, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, variant, cs, st);
   switch (g.P) { BZQ_ALL_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
@@ -1306,14 +1324,29 @@ hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout
 
 hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
                        const void* tw, Geometry g, int pair0, int npt, int S, bool fp32,
-                       const CellStrides& cs, hipStream_t st) {
-#define CASE(PP)                                                                                 \
-  case PP:                                                                                       \
-    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, cs, st)        \
-                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, cs, st);
+                       const CellStrides& cs, hipStream_t st, int variant) {
+#define CASE(PP)                                                                                     \
+  case PP:                                                                                           \
+    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, variant, cs, st)   \
+                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, variant, cs, st);
   switch (g.P) { BZQ_PAD_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
+}
+
+int stage_default_variant(int stage, int P, bool fp32) {
+#define CASE(PP) \
+  case PP:       \
+    return fp32 ? defaultVariant<float, PP>(stage) : defaultVariant<double, PP>(stage);
+  switch (P) { BZQ_ALL_P(CASE) }
+#undef CASE
+  return 1;
+}
+
+unsigned stage_variants(int stage, int P, bool fp32) {
+  (void)stage;
+  (void)fp32;
+  return (P == 48 || P == 72 || P == 96) ? 0x6u : 0x2u;
 }
 
 hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,

@@ -40,19 +40,28 @@ hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells
 // Step 1 of the pipeline: modulate (mode ZINV_PAIRS) and inverse-transform along
 // axis 3; writes A[pt][z][c] for pt < npt, z < P, c < (N-1)^2.
 hipError_t launch_zinv(const void* fc, const double* phase, void* A, const void* tw, Geometry g,
-                       int pair0, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st);
+                       int pair0, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st,
+                       int variant = 0);
 
 // Step 2: per (pt, z) plane: inverse along axes 2 and 1, product with the
 // physical f (mode PLANE_PRODUCT) or output of the real grid (PLANE_TO_GRID),
 // forward along axes 1 and 2.
 hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
-                        Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st);
+                        Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st,
+                        int variant = 0);
 
 // Step 3: forward along axis 3, split the two packed pairs, apply the stored
 // weights and the phase e^{i a k.sigma}, accumulate in FP64 into Qpart[s].
 hipError_t launch_zfwd(const void* B, const void* V, const double* phase, const double* cp,
                        double* Qpart, const void* tw, Geometry g, int pair0, int npt, int S,
-                       bool fp32, const CellStrides& cs, hipStream_t st);
+                       bool fp32, const CellStrides& cs, hipStream_t st, int variant = 0);
+
+// Kernel variants of the stages {0 z-inverse, 1 plane, 2 z-forward}: bit v of
+// stage_variants is set when variant v runs for padded length P (1 = one whole
+// pencil per lane, 2 = two waves per pencil / pipelined z-forward);
+// stage_default_variant is the one variant 0 selects.
+unsigned stage_variants(int stage, int P, bool fp32);
+int stage_default_variant(int stage, int P, bool fp32);
 
 // Sum of the S partial accumulators and Hermitian completion into Q (N^3 FFT order).
 hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -64,6 +65,11 @@ struct Plan {
   int npt = 0;      // pairs of pairs (packed into one complex transform)
   int G = 0;        // pair-twos per chunk
   int S = 0;        // accumulation splits of the last stage
+  int S_cap = 0;    // largest S of any schedule (sizes the accumulators)
+  // schedule: kernel variant per stage {z-inverse, plane, z-forward} (0 =
+  // default, see stage_variants) and the z-forward workgroups aimed at
+  int var[3] = {0, 0, 0};
+  int s_target = 1024;
   size_t esz = 0;   // bytes per real element (4 or 8)
   std::vector<double> pair_host;  // [npairs][6] for introspection
   // tables (read-only after creation)
@@ -92,6 +98,10 @@ struct Plan {
 };
 
 bzq_status workspace_init(Workspace& w, const Plan& p, int cells);
+int effective_variant(const Plan& p, int stage);
+// Autotuning cache: "key|value" lines in $BZQ_TUNE_CACHE or ~/.cache/bzq_autotune.txt
+std::map<std::string, int> tune_cache_read();
+void tune_cache_write(const std::map<std::string, int>& m);
 void set_chunking(Plan& p);
 size_t plan_footprint(int N, int N_rho, int M, int precision);
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
