@@ -494,7 +494,7 @@ std::string schedule_key(const Plan& p) {
   return k.str();
 }
 
-// Best of two timed evaluations (after one untimed) with the plan's current
+// Best of four timed evaluations (after one untimed) with the plan's current
 // schedule, in milliseconds.
 bzq_status time_schedule(Plan& p, const double* f_hat, double* Q, hipStream_t st, float* best) {
   hipEvent_t e0, e1;
@@ -502,7 +502,7 @@ bzq_status time_schedule(Plan& p, const double* f_hat, double* Q, hipStream_t st
   BZQ_HIP_TRY(hipEventCreate(&e1));
   bzq_status s = enqueue_collision(p, p.ws, single(f_hat), single(Q), 1, st);
   *best = 1e30f;
-  for (int r = 0; r < 2 && s == BZQ_OK; ++r) {
+  for (int r = 0; r < 4 && s == BZQ_OK; ++r) {
     (void)hipEventRecord(e0, st);
     s = enqueue_collision(p, p.ws, single(f_hat), single(Q), 1, st);
     (void)hipEventRecord(e1, st);
@@ -573,7 +573,7 @@ bzq_status bzq_plan_autotune(bzq_plan p, const double* f_hat, int use_cache, voi
         set_chunking(*p);
         float ms = 0.f;
         if ((s = time_schedule(*p, f_hat, Q, st, &ms)) != BZQ_OK) return s;
-        if (ms < 0.98f * best) {
+        if (ms < 0.97f * best) {   // a candidate must win clearly over timing noise
           best = ms;
         } else {
           p->var[stage] = old_v;
