@@ -12,6 +12,7 @@ Contents
   collision   the direct weighted sum (eq. sum with eq. approxG; eq. realQ regrouped)
   physics     moments, entropy dissipation, Heun and RK4 steps of the Galerkin ODE
   fast_fft    the fast algorithm (eq. realQ) with FFTs, for the CPU throughput baseline
+  collision2d the two-dimensional operator (circle rule, eq. FF2D1) and the 2-D BKW solution
   bkw         the BKW exact solution and its closed-form Q (Section 5.1)
 
 Every function here is pinned by a CPU test against something other than
@@ -25,4 +26,5 @@ from .collision import (Discretization, collision_direct, mode_vectors, quadratu
                         weight_table)
 from .physics import entropy_dissipation, heun_step, moments, rk4_step, to_physical
 from .fast_fft import collision_fft
+from . import collision2d
 from . import bkw, quadrature

@@ -28,7 +28,7 @@ __all__ = [
     "velocity_grid", "mode_indices", "to_spectral", "maxwellian_on_grid",
     "MaxwellianMixture", "two_maxwellians", "random_mixture", "bkw_profile_on_grid",
     "ProblemConfig", "CFG_SMALL", "CFG_MEDIUM", "CFG_LARGE", "config_input",
-    "cell_batch", "request_stream",
+    "cell_batch", "request_stream", "to_spectral_2d", "bkw2d_profile_on_grid", "random_mixture_2d",
 ]
 
 
@@ -116,6 +116,44 @@ def bkw_profile_on_grid(N: int, L: float, K: float) -> np.ndarray:
     v2 = v[:, None, None] ** 2 + v[None, :, None] ** 2 + v[None, None, :] ** 2
     return (2 * math.pi * K) ** -1.5 * np.exp(-v2 / (2 * K)) * (
         (5 * K - 3) / (2 * K) + (1 - K) * v2 / (2 * K * K))
+
+
+def to_spectral_2d(f_phys: np.ndarray) -> np.ndarray:
+    """The 2-D projection: f_k = N^-2 (-1)^(k1+k2) sum_j f(v_j) e^{-2 pi i k.j/N},
+    Nyquist removed; complex128 N^2 in FFT index order."""
+    f_phys = np.asarray(f_phys, dtype=np.float64)
+    N = f_phys.shape[0]
+    assert f_phys.shape == (N, N) and N % 2 == 0
+    sign = np.where(mode_indices(N) % 2 == 0, 1.0, -1.0)
+    fh = np.fft.fft2(f_phys) / float(N) ** 2 * sign[:, None] * sign[None, :]
+    fh[N // 2, :] = 0.0
+    fh[:, N // 2] = 0.0
+    return fh.astype(np.complex128)
+
+
+def bkw2d_profile_on_grid(N: int, L: float, K: float) -> np.ndarray:
+    """The 2-D BKW profile (2 pi K)^-1 exp(-|v|^2/2K) [ (4K - 2)/(2K) + (1 - K)|v|^2/(2K^2) ]
+    (Section 5.1 with d = 2), sampled on the N^2 grid; used only as initial data."""
+    v = velocity_grid(N, L)
+    v2 = v[:, None] ** 2 + v[None, :] ** 2
+    return np.exp(-v2 / (2 * K)) / (2 * math.pi * K) * ((4 * K - 2) / (2 * K) + (1 - K) * v2 / (2 * K * K))
+
+
+def random_mixture_2d(seed: int, N: int, L: float) -> np.ndarray:
+    """2-D analogue of `random_mixture` sampled on the N^2 grid: 2-5 Maxwellians,
+    centres U[-3,3]^2 (scaled by L/8 for boxes smaller than L = 8), temperatures
+    U[0.5,1.5] (same scaling squared), Dirichlet(1) weights."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 6))
+    scale = min(1.0, L / 8.0)
+    centers = rng.uniform(-3.0, 3.0, size=(n, 2)) * scale
+    temps = rng.uniform(0.5, 1.5, size=n) * scale ** 2
+    w = rng.dirichlet(np.ones(n))
+    v = velocity_grid(N, L)
+    f = np.zeros((N, N))
+    for wi, u, T in zip(w, centers, temps):
+        f += wi / (2.0 * math.pi * T) * np.exp(-((v[:, None] - u[0]) ** 2 + (v[None, :] - u[1]) ** 2) / (2.0 * T))
+    return f
 
 
 # --------------------------------------------------------------------------
