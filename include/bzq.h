@@ -49,6 +49,7 @@ typedef struct bzq_plan_s* bzq_plan;
 typedef struct bzq_workspace_s* bzq_workspace;
 typedef struct bzq_batch_s* bzq_batch;
 typedef struct bzq_server_s* bzq_server;
+typedef struct bzq_plan2d_s* bzq_plan2d;
 
 typedef enum {
     BZQ_OK = 0,
@@ -215,6 +216,24 @@ int bzq_server_poll(bzq_server s, unsigned long long id, double* f_out, double* 
 bzq_status bzq_server_wait(bzq_server s, unsigned long long id, double timeout_s);
 bzq_status bzq_server_stats(bzq_server s, double* out);
 bzq_status bzq_server_destroy(bzq_server s);
+
+/*
+ * The two-dimensional operator (d = 2, the setting of the paper's Section 5.2
+ * and Table 1): K_N = {-N/2+1 .. N/2-1}^2, f_k = (2L)^{-2} \int f e^{-i pi k.v/L},
+ * weight T = w_rho w_sigma rho^{1+gamma} F(k, rho, sigma) with F the angular
+ * integral of eq. FF2D1 for b = c t^{-1-s} (1-t)^{-r} (t = sin^2(th/2);
+ * -1 <= s < 1/2, -1 < r < 1/2, covering b1-b4 of Section 5.2), a Gauss-Legendre
+ * rule of N_rho nodes on [0, R] and the midpoint rule of N_sigma (even) points
+ * on the circle.  f_hat, Q_hat: device complex128 N^2, C order [i1][i2], FFT
+ * index order, Nyquist rows/columns not read and written 0.  N in {8, 16, 24,
+ * 32, 48, 64}; precision as for 3-D plans.  Creation is synchronous; the plan
+ * owns its scratch, so calls on one plan must not overlap in time.
+ */
+bzq_status bzq_plan2d_create(bzq_plan2d* out, int N, double L, double R, double gamma, double b_c,
+                             double b_s, double b_r, int n_jacobi, int N_rho, int N_sigma, int precision,
+                             void* stream);
+bzq_status bzq_collision2d(bzq_plan2d p, const double* f_hat, double* Q_hat, void* stream);
+bzq_status bzq_plan2d_destroy(bzq_plan2d p);
 
 /* Device bytes held by the plan (tables + scratch), for admission control. */
 size_t bzq_plan_device_bytes(bzq_plan p);

@@ -27,6 +27,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 
 SOURCES = [
     ("kernels.hip", True),
+    ("kernels2d.hip", True),
+    ("capi2d.cpp", False),
     ("capi.cpp", False),
     ("batch.cpp", False),
     ("server.cpp", False),

@@ -84,6 +84,9 @@ def _load():
         "bzq_plan_set_timing": ([vp, i], i),
         "bzq_plan_stage_times": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_destroy": ([vp], i),
+        "bzq_plan2d_create": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, i, vp], i),
+        "bzq_collision2d": ([vp, vp, vp, vp], i),
+        "bzq_plan2d_destroy": ([vp], i),
         "bzq_status_string": ([i], ctypes.c_char_p),
         "bzq_last_error": ([], ctypes.c_char_p),
     }
@@ -104,7 +107,8 @@ EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
             "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error",
-            "bzq_plan_set_schedule", "bzq_plan_schedule", "bzq_plan_autotune")
+            "bzq_plan_set_schedule", "bzq_plan_schedule", "bzq_plan_autotune", "bzq_plan2d_create",
+            "bzq_collision2d", "bzq_plan2d_destroy")
 
 
 def lib():
@@ -264,6 +268,58 @@ class Plan:
     def destroy(self):
         if getattr(self, "_h", None) is not None:
             _lib.bzq_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Plan2D:
+    """Plan of the two-dimensional operator (d = 2, Section 5.2): kernel
+    b = c t^{-1-s} (1-t)^{-r} with t = sin^2(th/2), N_rho Gauss-Legendre nodes on
+    [0, R], the midpoint rule of N_sigma points on the circle."""
+
+    def __init__(self, N: int, L: float, R: float, gamma: float, kernel: Sequence[float], N_rho: int,
+                 N_sigma: int, precision="fp64", n_jacobi: int = 64, stream=None):
+        self.N, self.L, self.R, self.gamma = int(N), float(L), float(R), float(gamma)
+        self.kernel = tuple(float(x) for x in kernel)
+        self.N_rho, self.N_sigma = int(N_rho), int(N_sigma)
+        self.precision = _PREC[precision]
+        c, sb, r = self.kernel
+        h = ctypes.c_void_p()
+        _check(_lib.bzq_plan2d_create(ctypes.byref(h), self.N, self.L, self.R, self.gamma, c, sb, r,
+                                      int(n_jacobi), self.N_rho, self.N_sigma, self.precision,
+                                      _stream(stream)))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def _spectral2d(self, t: torch.Tensor, name: str):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+            raise TypeError(f"{name} must be a complex128 CUDA tensor")
+        if tuple(t.shape) != (self.N, self.N) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous ({self.N},{self.N}) tensor")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def collision(self, f_hat: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        """Q(f, f) of eq. realQ in 2-D; complex128 (N,N) in FFT order on the GPU."""
+        fp = self._spectral2d(f_hat, "f_hat")
+        if out is None:
+            out = torch.empty_like(f_hat)
+        qp = self._spectral2d(out, "out")
+        _check(_lib.bzq_collision2d(self.handle, fp, qp, _stream(stream)))
+        return out
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.bzq_plan2d_destroy(self._h)
             self._h = None
 
     def __del__(self):

