@@ -233,6 +233,16 @@ bzq_status bzq_plan2d_create(bzq_plan2d* out, int N, double L, double R, double 
                              double b_s, double b_r, int n_jacobi, int N_rho, int N_sigma, int precision,
                              void* stream);
 bzq_status bzq_collision2d(bzq_plan2d p, const double* f_hat, double* Q_hat, void* stream);
+
+/* Time integrators of the 2-D Galerkin system, as for 3-D plans. */
+typedef enum { BZQ_HEUN = 0, BZQ_RK4 = 1 } bzq_method;
+
+/* Advance d f/dt = Q(f, f) by n_steps steps of Heun's method (BZQ_HEUN) or of
+ * the classical fourth-order Runge-Kutta method (BZQ_RK4, the integrator of the
+ * paper's 2-D experiments, Section 5.2), in place on the device array f_hat
+ * (N^2 complex128, FP64 state and stage sums).  Stage buffers belong to the
+ * plan.  dt > 0, n_steps >= 0, otherwise BZQ_EINVAL before any device work. */
+bzq_status bzq_step2d(bzq_plan2d p, double* f_hat, double dt, int n_steps, int method, void* stream);
 bzq_status bzq_plan2d_destroy(bzq_plan2d p);
 
 /* Device bytes held by the plan (tables + scratch), for admission control. */

@@ -86,6 +86,7 @@ def _load():
         "bzq_plan_destroy": ([vp], i),
         "bzq_plan2d_create": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, i, vp], i),
         "bzq_collision2d": ([vp, vp, vp, vp], i),
+        "bzq_step2d": ([vp, vp, d, i, i, vp], i),
         "bzq_plan2d_destroy": ([vp], i),
         "bzq_status_string": ([i], ctypes.c_char_p),
         "bzq_last_error": ([], ctypes.c_char_p),
@@ -108,7 +109,7 @@ EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
             "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error",
             "bzq_plan_set_schedule", "bzq_plan_schedule", "bzq_plan_autotune", "bzq_plan2d_create",
-            "bzq_collision2d", "bzq_plan2d_destroy")
+            "bzq_collision2d", "bzq_step2d", "bzq_plan2d_destroy")
 
 
 def lib():
@@ -316,6 +317,13 @@ class Plan2D:
         qp = self._spectral2d(out, "out")
         _check(_lib.bzq_collision2d(self.handle, fp, qp, _stream(stream)))
         return out
+
+    def step(self, f_hat: torch.Tensor, dt: float, n_steps: int = 1, method: str = "rk4", stream=None):
+        """n_steps of Heun's method ("heun") or classical RK4 ("rk4"), in place."""
+        fp = self._spectral2d(f_hat, "f_hat")
+        m = {"heun": 0, "rk4": 1}[method]
+        _check(_lib.bzq_step2d(self.handle, fp, float(dt), int(n_steps), m, _stream(stream)))
+        return f_hat
 
     def destroy(self):
         if getattr(self, "_h", None) is not None:

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/bzq.h"
+#include "kernels.hpp"
 #include "kernels2d.hpp"
 #include "plan.hpp"
 #include "quadrature.hpp"
@@ -32,10 +33,20 @@ struct bzq_plan2d_s {
   void* fc = nullptr;
   void* fgrid = nullptr;
   double* Qpart = nullptr;
+  double* q1 = nullptr;   // stage results and stage argument of the time steps (N^2 complex each)
+  double* q2 = nullptr;
+  double* fs = nullptr;
   bzq::DeviceArena mem;
 };
 
 using namespace bzq;
+
+namespace {
+hipError_t collide(bzq_plan2d p, const double* f_hat, double* Q_hat, hipStream_t st) {
+  return launch_collision2d(f_hat, Q_hat, p->fc, p->fgrid, p->V, p->ph, p->cp, p->tw, p->Qpart, p->N, p->P,
+                            p->npt, p->S, p->fp32, st);
+}
+}  // namespace
 
 extern "C" {
 
@@ -120,6 +131,9 @@ bzq_status bzq_plan2d_create(bzq_plan2d* out, int N, double L, double R, double 
       (s = p->mem.get(&p->fc, (size_t)n1 * n1 * 2 * esz)) != BZQ_OK ||
       (s = p->mem.get(&p->fgrid, (size_t)P * P * esz)) != BZQ_OK ||
       (s = p->mem.get(&p->Qpart, (size_t)p->S * p->nh * 16)) != BZQ_OK ||
+      (s = p->mem.get(&p->q1, (size_t)N * N * 16)) != BZQ_OK ||
+      (s = p->mem.get(&p->q2, (size_t)N * N * 16)) != BZQ_OK ||
+      (s = p->mem.get(&p->fs, (size_t)N * N * 16)) != BZQ_OK ||
       (s = tmp.get(&d_pd, pd.size() * sizeof(double))) != BZQ_OK ||
       (s = tmp.get(&d_gj, gj.size() * sizeof(double))) != BZQ_OK) {
     delete p;
@@ -146,9 +160,42 @@ bzq_status bzq_plan2d_create(bzq_plan2d* out, int N, double L, double R, double 
 bzq_status bzq_collision2d(bzq_plan2d p, const double* f_hat, double* Q_hat, void* stream) {
   if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
-  hipError_t e = launch_collision2d(f_hat, Q_hat, p->fc, p->fgrid, p->V, p->ph, p->cp, p->tw, p->Qpart, p->N,
-                                    p->P, p->npt, p->S, p->fp32, (hipStream_t)stream);
+  hipError_t e = collide(p, f_hat, Q_hat, (hipStream_t)stream);
   if (e != hipSuccess) return fail(BZQ_EDEVICE, std::string("2-D collision: ") + hipGetErrorString(e));
+  return BZQ_OK;
+}
+
+bzq_status bzq_step2d(bzq_plan2d p, double* f_hat, double dt, int n_steps, int method, void* stream) {
+  if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(BZQ_EINVAL, "dt must be finite and > 0");
+  if (n_steps < 0) return fail(BZQ_EINVAL, "n_steps must be >= 0");
+  if (method != BZQ_HEUN && method != BZQ_RK4) return fail(BZQ_EINVAL, "unknown method");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)p->N * p->N;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
+    if (method == BZQ_HEUN) {
+      // q1 = Q(f), fs = f + dt q1, q2 = Q(fs), f += dt/2 (q1 + q2)
+      if (e == hipSuccess) e = collide(p, f_hat, p->q1, st);
+      if (e == hipSuccess) e = launch_axpy(p->fs, f_hat, dt, p->q1, n, st);
+      if (e == hipSuccess) e = collide(p, p->fs, p->q2, st);
+      if (e == hipSuccess) e = launch_heun(f_hat, p->q1, p->q2, 0.5 * dt, n, st);
+    } else {
+      // classical RK4; q1 = the stage's Q, q2 = the running sum, fs = the stage argument
+      if (e == hipSuccess) e = collide(p, f_hat, p->q1, st);
+      if (e == hipSuccess) e = launch_axpy(p->q2, f_hat, dt / 6.0, p->q1, n, st);
+      if (e == hipSuccess) e = launch_axpy(p->fs, f_hat, 0.5 * dt, p->q1, n, st);
+      if (e == hipSuccess) e = collide(p, p->fs, p->q1, st);
+      if (e == hipSuccess) e = launch_axpy(p->q2, p->q2, dt / 3.0, p->q1, n, st);
+      if (e == hipSuccess) e = launch_axpy(p->fs, f_hat, 0.5 * dt, p->q1, n, st);
+      if (e == hipSuccess) e = collide(p, p->fs, p->q1, st);
+      if (e == hipSuccess) e = launch_axpy(p->q2, p->q2, dt / 3.0, p->q1, n, st);
+      if (e == hipSuccess) e = launch_axpy(p->fs, f_hat, dt, p->q1, n, st);
+      if (e == hipSuccess) e = collide(p, p->fs, p->q1, st);
+      if (e == hipSuccess) e = launch_axpy(f_hat, p->q2, dt / 6.0, p->q1, n, st);
+    }
+  }
+  if (e != hipSuccess) return fail(BZQ_EDEVICE, std::string("2-D step: ") + hipGetErrorString(e));
   return BZQ_OK;
 }
 

@@ -178,3 +178,57 @@ def test_table1_bkw(bzq):
         assert ref[8][name] / 20 < errs[8, name] < 20 * ref[8][name]
         # N = 64: the quadrature error alone, which reproduces the printed row
         assert abs(errs[64, name] / ref[64][name] - 1) < 0.1, (name, errs[64, name], ref[64][name])
+
+
+# ------------------------------------------------------------------ time steps
+@pytest.mark.parametrize("method,dt,n", [("heun", 0.05, 12), ("rk4", 0.1, 8)])
+def test_steps_match_oracle(bzq, method, dt, n):
+    """Heun and classical RK4 (Section 5.2) against the oracle's steps with the
+    2-D direct sum, N = 8, b3, checkpoints after n/2 and n steps."""
+    from oracle.physics import heun_step, rk4_step
+    N, L, R = 8, 8.0, 4.0
+    d = o2.Discretization2D(N, L, R, 0.0, o2.PAPER_KERNELS_2D["b3"], 6, 8)
+    T = o2.weight_table2d(d, o2.mode_vectors2d(N))
+    collide = lambda g: o2.collision_direct2d(g, d, T=T)  # noqa: E731
+    stepper = heun_step if method == "heun" else rk4_step
+    f = workloads.to_spectral_2d(workloads.random_mixture_2d(21, N, L))
+    ref = {0: f}
+    g = f
+    for i in range(1, n + 1):
+        g = stepper(g, None, dt, collide=collide)
+        if i in (n // 2, n):
+            ref[i] = g
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        plan = _plan(bzq, d, prec)
+        fd = _dev(f)
+        plan.step(fd, dt, n // 2, method=method)
+        h = _host(fd)
+        assert _rel(h, ref[n // 2]) < tol, (prec, _rel(h, ref[n // 2]))
+        plan.step(fd, dt, n - n // 2, method=method)
+        h = _host(fd)
+        assert _rel(h, ref[n]) < tol, (prec, _rel(h, ref[n]))
+        assert h[0, 0] == f[0, 0]                 # mass exactly conserved
+        plan.destroy()
+
+
+def test_bkw_evolution_rk4(bzq):
+    """The setup of the paper's 2-D BKW time evolution (RK4, dt = 0.05, N_sigma = 32,
+    R = 6, L = (3 + sqrt 2) R / 4) run from t = 0 to t = 2: the L_inf error of f on
+    the grid against the BKW solution f(K(t)) of eq. KK2 stays at the level of the
+    operator's error (Table 1) times t, far below the change of f."""
+    K = o2.bkw2d_K
+    errs = {}
+    for N in (32, 64):
+        v = workloads.velocity_grid(N, L_BKW)
+        v2 = v[:, None] ** 2 + v[None, :] ** 2
+        f0 = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L_BKW, K(0.0)))
+        plan = bzq.Plan2D(N, L_BKW, R_BKW, 0.0, _kernel("b3"), N, 32, precision="fp64")
+        fd = _dev(f0)
+        plan.step(fd, 0.05, 40, method="rk4")
+        f1 = o2.to_physical2d(_host(fd), L_BKW)
+        plan.destroy()
+        errs[N] = float(np.max(np.abs(f1 - o2.bkw2d_f(v2, K(2.0)))))
+        moved = float(np.max(np.abs(o2.bkw2d_f(v2, K(2.0)) - o2.bkw2d_f(v2, K(0.0)))))
+        print(f"2-D BKW, RK4 to t = 2, N = {N}: L_inf error {errs[N]:.3e}, change of f {moved:.3e}", flush=True)
+        assert errs[N] < 1e-3 * moved
+    assert errs[64] < 1e-7
