@@ -244,6 +244,45 @@ def cpu_fft_baseline(cfg, fhat_np, n_nodes=32, reps=5, seed=0):
                       f"value = sample / (time x nodes)"}
 
 
+def bench_2d(bzq, torch, n_evals=20):
+    """The 2-D operator at Table 1's largest setting (N = N_rho = 64, N_sigma = 32,
+    R = 6, L = (3 + sqrt 2) R / 4, kernel b3 of Section 5.2), BKW input at t = 0:
+    evals/s in both precisions and the L_inf error against the closed-form Q."""
+    import numpy as np
+    import workloads
+    N, R = 64, 6.0
+    L = (3 + math.sqrt(2)) * R / 4
+    K = 0.5
+    f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L, K))
+    fd = torch.from_numpy(f).to("cuda")
+    out = {"workload": "2-D collision N=64^2 N_rho=64 N_sigma=32 (midpoint) R=6 L=6.62 b3, BKW at t=0"}
+    v = workloads.velocity_grid(N, L)
+    v2 = v[:, None] ** 2 + v[None, :] ** 2
+    exact = np.exp(-v2 / (2 * K)) / (2 * math.pi * K) * (1 - K) ** 2 / (4 * K ** 4) * 0.125 * (
+        8 * K * K - 8 * K * v2 + v2 * v2)
+    sgn = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    for prec in ("fp32", "fp64"):
+        plan = bzq.Plan2D(N, L, R, 0.0, (1.0 / (8 * math.pi), 0.0, 0.0), N, 32, precision=prec)
+        q = torch.empty_like(fd)
+        for _ in range(3):
+            plan.collision(fd, q)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n_evals):
+            plan.collision(fd, q)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n_evals
+        qn = q.cpu().numpy()
+        qphys = np.real(np.fft.ifft2(qn * sgn[:, None] * sgn[None, :])) * N * N
+        out[prec] = {"evals_per_s": round(1e3 / ms, 2), "ms_per_eval": round(ms, 4),
+                     "table1_linf_error": float(np.max(np.abs(qphys - exact)))}
+        plan.destroy()
+    out["table1_paper_b3_N64"] = 3.1950e-09
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +291,8 @@ def main():
     ap.add_argument("--no-large", dest="large", action="store_false",
                     help="skip the N=64 workload (timed by default beside the headline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-2d", dest="two_d", action="store_false",
+                    help="skip the 2-D operator at Table 1's N = 64 setting")
     ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
     ap.add_argument("--serve-rates", default="2,20", help="request rates (req/s) of the served form ('': skip)")
     ap.add_argument("--serve-duration", type=float, default=5.0)
@@ -356,6 +397,8 @@ def main():
             torch.cuda.empty_cache()
         large["err_fp32_vs_fp64"] = float(np.linalg.norm(qs["fp32"] - qs["fp64"]) / np.linalg.norm(qs["fp64"]))
         out["large_N64"] = large
+    if args.two_d:
+        out["two_d"] = bench_2d(bzq, torch)
     if args.batch_cells > 0:
         out["batched"] = batch_bench(bzq, torch, args.batch_cells, 2)
         torch.cuda.empty_cache()

@@ -33,6 +33,7 @@ struct bzq_plan2d_s {
   void* fc = nullptr;
   void* fgrid = nullptr;
   double* Qpart = nullptr;
+  double* fin = nullptr;  // 16 chunk sums of the partials
   double* q1 = nullptr;   // stage results and stage argument of the time steps (N^2 complex each)
   double* q2 = nullptr;
   double* fs = nullptr;
@@ -43,8 +44,8 @@ using namespace bzq;
 
 namespace {
 hipError_t collide(bzq_plan2d p, const double* f_hat, double* Q_hat, hipStream_t st) {
-  return launch_collision2d(f_hat, Q_hat, p->fc, p->fgrid, p->V, p->ph, p->cp, p->tw, p->Qpart, p->N, p->P,
-                            p->npt, p->S, p->fp32, st);
+  return launch_collision2d(f_hat, Q_hat, p->fc, p->fgrid, p->V, p->ph, p->cp, p->tw, p->Qpart, p->fin, p->N,
+                            p->P, p->npt, p->S, p->fp32, st);
 }
 }  // namespace
 
@@ -131,6 +132,7 @@ bzq_status bzq_plan2d_create(bzq_plan2d* out, int N, double L, double R, double 
       (s = p->mem.get(&p->fc, (size_t)n1 * n1 * 2 * esz)) != BZQ_OK ||
       (s = p->mem.get(&p->fgrid, (size_t)P * P * esz)) != BZQ_OK ||
       (s = p->mem.get(&p->Qpart, (size_t)p->S * p->nh * 16)) != BZQ_OK ||
+      (s = p->mem.get(&p->fin, (size_t)16 * p->nh * 16)) != BZQ_OK ||
       (s = p->mem.get(&p->q1, (size_t)N * N * 16)) != BZQ_OK ||
       (s = p->mem.get(&p->q2, (size_t)N * N * 16)) != BZQ_OK ||
       (s = p->mem.get(&p->fs, (size_t)N * N * 16)) != BZQ_OK ||
