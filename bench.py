@@ -283,6 +283,46 @@ def bench_2d(bzq, torch, n_evals=20):
     return out
 
 
+def bench_otf(bzq, torch, cfg, fhat_np, q_ref, n_evals=3):
+    """Weights on the fly at the N = 64 workload: evals/s, plan bytes and plan
+    creation time against the table plan, and the difference of the results."""
+    import numpy as np
+    fd = torch.from_numpy(fhat_np).to("cuda")
+    out = {}
+    for prec in ("fp32", "fp64"):
+        row = {}
+        for mode in ("table", "otf"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p = bzq.Plan(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"], cfg["N_rho"], cfg["M"],
+                         precision=prec, weights=mode)
+            torch.cuda.synchronize()
+            t_create = time.perf_counter() - t0
+            q = torch.empty_like(fd)
+            p.collision(fd, q)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n_evals):
+                p.collision(fd, q)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / n_evals
+            row[mode] = {"ms_per_eval": round(ms, 3), "plan_create_s": round(t_create, 3),
+                         "plan_device_MB": round(p.device_bytes() / 2 ** 20, 1)}
+            if mode == "otf":
+                qn = q.cpu().numpy()
+                row["otf_vs_table_rel"] = float(np.linalg.norm(qn - qt) / np.linalg.norm(qt))
+            else:
+                qt = q.cpu().numpy()
+            p.destroy()
+            del p, q
+            torch.cuda.empty_cache()
+        out[prec] = row
+    out["workload"] = "N=64^3 M=302 N_rho=64, the large workload"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,6 +331,8 @@ def main():
     ap.add_argument("--no-large", dest="large", action="store_false",
                     help="skip the N=64 workload (timed by default beside the headline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-otf", dest="otf", action="store_false",
+                    help="skip the plans with weights on the fly (beside the N = 64 workload)")
     ap.add_argument("--no-2d", dest="two_d", action="store_false",
                     help="skip the 2-D operator at Table 1's N = 64 setting")
     ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
@@ -397,6 +439,8 @@ def main():
             torch.cuda.empty_cache()
         large["err_fp32_vs_fp64"] = float(np.linalg.norm(qs["fp32"] - qs["fp64"]) / np.linalg.norm(qs["fp64"]))
         out["large_N64"] = large
+        if args.otf:
+            out["weights_on_the_fly"] = bench_otf(bzq, torch, cl, fl, qs["fp64"])
     if args.two_d:
         out["two_d"] = bench_2d(bzq, torch)
     if args.batch_cells > 0:

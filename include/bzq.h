@@ -99,6 +99,21 @@ bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, dou
                                    double b_c, double b_s, double b_r, int n_jacobi,
                                    int N_rho, int M, int precision, void* stream);
 
+/* The same plan with its weights evaluated on the fly (beyond the paper):
+ * no table of J N^3 / 2 weights is stored or built.  Before the last stage of
+ * each chunk of pairs, a kernel evaluates the weights of that chunk from the
+ * Funk-Hecke series of the exact weight of eq. FF,
+ *   Re(e^{-ix} F) = sum_{l even} (2l+1) (-1)^{l/2} mu_l j_l(a|k|) P_l(k.sigma/|k|),
+ *   mu_l = 2 pi \int b(u) (P_l(u) - 1) du  (finite for every s < 1),
+ * truncated where the terms fall below 1e-13 of the sum (at most 126 even
+ * terms: a |k| <= ~80).  The plan then holds N_rho x terms x 3(N/2-1)^2
+ * coefficients (70 MB at N = 64, N_rho = 64) instead of the weight table
+ * (4.8 GB in FP64), and its workspace one chunk of weights.  Same arguments
+ * and limits as bzq_plan_create_general (n_jacobi is not used); every other
+ * call accepts the plan unchanged.  BZQ_EUNSUPPORTED if a |k| is too large. */
+bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, double b_c,
+                               double b_s, double b_r, int N_rho, int M, int precision, void* stream);
+
 /* Q_hat = Q(f_hat, f_hat) (eq. realQ).  f_hat and Q_hat: device, complex128
  * N^3 (layout above); they must not overlap.  Q_hat[0] is exactly 0
  * (Remark 4.1).  A non-finite f_hat gives a non-finite Q_hat. */

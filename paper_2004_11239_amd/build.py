@@ -33,6 +33,7 @@ SOURCES = [
     ("batch.cpp", False),
     ("server.cpp", False),
     ("quadrature.cpp", False),
+    ("funk_hecke.cpp", False),
 ]
 
 

@@ -48,6 +48,7 @@ def _load():
     sigs = {
         "bzq_plan_create": ([ctypes.POINTER(vp), i, d, d, d, d, i, i, i, vp], i),
         "bzq_plan_create_general": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, i, vp], i),
+        "bzq_plan_create_otf": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, vp], i),
         "bzq_collision": ([vp, vp, vp, vp], i),
         "bzq_step": ([vp, vp, d, i, vp], i),
         "bzq_step_rk4": ([vp, vp, d, i, vp], i),
@@ -104,7 +105,7 @@ EXPORTED_EXTRA = ("bzq_workspace_create", "bzq_collision_ws", "bzq_step_ws", "bz
                   "bzq_batch_groups", "bzq_batch_group_info", "bzq_batch_device_bytes",
                   "bzq_batch_destroy", "bzq_server_create", "bzq_server_submit", "bzq_server_poll",
                   "bzq_server_wait", "bzq_server_stats", "bzq_server_destroy", "bzq_plan_bytes_estimate")
-EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_collision", "bzq_step", "bzq_step_rk4", "bzq_moments",
+EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_plan_create_otf", "bzq_collision", "bzq_step", "bzq_step_rk4", "bzq_moments",
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
             "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error",
@@ -140,15 +141,27 @@ class Plan:
 
     def __init__(self, N: int, L: float, R: float, gamma: float, s: float, N_rho: int, M: int,
                  precision="fp64", kernel: Optional[Sequence[float]] = None, n_jacobi: int = 64,
-                 stream=None):
+                 stream=None, weights: str = "table"):
         """kernel=None: b = c_s sin^{-(2+2s)}(th/2), c_s = (1-s)(2-s)/(24 pi).
-        kernel=(c, s_b, r): b = c t^{-1-s_b} (1-t)^{-r}, t = sin^2(th/2) (then `s` is ignored)."""
+        kernel=(c, s_b, r): b = c t^{-1-s_b} (1-t)^{-r}, t = sin^2(th/2) (then `s` is ignored).
+        weights="table" stores the weights at creation; "otf" evaluates them per
+        chunk of pairs from their series (bzq_plan_create_otf)."""
         self.N, self.L, self.R, self.gamma = int(N), float(L), float(R), float(gamma)
         self.N_rho, self.M = int(N_rho), int(M)
         self.precision = _PREC[precision]
+        if weights not in ("table", "otf"):
+            raise ValueError("weights must be 'table' or 'otf'")
+        self.weights_mode = weights
         h = ctypes.c_void_p()
         st = _stream(stream)
-        if kernel is None:
+        if weights == "otf":
+            if kernel is None:
+                kernel = ((1 - s) * (2 - s) / (24 * math.pi), float(s), 0.0)
+            self.kernel = tuple(float(x) for x in kernel)
+            c, sb, r = self.kernel
+            code = _lib.bzq_plan_create_otf(ctypes.byref(h), self.N, self.L, self.R, self.gamma, c, sb, r,
+                                            self.N_rho, self.M, self.precision, st)
+        elif kernel is None:
             self.kernel = ((1 - s) * (2 - s) / (24 * math.pi), float(s), 0.0)
             code = _lib.bzq_plan_create(ctypes.byref(h), self.N, self.L, self.R, self.gamma, float(s),
                                         self.N_rho, self.M, self.precision, st)

@@ -41,7 +41,7 @@ struct Group {
 std::string tune_key(const Plan& p) {
   std::ostringstream k;
   k << "N=" << p.N << " P=" << p.P << " prec=" << (p.fp32 ? "fp32" : "fp64") << " npairs=" << p.npairs
-    << " G=" << p.G << " S=" << p.S << " sched=" << p.var[0] << p.var[1] << p.var[2];
+    << " G=" << p.G << " S=" << p.S << " sched=" << p.var[0] << p.var[1] << p.var[2] << (p.otf ? " otf" : "");
   return k.str();
 }
 

@@ -31,6 +31,7 @@
 
 #include <sys/stat.h>
 
+#include "funk_hecke.hpp"
 #include "plan.hpp"
 #include "quadrature.hpp"
 
@@ -74,7 +75,8 @@ Plan::~Plan() {
 size_t Plan::workspace_bytes_per_cell() const {
   const size_t N3 = (size_t)N * N * N;
   return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * nn * 2 * esz +
-         (size_t)G * P * 2 * nhp * 2 * esz + (size_t)S_cap * nh * n1 * 16 + 3 * N3 * 16;
+         (size_t)G * P * 2 * nhp * 2 * esz + (size_t)S_cap * nh * n1 * 16 + 3 * N3 * 16 +
+         (otf ? (size_t)2 * Gw * nh * n1 * esz : 0);
 }
 
 bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
@@ -97,6 +99,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   if ((s = w.arena.get(&w.q1, cells * N3 * 16)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.q2, cells * N3 * 16)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.fs, cells * N3 * 16)) != BZQ_OK) return s;
+  if (p.otf && (s = w.arena.get(&w.Vc, (size_t)2 * p.Gw * p.nh * p.n1 * p.esz)) != BZQ_OK) return s;
   return BZQ_OK;
 }
 
@@ -159,6 +162,12 @@ void set_chunking(Plan& p) {
   const char* env = std::getenv("BZQ_CHUNK_MB");
   const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
   p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
+  // weights on the fly: pair-twos per generated block of weights (below
+  // BZQ_OTF_MB, default 128 MiB)
+  const char* envw = std::getenv("BZQ_OTF_MB");
+  const size_t capw = (envw && std::atoll(envw) > 0 ? (size_t)std::atoll(envw) : 128ull) << 20;
+  const size_t per_w = (size_t)2 * p.nh * p.n1 * p.esz;
+  p.Gw = p.otf ? (int)std::max<size_t>(1, std::min<size_t>((size_t)p.G, capw / per_w)) : 0;
   p.S = zfwd_splits(p, effective_variant(p, 2), p.s_target);
   p.S_cap = p.S;
   for (int v = 1; v <= 2; ++v)
@@ -188,6 +197,71 @@ size_t plan_footprint(int N, int N_rho, int M, int precision) {
 }
 
 namespace {
+
+// Tables of a plan whose weights are evaluated on the fly (funk_hecke.hpp):
+// the series coefficients per radial node and |k|^2, and the pair
+// directions and scales.
+bzq_status build_series(Plan* p, const std::vector<double>& rho, int Mh, int nreal, hipStream_t st) {
+  const int h = p->N / 2;
+  p->Mh = Mh;
+  p->nreal = nreal;
+  p->ncoef = 3 * (h - 1) * (h - 1) + 1;
+  std::vector<int> terms(p->N_rho);
+  int need = 1;
+  for (int ip = 0; ip < p->N_rho; ++ip) {
+    const double a = (double)(kPi * rho[ip] / (2.0L * p->L));
+    terms[ip] = fh_lmax(a * std::sqrt((double)(p->ncoef - 1))) / 2 + 1;
+    need = std::max(need, terms[ip]);
+  }
+  if (need > 64)
+    return fail(BZQ_EUNSUPPORTED, "weights on the fly: a |k| too large for the series (at most 64 even terms)");
+  p->mt = (need + 7) / 8 * 8;   // coefficient slots: the kernel unrolls in multiples of 8 terms
+  std::vector<long double> mu, Ml;
+  if (!fh_moments(2 * (need - 1), p->bc, p->bs, p->br, mu)) return fail(BZQ_EINVAL, "Gauss-Jacobi rule failed");
+  fh_cheb_matrix(need, Ml);
+  std::vector<double> M(Ml.begin(), Ml.end());
+  // coef[p][n][k]: Chebyshev coefficients in u = 2t^2 - 1 of the series for
+  // radial node p and |k|^2 = n
+  std::vector<double> coef((size_t)p->N_rho * p->ncoef * p->mt, 0.0);
+  std::vector<long double> jl;
+  std::vector<double> c(need);
+  for (int ip = 0; ip < p->N_rho; ++ip) {
+    const long double a = kPi * rho[ip] / (2.0L * p->L);
+    const int tp = terms[ip];
+    for (int n = 0; n < p->ncoef; ++n) {
+      fh_sph_bessel(2 * (tp - 1), a * sqrtl((long double)n), jl);
+      for (int m = 0; m < tp; ++m) {
+        const int l = 2 * m;
+        c[m] = (double)((2 * l + 1) * ((m & 1) ? -1.0L : 1.0L) * mu[m] * jl[l]);
+      }
+      double* d = &coef[((size_t)ip * p->ncoef + n) * p->mt];
+      for (int k = 0; k < tp; ++k) {
+        double acc = 0.0;
+        for (int m = k; m < tp; ++m) acc += M[(size_t)k * need + m] * c[m];
+        d[k] = acc;
+      }
+    }
+  }
+  std::vector<double> pdv((size_t)p->npairs * 4, 0.0);
+  const long double P3 = (long double)p->P * p->P * p->P;
+  for (int j = 0; j < nreal; ++j) {
+    const double* ho = &p->pair_host[6 * j];
+    pdv[4 * j] = ho[1];
+    pdv[4 * j + 1] = ho[2];
+    pdv[4 * j + 2] = ho[3];
+    pdv[4 * j + 3] = (double)(2.0L * ho[4] / P3);
+  }
+  bzq_status s;
+  if ((s = p->tables.get(&p->coef, coef.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->tables.get(&p->pdv, pdv.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->tables.get(&p->terms, terms.size() * sizeof(int))) != BZQ_OK) return s;
+  BZQ_HIP_TRY(hipMemcpyAsync(p->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(p->pdv, pdv.data(), pdv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(p->terms, terms.data(), terms.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  // the host vectors go out of scope: wait for the copies
+  BZQ_HIP_TRY(hipStreamSynchronize(st));
+  return BZQ_OK;
+}
 
 bzq_status build_plan(Plan* p, hipStream_t st) {
   const int N = p->N, P = p->P, nn = p->nn, nh = p->nh;
@@ -242,7 +316,11 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
   // -- tables
   bzq_status s;
   const size_t vcount = (size_t)p->npairs * nh * p->n1;
-  if ((s = p->tables.get(&p->V, vcount * p->esz)) != BZQ_OK) return s;
+  if (p->otf) {
+    if ((s = build_series(p, rho, Mh, nreal, st)) != BZQ_OK) return s;
+  } else if ((s = p->tables.get(&p->V, vcount * p->esz)) != BZQ_OK) {
+    return s;
+  }
   if ((s = p->tables.get(&p->ph, ph.size() * sizeof(double))) != BZQ_OK) return s;
   if ((s = p->tables.get(&p->cp, cp.size() * sizeof(double))) != BZQ_OK) return s;
   if ((s = p->tables.get(&p->tw_pad, (size_t)P * 2 * p->esz)) != BZQ_OK) return s;
@@ -283,7 +361,7 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
     BZQ_HIP_TRY(hipMemcpyAsync(p->tw_pad, twpf.data(), twpf.size() * sizeof(float), hipMemcpyHostToDevice, st));
   else
     BZQ_HIP_TRY(hipMemcpyAsync(p->tw_pad, twp.data(), twp.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  BZQ_HIP_TRY(launch_table(p->V, d_pd, d_gj, p->nj, N, p->npairs, p->fp32, st));
+  if (!p->otf) BZQ_HIP_TRY(launch_table(p->V, d_pd, d_gj, p->nj, N, p->npairs, p->fp32, st));
   BZQ_HIP_TRY(hipStreamSynchronize(st));
   return BZQ_OK;
 }
@@ -330,8 +408,21 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
     TIMED(ST_ZINV, launch_zinv(w.fc, p.ph, w.A, p.tw_pad, g, 2 * c0, n, ZINV_PAIRS, p.fp32, cs, st, p.var[0]));
     TIMED(ST_PLANE, launch_plane(w.A, w.B, w.fgrid, nullptr, p.tw_pad, g, n, PLANE_PRODUCT, p.fp32, cs, st,
                                  p.var[1]));
-    TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, p.S, p.fp32, cs, st,
-                               p.var[2]));
+    if (p.otf) {
+      // weights of Gw pair-twos at a time, then the last stage over those pair-twos
+      for (int w0 = 0; w0 < n; w0 += p.Gw) {
+        const int m = std::min(p.Gw, n - w0);
+        const int pair0 = 2 * (c0 + w0);
+        const void* Bw = (const char*)w.B + (size_t)w0 * p.P * 2 * p.nhp * 2 * p.esz;
+        TIMED(ST_ZFWD, launch_wgen(w.Vc, p.coef, p.pdv, p.terms, p.mt, p.N, p.Mh, p.nreal, pair0, 2 * m,
+                                   p.ncoef, p.fp32, st));
+        TIMED(ST_ZFWD, launch_zfwd(Bw, w.Vc, p.ph, p.cp, w.Qpart, p.tw_pad, g, pair0, m, p.S, p.fp32, cs, st,
+                                   p.var[2], pair0));
+      }
+    } else {
+      TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, p.S, p.fp32, cs, st,
+                                 p.var[2]));
+    }
   }
   TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, p.S, st));
   return BZQ_OK;
@@ -386,7 +477,7 @@ bzq_status enqueue_step_rk4(Plan& p, Workspace& w, const PtrPack& f, int cells, 
 }
 
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
-                       double br, int nj, int N_rho, int M, int precision, void* stream) {
+                       double br, int nj, int N_rho, int M, int precision, void* stream, bool otf) {
   if (!out) return fail(BZQ_EINVAL, "out is NULL");
   *out = nullptr;
   if (N < 8 || (N & 1)) return fail(BZQ_EINVAL, "N must be even and >= 8");
@@ -412,6 +503,7 @@ bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, d
   p->bc = bc; p->bs = bs; p->br = br; p->nj = nj;
   p->N_rho = N_rho; p->M = M;
   p->fp32 = precision == BZQ_FP32_ACC64;
+  p->otf = otf;
   bzq_status s = build_plan(p, (hipStream_t)stream);
   if (s != BZQ_OK) {
     delete p;
@@ -460,6 +552,11 @@ bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, dou
   return create_plan(out, N, L, R, gamma, b_c, b_s, b_r, n_jacobi, N_rho, M, precision, stream);
 }
 
+bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, double b_c, double b_s,
+                               double b_r, int N_rho, int M, int precision, void* stream) {
+  return create_plan(out, N, L, R, gamma, b_c, b_s, b_r, 64, N_rho, M, precision, stream, true);
+}
+
 bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream) {
   if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
@@ -490,7 +587,7 @@ void decode_schedule(Plan& p, int code) {
 std::string schedule_key(const Plan& p) {
   std::ostringstream k;
   k << "schedule N=" << p.N << " P=" << p.P << " prec=" << (p.fp32 ? "fp32" : "fp64")
-    << " npairs=" << p.npairs << " G=" << p.G;
+    << " npairs=" << p.npairs << " G=" << p.G << (p.otf ? " otf" : "");
   return k.str();
 }
 
@@ -703,7 +800,8 @@ bzq_status bzq_plan_info(bzq_plan p, double* out) {
   out[4] = p->S;
   out[5] = p->fp32 ? BZQ_FP32_ACC64 : BZQ_FP64;
   out[6] = p->nj;
-  out[7] = (double)((size_t)p->npairs * p->nh * p->n1 * p->esz);
+  out[7] = p->otf ? (double)((size_t)p->N_rho * p->mt * p->ncoef * sizeof(double))
+                  : (double)((size_t)p->npairs * p->nh * p->n1 * p->esz);
   return BZQ_OK;
 }
 
@@ -718,7 +816,20 @@ bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
   if (pair < 0 || pair >= p->npairs) return fail(BZQ_EINVAL, "pair index out of range");
   // stored as [i3][c]; returned as [c][i3]
   const size_t cnt = (size_t)p->nh * p->n1;
-  const char* src = (const char*)p->V + (size_t)pair * cnt * p->esz;
+  const char* src = nullptr;
+  DeviceArena scratch;
+  if (!p->otf) {
+    src = (const char*)p->V + (size_t)pair * cnt * p->esz;
+  } else {
+    // evaluate this pair's weights with the kernel the evaluations use
+    void* d = nullptr;
+    bzq_status s = scratch.get(&d, cnt * p->esz);
+    if (s != BZQ_OK) return s;
+    BZQ_HIP_TRY(launch_wgen(d, p->coef, p->pdv, p->terms, p->mt, p->N, p->Mh, p->nreal, pair, 1, p->ncoef,
+                            p->fp32, nullptr));
+    BZQ_HIP_TRY(hipStreamSynchronize(nullptr));
+    src = (const char*)d;
+  }
   std::vector<double> tmp(cnt);
   if (p->fp32) {
     std::vector<float> tf(cnt);

@@ -24,7 +24,10 @@
 // holds a whole length-P pencil, twiddles are compile-time constants and the
 // zero padding folds away) used wherever a pencil fits the register file, and
 // an LDS Stockham one used otherwise (FP64 at P >= 72) and by the last stage.
+#include <algorithm>
+
 #include "fft.hpp"
+#include "funk_hecke.hpp"
 #include "kernels.hpp"
 
 namespace bzq {
@@ -222,7 +225,7 @@ template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const T* __restrict__ V,
                                              const double2* __restrict__ ph, const double* __restrict__ cp,
                                              double2* __restrict__ Qpart, const cx<T>* __restrict__ twg,
-                                             int N, int pair0, int npt, int S, CellStrides cs) {
+                                             int N, int pair0, int vpair0, int npt, int S, CellStrides cs) {
   constexpr int LD = P + 1;
   B += blockIdx.z * cs.b;
   Qpart += blockIdx.z * cs.qp;
@@ -271,8 +274,8 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
         const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
         const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
         const size_t vi = (size_t)i3 * nh + c;
-        const double vA = cA * (double)V[(size_t)jA * nh * n1 + vi];
-        const double vB = cB * (double)V[(size_t)jB * nh * n1 + vi];
+        const double vA = cA * (double)V[(size_t)(jA - vpair0) * nh * n1 + vi];
+        const double vB = cB * (double)V[(size_t)(jB - vpair0) * nh * n1 + vi];
         const cx<double> eA = cmul(cmul(d2c(phA[k1]), d2c(phA[PL + k2])), d2c(phA[2 * PL + k3]));
         const cx<double> eB = cmul(cmul(d2c(phB[k1]), d2c(phB[PL + k2])), d2c(phB[2 * PL + k3]));
         const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
@@ -715,7 +718,8 @@ __device__ __forceinline__ void zfwd_produce(const cx<T>* __restrict__ Bin, cx<T
 template <typename T, int N, int P>
 __global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
     const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
-    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int npt, int S, CellStrides cs) {
+    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
+    CellStrides cs) {
   using C = ZfwdPipeCfg<P>;
   constexpr int TQ = C::TQ, PW = C::PW, NC = 64 * C::CW;
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
@@ -805,7 +809,7 @@ __global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
       if (i < nmine) {
         // weights of the pair-two the producers are transforming now
         const int jA = pair0 + 2 * (s + i * S);
-        const T* VA = V + (size_t)jA * nh * n1;
+        const T* VA = V + (size_t)(jA - vpair0) * nh * n1;
         const T* VB = VA + (size_t)nh * n1;
 #pragma unroll
         for (int bb = 0; bb < OPT; ++bb) {
@@ -851,7 +855,8 @@ struct ZfwdCfg {
 template <typename T, int N, int P>
 __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
     const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
-    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int npt, int S, CellStrides cs) {
+    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
+    CellStrides cs) {
   using C = ZfwdCfg<T, P>;
   B += blockIdx.z * cs.b;
   Qpart += blockIdx.z * cs.qp;
@@ -923,8 +928,8 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
             const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
             const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
             const size_t vi = (size_t)i3 * nh + c;
-            const double vA = CPV[pp][0] * (double)V[(size_t)jA * nh * n1 + vi];
-            const double vB = CPV[pp][1] * (double)V[(size_t)(jA + 1) * nh * n1 + vi];
+            const double vA = CPV[pp][0] * (double)V[(size_t)(jA - vpair0) * nh * n1 + vi];
+            const double vB = CPV[pp][1] * (double)V[(size_t)(jA + 1 - vpair0) * nh * n1 + vi];
             const cx<double> eA = cmul(d2c(E12[pp][0][qq]), d2c(E3[pp][0][i3]));
             const cx<double> eB = cmul(d2c(E12[pp][1][qq]), d2c(E3[pp][1][i3]));
             const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
@@ -1073,6 +1078,98 @@ __global__ void k_table(TV* __restrict__ V, const double* __restrict__ pd, const
       }
     }
     V[e] = (TV)(scale * W);
+  }
+}
+
+// ------------------------------------------------- weights on the fly
+// V = 2 w_sigma Re(e^{-ix} F) / P^3 from the series over even l of
+// (2l+1) (-1)^{l/2} mu_l j_l(a |k|) P_l(t), t = k.sigma / |k|, rewritten on the
+// host as a Chebyshev series sum_k d_k T_k(u) in u = 2 t^2 - 1 and summed by
+// Clenshaw's rule (b_k = d_k + 2u b_{k+1} - b_{k+2}: one subtraction and one
+// FMA per term, no per-term constants).  One thread per mode (i3, c) holds the
+// d_k of its |k|^2 in registers over the run of pairs that share a radial
+// node, and advances PB pairs together; the term count, rounded up to a
+// multiple of 8, selects a fully unrolled body (no per-term branches).
+// blockIdx.y splits the pair range.
+// Pairs jb .. jend-1 of one radial node, MTB Chebyshev terms (the node's
+// terms rounded up to a multiple of 8; the extra coefficients are 0).
+template <typename T, int PB, int MTB>
+__device__ __forceinline__ void wgen_run(T* __restrict__ Vc, const double4* __restrict__ cq,
+                                         const double4* __restrict__ pdv, int jb, int jend, int j0, int per, int e,
+                                         int k1, int k2, int k3, double rinv) {
+  double d[MTB];
+#pragma unroll
+  for (int g = 0; g < MTB / 4; ++g) {
+    const double4 v = cq[g];
+    d[4 * g] = v.x;
+    d[4 * g + 1] = v.y;
+    d[4 * g + 2] = v.z;
+    d[4 * g + 3] = v.w;
+  }
+  for (int jg = jb; jg < jend; jg += PB) {
+    double u2[PB], b1[PB], b2[PB];
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const double4 v = pdv[min(jg + q, jend - 1)];
+      const double t = ((double)k1 * v.x + (double)k2 * v.y + (double)k3 * v.z) * rinv;
+      u2[q] = 4.0 * t * t - 2.0;          // 2u
+      b1[q] = 0.0;
+      b2[q] = 0.0;
+    }
+#pragma unroll
+    for (int k = MTB - 1; k >= 1; --k) {
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        const double b0 = fma(u2[q], b1[q], d[k] - b2[q]);
+        b2[q] = b1[q];
+        b1[q] = b0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q)
+      if (jg + q < jend)
+        Vc[(size_t)(jg + q - j0) * per + e] = (T)(pdv[jg + q].w * fma(0.5 * u2[q], b1[q], d[0] - b2[q]));
+  }
+}
+
+template <typename T, int PB>
+__global__ __launch_bounds__(256) void k_wgen(T* __restrict__ Vc, const double* __restrict__ coef,
+                                              const double4* __restrict__ pdv, const int* __restrict__ terms,
+                                              int mt, int N, int Mh, int nreal, int j0, int nj, int ncoef) {
+  const int n1 = N - 1, h = N / 2, nh = (n1 * n1 + 1) / 2;
+  const int per = nh * n1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= per) return;
+  const int i3 = e / nh, c = e - i3 * nh;
+  const int i2 = c / n1, i1 = c - i2 * n1;
+  const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
+  const int n = k1 * k1 + k2 * k2 + k3 * k3;
+  const double rinv = n > 0 ? 1.0 / sqrt((double)n) : 0.0;
+  // the pair loop is uniform over the wave (k = 0 needs no branch: its
+  // coefficients are all zero, so its weights come out exactly 0)
+  const int chunk = (nj + gridDim.y - 1) / gridDim.y;
+  int j = j0 + blockIdx.y * chunk;
+  const int j1 = min(j0 + nj, j + chunk);
+  while (j < j1) {
+    const int p = __builtin_amdgcn_readfirstlane(j / Mh);
+    const int jend = __builtin_amdgcn_readfirstlane(min(j1, (p + 1) * Mh));
+    if (j >= nreal) {
+      for (; j < jend; ++j) Vc[(size_t)(j - j0) * per + e] = T(0);
+      continue;
+    }
+    const int b8 = __builtin_amdgcn_readfirstlane((terms[p] + 7) >> 3);
+    const double4* cq = (const double4*)(coef + ((size_t)p * ncoef + n) * mt);
+    switch (b8) {
+      case 1: wgen_run<T, PB, 8>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 2: wgen_run<T, PB, 16>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 3: wgen_run<T, PB, 24>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 4: wgen_run<T, PB, 32>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 5: wgen_run<T, PB, 40>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 6: wgen_run<T, PB, 48>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 7: wgen_run<T, PB, 56>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      default: wgen_run<T, PB, 64>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+    }
+    j = jend;
   }
 }
 
@@ -1253,8 +1350,8 @@ hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, con
 
 template <typename T, int P>
 hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
-                  const void* tw, int N, int pair0, int npt, int S, int variant, const CellStrides& cs,
-                  hipStream_t st) {
+                  const void* tw, int N, int pair0, int vpair0, int npt, int S, int variant,
+                  const CellStrides& cs, hipStream_t st) {
   const int v = variant ? variant : defaultVariant<T, P>(2);
   if constexpr (hasTwo<P>())
     if (v == 2) {
@@ -1263,7 +1360,7 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
       constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
       dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
       hipLaunchKernelGGL((k_zfwd_pipe<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
-                         (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S, cs);
+                         (const double2*)ph, cp, (double2*)Qpart, pair0, vpair0, npt, S, cs);
       return hipGetLastError();
     }
   if constexpr (RegFit<T, P>::value && isPad<P>()) {
@@ -1272,14 +1369,14 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
     constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
     dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
     hipLaunchKernelGGL((k_zfwd_reg<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
-                       (const double2*)ph, cp, (double2*)Qpart, pair0, npt, S, cs);
+                       (const double2*)ph, cp, (double2*)Qpart, pair0, vpair0, npt, S, cs);
     return hipGetLastError();
   }
   const int nn = (N - 1) * (N - 1), nh = (nn + 1) / 2;
   dim3 grid((nh + K3_TQ - 1) / K3_TQ, S, cs.cells);
   hipLaunchKernelGGL((k_zfwd<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)B,
                      (const T*)V, (const double2*)ph, cp, (double2*)Qpart, (const cx<T>*)tw, N, pair0,
-                     npt, S, cs);
+                     vpair0, npt, S, cs);
   return hipGetLastError();
 }
 
@@ -1324,11 +1421,11 @@ hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout
 
 hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
                        const void* tw, Geometry g, int pair0, int npt, int S, bool fp32,
-                       const CellStrides& cs, hipStream_t st, int variant) {
-#define CASE(PP)                                                                                     \
-  case PP:                                                                                           \
-    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, variant, cs, st)   \
-                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, npt, S, variant, cs, st);
+                       const CellStrides& cs, hipStream_t st, int variant, int vpair0) {
+#define CASE(PP)                                                                                      \
+  case PP:                                                                                            \
+    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, variant, cs, st) \
+                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, variant, cs, st);
   switch (g.P) { BZQ_PAD_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
@@ -1380,6 +1477,23 @@ hipError_t launch_table(void* V, const double* pd, const double* gj, int nj, int
     hipLaunchKernelGGL(k_table<float>, dim3(g), dim3(256), 0, st, (float*)V, pd, gj, nj, N, npairs);
   else
     hipLaunchKernelGGL(k_table<double>, dim3(g), dim3(256), 0, st, (double*)V, pd, gj, nj, N, npairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgen(void* Vc, const double* coef, const double* pdv, const int* terms, int mt, int N, int Mh,
+                       int nreal, int j0, int nj, int ncoef, bool fp32, hipStream_t st) {
+  if (mt < 8 || mt > 64 || (mt & 7)) return hipErrorInvalidValue;
+  const int n1 = N - 1, per = ((n1 * n1 + 1) / 2) * n1;
+  const int bx = (per + 255) / 256;
+  // about 2048 workgroups, each over at least 16 pairs
+  const int by = std::max(1, std::min((2048 + bx - 1) / bx, nj / 16));
+  const dim3 grid(bx, by);
+  if (fp32)
+    hipLaunchKernelGGL((k_wgen<float, 4>), grid, dim3(256), 0, st, (float*)Vc, coef, (const double4*)pdv, terms,
+                       mt, N, Mh, nreal, j0, nj, ncoef);
+  else
+    hipLaunchKernelGGL((k_wgen<double, 4>), grid, dim3(256), 0, st, (double*)Vc, coef, (const double4*)pdv, terms,
+                       mt, N, Mh, nreal, j0, nj, ncoef);
   return hipGetLastError();
 }
 

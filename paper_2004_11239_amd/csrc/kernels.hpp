@@ -52,9 +52,21 @@ hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout
 
 // Step 3: forward along axis 3, split the two packed pairs, apply the stored
 // weights and the phase e^{i a k.sigma}, accumulate in FP64 into Qpart[s].
+// The weight of pair j is row j - vpair0 of V (0 for a plan-wide table, the
+// chunk's first pair for weights generated per chunk).
 hipError_t launch_zfwd(const void* B, const void* V, const double* phase, const double* cp,
                        double* Qpart, const void* tw, Geometry g, int pair0, int npt, int S,
-                       bool fp32, const CellStrides& cs, hipStream_t st, int variant = 0);
+                       bool fp32, const CellStrides& cs, hipStream_t st, int variant = 0, int vpair0 = 0);
+
+// Weights of pairs j0 .. j0+nj-1 into Vc[j - j0][n1][nh] (compute precision)
+// from the series of the angular weight in Chebyshev form:
+// Re(e^{-ix} F) = sum_k coef[p][n][k] T_k(2 t^2 - 1), t = k.sigma/|k|, for
+// radial node p and n = |k|^2 < ncoef (k < terms[p], zero above);
+// pdv[j] = {sigma_x, sigma_y, sigma_z, 2 w_sigma / P^3} (0 for the padding
+// pair).  mt (coefficient slots) is a multiple of 8, at most 64, and at
+// least every terms[p] rounded up to a multiple of 8.
+hipError_t launch_wgen(void* Vc, const double* coef, const double* pdv, const int* terms, int mt, int N, int Mh,
+                       int nreal, int j0, int nj, int ncoef, bool fp32, hipStream_t st);
 
 // Kernel variants of the stages {0 z-inverse, 1 plane, 2 z-forward}: bit v of
 // stage_variants is set when variant v runs for padded length P (1 = one whole

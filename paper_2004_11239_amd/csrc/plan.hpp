@@ -53,6 +53,7 @@ struct Workspace {
   double* q1 = nullptr;      // cells x N^3 complex128 (Heun stages)
   double* q2 = nullptr;
   double* fs = nullptr;
+  void* Vc = nullptr;        // weights of one chunk's pairs (plans with weights on the fly)
   DeviceArena arena;
 };
 
@@ -72,8 +73,19 @@ struct Plan {
   int s_target = 1024;
   size_t esz = 0;   // bytes per real element (4 or 8)
   std::vector<double> pair_host;  // [npairs][6] for introspection
+  // weights on the fly: no table V; per chunk, k_wgen evaluates the series
+  // of the angular weight (funk_hecke.hpp) into the workspace
+  bool otf = false;
+  int mt = 0;                   // coefficient slots per (radial node, |k|^2): multiple of 8, <= 64
+  int Gw = 0;                   // pair-twos per block of generated weights
+  int Mh = 0;                   // pairs per radial node
+  int nreal = 0;                // pairs before the zero-weight pad
+  int ncoef = 0;                // |k|^2 values, 0 .. 3 (N/2-1)^2
+  double* coef = nullptr;       // [N_rho][ncoef][mt]
+  double* pdv = nullptr;        // [npairs][4] sigma, 2 w_sigma / P^3
+  int* terms = nullptr;         // [N_rho] terms used per radial node
   // tables (read-only after creation)
-  void* V = nullptr;            // [npairs][n1][nh] real weights
+  void* V = nullptr;            // [npairs][n1][nh] real weights (table plans)
   double* ph = nullptr;         // [npairs][3][2N-3] complex128 phases
   double* cp = nullptr;         // [npairs] w_rho rho^{2+gamma}
   void* tw_pad = nullptr;       // P twiddles (LDS kernels), compute precision
@@ -105,7 +117,7 @@ void tune_cache_write(const std::map<std::string, int>& m);
 void set_chunking(Plan& p);
 size_t plan_footprint(int N, int N_rho, int M, int precision);
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
-                       double br, int nj, int N_rho, int M, int precision, void* stream);
+                       double br, int nj, int N_rho, int M, int precision, void* stream, bool otf = false);
 double power_kernel_constant(double s);
 
 // Enqueue Q = Q(f) for `cells` cells sharing plan p, using workspace w.

@@ -1,0 +1,157 @@
+"""Plans with their weights evaluated on the fly (bzq_plan_create_otf) against
+the oracle, and against plans with a stored table.
+
+The weights come from the Funk-Hecke series of the exact F of eq. FF, evaluated
+per chunk of pairs on the GPU; the oracle's F is the t-integral of its own
+(J0 route), so the two share nothing but the definition.  Tolerances as in
+test_gpu_parity.py: the series is truncated at 1e-13 of its sum.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = {"fp64": 1e-11, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def bzq():
+    import torch  # noqa: F401
+    from paper_2004_11239_amd import bzq as b
+    return b
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _modes_half(N):
+    n1 = N - 1
+    r = np.arange(n1) - (N // 2 - 1)
+    K = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).transpose(1, 0, 2, 3).reshape(n1 * n1, n1, 3)
+    nh = (n1 * n1 + 1) // 2
+    return K[:nh].reshape(-1, 3), nh, n1
+
+
+@pytest.mark.parametrize("N,L,R,kname", [(16, 8.0, 4.0, "s050"), (32, (3 + math.sqrt(2)) * 1.5, 6.0, "b5"),
+                                         (32, (3 + math.sqrt(2)) * 1.5, 6.0, "b7"),
+                                         (32, (3 + math.sqrt(2)) * 1.5, 6.0, "b8")])
+def test_otf_weights_match_oracle(bzq, N, L, R, kname):
+    """Every half-spectrum weight of sampled pairs, up to the largest a|k| of the
+    BKW setting (R = 6: a|k| ~ 37)."""
+    kern = oracle.power_kernel(0.5) if kname == "s050" else oracle.PAPER_KERNELS[kname]
+    plan = bzq.Plan(N, L, R, 0.0, 0.5, 8, 38, precision="fp64", weights="otf",
+                    kernel=None if kname == "s050" else (kern.c, kern.s, kern.r))
+    pairs = plan.pairs()
+    P = plan.info()["P"]
+    K, nh, n1 = _modes_half(N)
+    for j in (0, 5, len(pairs) // 2, len(pairs) - 1):
+        rho, sx, sy, sz, wq, _ = pairs[j]
+        a = math.pi * rho / (2 * L)
+        sig = np.array([sx, sy, sz])
+        F = oracle.F_weight(K, a, sig, kern)
+        x = a * (K @ sig)
+        ref = (2 * wq * np.real(np.exp(-1j * x) * F) / P ** 3).reshape(nh, n1)
+        got = plan.weights(j)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(kname, j, f"{err:.2e}")
+        assert err <= 1e-12, (j, err)
+    plan.destroy()
+
+
+def _golden(name):
+    data = np.load(os.path.join(GOLDEN, name + ".npz"), allow_pickle=False)
+    N, L, R, gamma, s, N_rho, M, seed = data["params"]
+    N, N_rho, M, seed = int(N), int(N_rho), int(M), int(seed)
+    mix = workloads.two_maxwellians(seed) if int(data["kind"]) == 0 else workloads.random_mixture(seed)
+    f = workloads.to_spectral(mix.sample(N, L))
+    return (N, L, R, gamma, s, N_rho, M), f, data["modes"], data["Q"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_otf_all_modes_small(bzq, prec):
+    for (N, L, R, gamma, s, N_rho, M) in [(8, 6.0, 3.0, 0.5, 0.25, 5, 14), (16, 8.0, 4.0, 0.0, 0.5, 16, 38)]:
+        d = oracle.Discretization.power(N, L, R, gamma, s, N_rho, M)
+        f = workloads.to_spectral(workloads.two_maxwellians(0).sample(N, L))
+        ref = oracle.collision_direct(f, d)
+        plan = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision=prec, weights="otf")
+        Q = _host(plan.collision(_dev(f)))
+        err = _rel(Q, ref)
+        print(N, prec, f"{err:.3e}")
+        assert err < TOL[prec]
+        assert Q[0, 0, 0] == 0.0
+        plan.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["medium_s050", "medium_s075", "medium_gm1", "large_s050"])
+def test_otf_golden_samples(bzq, name, prec):
+    params, f, ks, ref = _golden(name)
+    N = params[0]
+    fd = _dev(f)
+    plan = bzq.Plan(*params, precision=prec, weights="otf")
+    Q = _host(plan.collision(fd))
+    got = Q[tuple(np.mod(ks, N).T)]
+    err = _rel(got, ref)
+    info = plan.info()
+    print(name, prec, f"{err:.3e}", "coefficient bytes", info["table_bytes"])
+    assert err < TOL[prec]
+    # every schedule with weights generated per chunk
+    for sched in [(1, 1, 1, 1024), (0, 0, 2, 512)]:
+        try:
+            plan.set_schedule(*sched)
+        except bzq.BzqError:
+            continue
+        Q2 = _host(plan.collision(fd))
+        assert _rel(Q2[tuple(np.mod(ks, N).T)], ref) < TOL[prec], sched
+    plan.destroy()
+
+
+def test_otf_equals_table_and_steps(bzq):
+    """FP64: the on-the-fly plan and the table plan agree to the series' 1e-13,
+    also after Heun steps; the plan holds far fewer bytes."""
+    N, L, R, gamma, s, N_rho, M = 32, 8.0, 4.0, 0.0, 0.5, 32, 110
+    f = workloads.to_spectral(workloads.two_maxwellians(3).sample(N, L))
+    pt = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision="fp64")
+    po = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision="fp64", weights="otf")
+    qa = _host(pt.collision(_dev(f)))
+    qb = _host(po.collision(_dev(f)))
+    assert _rel(qb, qa) < 1e-12
+    ga, gb = _dev(f), _dev(f)
+    pt.step(ga, 0.01, 5)
+    po.step(gb, 0.01, 5)
+    assert _rel(_host(gb), _host(ga)) < 1e-13
+    assert po.info()["table_bytes"] < 0.2 * pt.info()["table_bytes"]
+    assert po.device_bytes() < pt.device_bytes()
+
+
+def test_otf_batch_bitwise_equals_solo(bzq):
+    import torch
+    pa = bzq.Plan(16, 8.0, 4.0, 0.0, 0.5, 16, 38, precision="fp32", weights="otf")
+    fs = [workloads.to_spectral(workloads.random_mixture(40 + i).sample(16, 8.0)) for i in range(5)]
+    solo = [_host(pa.collision(_dev(f))) for f in fs]
+    fd = [_dev(f) for f in fs]
+    batch = bzq.Batch([pa] * 5, fd, cells_per_launch=0)
+    outs = [torch.empty_like(x) for x in fd]
+    batch.collision(outs)
+    for a, b in zip(solo, outs):
+        assert np.array_equal(a, _host(b))
+    batch.destroy()

@@ -132,3 +132,9 @@ def test_plan2d_argument_validation_without_device(lib):
     assert lib.bzq_collision2d(None, None, None, None) == 1
     lib.bzq_plan2d_destroy.argtypes = [ctypes.c_void_p]
     assert lib.bzq_plan2d_destroy(None) == 0
+
+
+def test_weight_series_on_host(tmp_path):
+    r = _compile_and_run("fh_host_check.cpp", [os.path.join(CSRC, "funk_hecke.cpp"),
+                                               os.path.join(CSRC, "quadrature.cpp")], tmp_path)
+    assert r.returncode == 0, r.stdout
