@@ -65,6 +65,16 @@ def flop_model(N: int, npairs: int):
     return out
 
 
+def plane_bytes_per_pt(N: int, esz: int) -> int:
+    """Algorithmic HBM bytes of the plane stage per pair-two: read the z-inverse
+    output A (P (N-1)^2 complex) and write B (P x 2 half spectra of
+    ((N-1)^2+1)/2 modes, complex)."""
+    P, n1 = 3 * N // 2, N - 1
+    nn = n1 * n1
+    nh = (nn + 1) // 2
+    return P * (nn + 2 * nh) * 2 * esz
+
+
 def table_bytes(N: int, npairs: int, esz: int) -> int:
     n1 = N - 1
     return npairs * ((n1 * n1 + 1) // 2) * n1 * esz
@@ -383,13 +393,25 @@ def main():
     plane_ms, plane_n = st32.pop("plane_timed_region")
     avg_plane_s = plane_ms * 1e-3 / plane_n
     pts_per_launch = (npairs // 2) / (plane_n / evals32)
-    achieved = fm["plane_per_pt"] * pts_per_launch / avg_plane_s / 1e12
+    flop_launch = fm["plane_per_pt"] * pts_per_launch
+    bytes_launch = plane_bytes_per_pt(cfg["N"], 4) * pts_per_launch
+    tflops = flop_launch / avg_plane_s / 1e12
+    gbps = bytes_launch / avg_plane_s / 1e9
     kern_tag = f"k_plane_reg<float, {cfg['N']}, {3 * cfg['N'] // 2}, 0>"
     traffic = traffic_from_profiles(kern_tag)
-    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK["fp32"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK["fp32"], 4), "traffic": traffic,
-            "kernel": kern_tag, "avg_launch_ms": round(avg_plane_s * 1e3, 5),
-            "alg_flop_per_launch": fm["plane_per_pt"] * pts_per_launch}
+    # the binding roof of the roofline model: the larger of bytes / HBM peak
+    # and flops / FP32 vector peak
+    if bytes_launch / HBM_PEAK >= flop_launch / (PEAK["fp32"] * 1e12):
+        roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": round(gbps / (HBM_PEAK / 1e9), 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                "frac": round(tflops / PEAK["fp32"], 4)}
+    roof.update({"traffic": traffic, "kernel": kern_tag, "avg_launch_ms": round(avg_plane_s * 1e3, 5),
+                 "alg_bytes_per_launch": bytes_launch, "alg_flop_per_launch": flop_launch,
+                 "other_roof": ({"alu_tflops": round(tflops, 3), "alu_frac": round(tflops / PEAK["fp32"], 4)}
+                                if roof["bound"] == "hbm" else
+                                {"hbm_gbps": round(gbps, 1), "hbm_frac": round(gbps / (HBM_PEAK / 1e9), 4)})})
     per_eval_ms = ms32 / evals32
     whole = whole_path(cfg["N"], npairs, 4, ms32 / evals32)
     stage_ms = {k: round(v[0] / evals32, 4) for k, v in st32.items()}
