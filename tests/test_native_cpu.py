@@ -138,3 +138,26 @@ def test_weight_series_on_host(tmp_path):
     r = _compile_and_run("fh_host_check.cpp", [os.path.join(CSRC, "funk_hecke.cpp"),
                                                os.path.join(CSRC, "quadrature.cpp")], tmp_path)
     assert r.returncode == 0, r.stdout
+
+
+def test_otf_plan_limits_without_device(lib):
+    """bzq_plan_create_otf validates like bzq_plan_create_general and refuses,
+    before any device work, a geometry whose largest a|k| needs more than 64
+    even terms of the weight series."""
+    f = lib.bzq_plan_create_otf
+    d, i = ctypes.c_double, ctypes.c_int
+    f.argtypes = [ctypes.POINTER(ctypes.c_void_p), i, d, d, d, d, d, d, i, i, i, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    c = (1 - 0.5) * (2 - 0.5) / (24 * 3.141592653589793)
+    h = ctypes.c_void_p()
+    cases = [
+        ((15, 8.0, 4.0, 0.0, c, 0.5, 0.0, 16, 38, 0), 1),      # odd N
+        ((16, 8.0, 4.0, 0.0, c, 1.0, 0.0, 16, 38, 0), 1),      # s = 1
+        ((16, 8.0, 4.0, 0.0, c, 0.5, 0.0, 16, 37, 0), 1),      # no Lebedev rule of size 37
+        ((12, 8.0, 4.0, 0.0, c, 0.5, 0.0, 16, 38, 0), 4),      # no FFT schedule
+        ((64, 2.0, 40.0, 0.0, c, 0.5, 0.0, 8, 38, 0), 4),      # a|k| ~ 840: series too long
+    ]
+    for args, code in cases:
+        h.value = 1234
+        assert f(ctypes.byref(h), *args, None) == code, args
+        assert h.value is None
