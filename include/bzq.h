@@ -114,6 +114,20 @@ bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, dou
 bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, double b_c,
                                double b_s, double b_r, int N_rho, int M, int precision, void* stream);
 
+/* A plan for another gamma that shares the tables of `base` (weights,
+ * phases, twiddles: they do not depend on gamma, which enters eq. realQ only
+ * through c_p = w_rho rho^{2+gamma} with Phi = |q|^gamma).  The new plan holds
+ * its own c_p table, workspace and scratch; the shared tables stay allocated
+ * until every plan holding them is destroyed, so `base` may be destroyed
+ * first.  Results equal, bitwise, those of a plan created from scratch with
+ * the same arguments and gamma.  Synchronous; BZQ_EINVAL for a NULL base or
+ * gamma outside (-3, 1]. */
+bzq_status bzq_plan_derive_gamma(bzq_plan* out, bzq_plan base, double gamma, void* stream);
+
+/* Device bytes of the tables a plan shares with the plans derived from it
+ * (bzq_plan_device_bytes counts them too). */
+size_t bzq_plan_shared_bytes(bzq_plan p);
+
 /* Q_hat = Q(f_hat, f_hat) (eq. realQ).  f_hat and Q_hat: device, complex128
  * N^3 (layout above); they must not overlap.  Q_hat[0] is exactly 0
  * (Remark 4.1).  A non-finite f_hat gives a non-finite Q_hat. */

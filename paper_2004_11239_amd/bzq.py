@@ -49,6 +49,8 @@ def _load():
         "bzq_plan_create": ([ctypes.POINTER(vp), i, d, d, d, d, i, i, i, vp], i),
         "bzq_plan_create_general": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, i, vp], i),
         "bzq_plan_create_otf": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, vp], i),
+        "bzq_plan_derive_gamma": ([ctypes.POINTER(vp), vp, d, vp], i),
+        "bzq_plan_shared_bytes": ([vp], sz),
         "bzq_collision": ([vp, vp, vp, vp], i),
         "bzq_step": ([vp, vp, d, i, vp], i),
         "bzq_step_rk4": ([vp, vp, d, i, vp], i),
@@ -105,7 +107,8 @@ EXPORTED_EXTRA = ("bzq_workspace_create", "bzq_collision_ws", "bzq_step_ws", "bz
                   "bzq_batch_groups", "bzq_batch_group_info", "bzq_batch_device_bytes",
                   "bzq_batch_destroy", "bzq_server_create", "bzq_server_submit", "bzq_server_poll",
                   "bzq_server_wait", "bzq_server_stats", "bzq_server_destroy", "bzq_plan_bytes_estimate")
-EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_plan_create_otf", "bzq_collision", "bzq_step", "bzq_step_rk4", "bzq_moments",
+EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_plan_create_otf", "bzq_plan_derive_gamma",
+            "bzq_plan_shared_bytes", "bzq_collision", "bzq_step", "bzq_step_rk4", "bzq_moments",
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
             "bzq_plan_set_timing", "bzq_plan_stage_times", "bzq_plan_destroy", "bzq_status_string", "bzq_last_error",
@@ -179,6 +182,20 @@ class Plan:
         if self._h is None:
             raise RuntimeError("plan destroyed")
         return self._h
+
+    def with_gamma(self, gamma: float, stream=None) -> "Plan":
+        """A plan for another gamma sharing this plan's tables (bzq_plan_derive_gamma)."""
+        h = ctypes.c_void_p()
+        _check(_lib.bzq_plan_derive_gamma(ctypes.byref(h), self.handle, float(gamma), _stream(stream)))
+        p = Plan.__new__(Plan)
+        p.N, p.L, p.R, p.gamma = self.N, self.L, self.R, float(gamma)
+        p.N_rho, p.M, p.precision = self.N_rho, self.M, self.precision
+        p.weights_mode, p.kernel = self.weights_mode, self.kernel
+        p._h = h
+        return p
+
+    def shared_bytes(self) -> int:
+        return int(_lib.bzq_plan_shared_bytes(self.handle))
 
     def collision(self, f_hat: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
         """Q(f, f) of eq. realQ; complex128 (N,N,N) in FFT order on the GPU."""

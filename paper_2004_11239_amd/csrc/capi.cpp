@@ -190,10 +190,64 @@ size_t plan_footprint(int N, int N_rho, int M, int precision) {
   p.npt = p.npairs / 2;
   set_chunking(p);
   const size_t n3 = (size_t)N * N * N;
-  const size_t tables = (size_t)p.npairs * p.nh * p.n1 * p.esz + (size_t)p.npairs * 3 * (2 * N - 3) * 16 +
-                        (size_t)p.npairs * 8 + (size_t)p.P * 2 * p.esz + (size_t)N * 16;
+  const size_t tables = plan_shared_bytes_estimate(N, N_rho, M, precision) + (size_t)p.npairs * 8;
   const size_t grid = (size_t)p.n1 * p.nn * 16 + (size_t)N * p.nn * 16 + 2 * n3 * 8 + 256 * 8 * 8 + 16;
   return tables + p.workspace_bytes_per_cell() + grid;
+}
+
+namespace {
+bzq_status alloc_scratch(Plan* p);
+}  // namespace
+
+size_t plan_shared_bytes_estimate(int N, int N_rho, int M, int precision) {
+  const int P = 3 * N / 2, n1 = N - 1, nh = (n1 * n1 + 1) / 2;
+  const size_t esz = precision == BZQ_FP32_ACC64 ? 4 : 8;
+  const int nreal = N_rho * (M / 2);
+  const size_t npairs = nreal + (nreal & 1);
+  return npairs * nh * n1 * esz + npairs * 3 * (2 * N - 3) * 16 + (size_t)P * 2 * esz + (size_t)N * 16;
+}
+
+bzq_status derive_plan(const Plan& base, double gamma, bzq_plan* out, hipStream_t st) {
+  if (!out) return fail(BZQ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!(gamma > -3.0 && gamma <= 1.0)) return fail(BZQ_EINVAL, "gamma must lie in (-3, 1]");
+  bzq_plan_s* p = new bzq_plan_s();
+  // geometry, schedule and the shared tables
+  p->N = base.N; p->P = base.P; p->n1 = base.n1; p->nn = base.nn; p->nh = base.nh; p->nhp = base.nhp;
+  p->L = base.L; p->R = base.R; p->gamma = gamma;
+  p->bc = base.bc; p->bs = base.bs; p->br = base.br;
+  p->N_rho = base.N_rho; p->M = base.M; p->nj = base.nj; p->fp32 = base.fp32;
+  p->npairs = base.npairs; p->npt = base.npt; p->G = base.G; p->S = base.S; p->S_cap = base.S_cap;
+  for (int i = 0; i < 3; ++i) p->var[i] = base.var[i];
+  p->s_target = base.s_target; p->esz = base.esz;
+  p->otf = base.otf; p->mt = base.mt; p->Gw = base.Gw; p->Mh = base.Mh; p->nreal = base.nreal;
+  p->ncoef = base.ncoef; p->coef = base.coef; p->pdv = base.pdv; p->terms = base.terms;
+  p->V = base.V; p->ph = base.ph; p->tw_pad = base.tw_pad; p->tw_grid = base.tw_grid;
+  p->shared = base.shared;
+  p->pair_host = base.pair_host;
+  // c_p = w_rho rho^{2+gamma} for the new gamma
+  std::vector<double> rho, wr;
+  gauss_legendre(p->N_rho, p->R, rho, wr);
+  std::vector<double> cp(p->npairs, 0.0);
+  for (int j = 0; j < p->nreal; ++j) {
+    const int ip = j / p->Mh;
+    cp[j] = (double)((long double)wr[ip] * powl((long double)rho[ip], 2.0L + gamma));
+    p->pair_host[6 * j + 5] = cp[j];
+  }
+  bzq_status s;
+  hipError_t e = hipSuccess;
+  if ((s = p->tables.get(&p->cp, cp.size() * sizeof(double))) != BZQ_OK || (s = alloc_scratch(p)) != BZQ_OK) {
+    delete p;
+    return s;
+  }
+  e = hipMemcpyAsync(p->cp, cp.data(), cp.size() * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(BZQ_EDEVICE, std::string("derived plan: ") + hipGetErrorString(e));
+  }
+  *out = p;
+  return BZQ_OK;
 }
 
 namespace {
@@ -252,9 +306,9 @@ bzq_status build_series(Plan* p, const std::vector<double>& rho, int Mh, int nre
     pdv[4 * j + 3] = (double)(2.0L * ho[4] / P3);
   }
   bzq_status s;
-  if ((s = p->tables.get(&p->coef, coef.size() * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->tables.get(&p->pdv, pdv.size() * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->tables.get(&p->terms, terms.size() * sizeof(int))) != BZQ_OK) return s;
+  if ((s = p->shared->get(&p->coef, coef.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->shared->get(&p->pdv, pdv.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->shared->get(&p->terms, terms.size() * sizeof(int))) != BZQ_OK) return s;
   BZQ_HIP_TRY(hipMemcpyAsync(p->coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice, st));
   BZQ_HIP_TRY(hipMemcpyAsync(p->pdv, pdv.data(), pdv.size() * sizeof(double), hipMemcpyHostToDevice, st));
   BZQ_HIP_TRY(hipMemcpyAsync(p->terms, terms.data(), terms.size() * sizeof(int), hipMemcpyHostToDevice, st));
@@ -263,8 +317,23 @@ bzq_status build_series(Plan* p, const std::vector<double>& rho, int Mh, int nre
   return BZQ_OK;
 }
 
+// The plan's own workspace (one cell) and its FP64 physical-grid scratch.
+bzq_status alloc_scratch(Plan* p) {
+  const int N = p->N, nn = p->nn;
+  bzq_status s;
+  if ((s = workspace_init(p->ws, *p, 1)) != BZQ_OK) return s;
+  const size_t n3 = (size_t)N * N * N;
+  if ((s = p->grid_scratch.get(&p->gfc, (size_t)p->n1 * nn * 2 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->gA, (size_t)N * nn * 2 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->gf, n3 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->gq, n3 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->part, (size_t)kMomentBlocks * 8 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->flag, sizeof(int) * 4)) != BZQ_OK) return s;
+  return BZQ_OK;
+}
+
 bzq_status build_plan(Plan* p, hipStream_t st) {
-  const int N = p->N, P = p->P, nn = p->nn, nh = p->nh;
+  const int N = p->N, P = p->P, nh = p->nh;
   // -- quadrature
   std::vector<double> rho, wr;
   gauss_legendre(p->N_rho, p->R, rho, wr);
@@ -277,6 +346,8 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
   const int nreal = p->N_rho * Mh;
   p->npairs = nreal + (nreal & 1);
   p->npt = p->npairs / 2;
+  p->Mh = Mh;
+  p->nreal = nreal;
   // -- per-pair data
   const int PL = 2 * N - 3;
   std::vector<double> pd((size_t)p->npairs * 8, 0.0), cp(p->npairs, 0.0), ph((size_t)p->npairs * 3 * PL * 2);
@@ -318,22 +389,15 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
   const size_t vcount = (size_t)p->npairs * nh * p->n1;
   if (p->otf) {
     if ((s = build_series(p, rho, Mh, nreal, st)) != BZQ_OK) return s;
-  } else if ((s = p->tables.get(&p->V, vcount * p->esz)) != BZQ_OK) {
+  } else if ((s = p->shared->get(&p->V, vcount * p->esz)) != BZQ_OK) {
     return s;
   }
-  if ((s = p->tables.get(&p->ph, ph.size() * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->shared->get(&p->ph, ph.size() * sizeof(double))) != BZQ_OK) return s;
   if ((s = p->tables.get(&p->cp, cp.size() * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->tables.get(&p->tw_pad, (size_t)P * 2 * p->esz)) != BZQ_OK) return s;
-  if ((s = p->tables.get(&p->tw_grid, (size_t)N * 2 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->shared->get(&p->tw_pad, (size_t)P * 2 * p->esz)) != BZQ_OK) return s;
+  if ((s = p->shared->get(&p->tw_grid, (size_t)N * 2 * sizeof(double))) != BZQ_OK) return s;
   // -- the plan's own workspace and grid scratch
-  if ((s = workspace_init(p->ws, *p, 1)) != BZQ_OK) return s;
-  const size_t n3 = (size_t)N * N * N;
-  if ((s = p->grid_scratch.get(&p->gfc, (size_t)p->n1 * nn * 2 * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->grid_scratch.get(&p->gA, (size_t)N * nn * 2 * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->grid_scratch.get(&p->gf, n3 * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->grid_scratch.get(&p->gq, n3 * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->grid_scratch.get(&p->part, (size_t)kMomentBlocks * 8 * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->grid_scratch.get(&p->flag, sizeof(int) * 4)) != BZQ_OK) return s;
+  if ((s = alloc_scratch(p)) != BZQ_OK) return s;
   DeviceArena tmp;
   double* d_pd = nullptr;
   double* d_gj = nullptr;
@@ -557,6 +621,16 @@ bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double 
   return create_plan(out, N, L, R, gamma, b_c, b_s, b_r, 64, N_rho, M, precision, stream, true);
 }
 
+bzq_status bzq_plan_derive_gamma(bzq_plan* out, bzq_plan base, double gamma, void* stream) {
+  if (!base) {
+    if (out) *out = nullptr;
+    return fail(BZQ_EINVAL, "NULL base plan");
+  }
+  return derive_plan(*base, gamma, out, (hipStream_t)stream);
+}
+
+size_t bzq_plan_shared_bytes(bzq_plan p) { return p ? p->shared->bytes : 0; }
+
 bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream) {
   if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
@@ -779,7 +853,7 @@ bzq_status bzq_check_finite(bzq_plan p, const double* f_hat, void* stream) {
 }
 
 size_t bzq_plan_device_bytes(bzq_plan p) {
-  return p ? p->tables.bytes + p->ws.arena.bytes + p->grid_scratch.bytes : 0;
+  return p ? p->shared->bytes + p->tables.bytes + p->ws.arena.bytes + p->grid_scratch.bytes : 0;
 }
 
 size_t bzq_plan_bytes_estimate(int N, int N_rho, int M, int precision) {

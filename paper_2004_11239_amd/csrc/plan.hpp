@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -84,12 +85,15 @@ struct Plan {
   double* coef = nullptr;       // [N_rho][ncoef][mt]
   double* pdv = nullptr;        // [npairs][4] sigma, 2 w_sigma / P^3
   int* terms = nullptr;         // [N_rho] terms used per radial node
-  // tables (read-only after creation)
+  // tables (read-only after creation).  Everything but cp is independent of
+  // gamma and lives in `shared`, which plans derived for other gammas
+  // (derive_plan) hold too; cp lives in the plan's own `tables`.
   void* V = nullptr;            // [npairs][n1][nh] real weights (table plans)
   double* ph = nullptr;         // [npairs][3][2N-3] complex128 phases
   double* cp = nullptr;         // [npairs] w_rho rho^{2+gamma}
   void* tw_pad = nullptr;       // P twiddles (LDS kernels), compute precision
   double* tw_grid = nullptr;    // N twiddles, FP64
+  std::shared_ptr<DeviceArena> shared = std::make_shared<DeviceArena>();
   DeviceArena tables;
   // the plan's own workspace (one cell) and FP64 physical-grid scratch
   Workspace ws;
@@ -118,6 +122,11 @@ void set_chunking(Plan& p);
 size_t plan_footprint(int N, int N_rho, int M, int precision);
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
                        double br, int nj, int N_rho, int M, int precision, void* stream, bool otf = false);
+// A plan for another gamma that shares base's gamma-independent tables (the
+// weights, phases and twiddles); only its c_p table and scratch are new.
+bzq_status derive_plan(const Plan& base, double gamma, bzq_plan* out, hipStream_t st);
+// Device bytes of the gamma-independent tables of a plan geometry.
+size_t plan_shared_bytes_estimate(int N, int N_rho, int M, int precision);
 double power_kernel_constant(double s);
 
 // Enqueue Q = Q(f) for `cells` cells sharing plan p, using workspace w.

@@ -6,7 +6,8 @@
 // are served by one worker thread that owns every HIP call:
 //   * plans are cached by their parameters and kept resident; a plan's
 //     workspaces are pooled, so concurrent requests on one plan each get
-//     their own scratch;
+//     their own scratch; plans that differ only in gamma share one set of
+//     tables (gamma enters only through c_p), counted once in the budget;
 //   * admission is by device-memory footprint: a request starts only when
 //     its plan (if not cached), a workspace (if none is free) and its state
 //     fit in the budget; idle cached plans are evicted least recently used
@@ -45,8 +46,9 @@ using Clock = std::chrono::steady_clock;
 
 struct PlanEntry {
   std::string key;
+  std::string tkey;                 // the plan's gamma-independent tables
   bzq_plan plan = nullptr;
-  size_t plan_bytes = 0;
+  size_t plan_bytes = 0;            // excluding the shared tables
   size_t ws_bytes = 0;              // bytes of one extra workspace
   int in_use = 0;
   bool own_ws_busy = false;         // the plan's built-in workspace
@@ -90,6 +92,7 @@ struct bzq_server_s {
   std::unordered_map<unsigned long long, std::unique_ptr<Request>> reqs;   // guarded by mu
   std::deque<Request*> pending;                    // worker only
   std::map<std::string, std::unique_ptr<PlanEntry>> plans;   // worker only
+  std::map<std::string, std::pair<size_t, int>> tables;       // tkey -> (bytes, plans holding them)
   std::map<int, std::vector<std::pair<double*, double*>>> buf_pool;   // N -> (device f, pinned host)
   std::thread worker;
   std::atomic<bool> stop{false};
@@ -112,12 +115,25 @@ std::string plan_key(const bzq_request& d) {
   return k.str();
 }
 
+// plans that differ only in gamma share their tables (bzq_plan_derive_gamma)
+std::string table_key(const bzq_request& d) {
+  std::ostringstream k;
+  k.precision(17);
+  k << d.N << "|" << d.L << "|" << d.R << "|" << d.s << "|" << d.N_rho << "|" << d.M << "|" << d.precision;
+  return k.str();
+}
+
 size_t state_bytes(int N) { return (size_t)N * N * N * 16; }
 
 void release_plan(bzq_server_s* s, PlanEntry* pe) {
   for (Workspace* w : pe->all_ws) delete w;
   s->used -= pe->plan_bytes + pe->ws_bytes * pe->all_ws.size();
   bzq_plan_destroy(pe->plan);
+  auto t = s->tables.find(pe->tkey);
+  if (t != s->tables.end() && --t->second.second == 0) {
+    s->used -= t->second.first;
+    s->tables.erase(t);
+  }
 }
 
 // make room for `need` bytes by evicting idle plans, least recently used first
@@ -156,28 +172,48 @@ bool try_start(bzq_server_s* s, Request* r, Slot& sl) {
   PlanEntry* pe = nullptr;
   auto it = s->plans.find(key);
   if (it == s->plans.end()) {
-    // a new plan: its footprint is known from the geometry before creating it
-    const size_t est = plan_footprint(d.N, d.N_rho, d.M, d.precision) + state_bytes(d.N);
-    if (est > s->budget) {
+    // a new plan: its footprint is known from the geometry before creating
+    // it; a cached plan differing only in gamma lends its tables
+    const std::string tkey = table_key(d);
+    PlanEntry* base = nullptr;
+    for (auto& kv : s->plans)
+      if (kv.second->tkey == tkey) {
+        base = kv.second.get();
+        break;
+      }
+    const size_t full = plan_footprint(d.N, d.N_rho, d.M, d.precision) + state_bytes(d.N);
+    const size_t est = base ? full - plan_shared_bytes_estimate(d.N, d.N_rho, d.M, d.precision) : full;
+    if (full > s->budget) {
       finish(s, r, 3, BZQ_ENOMEM, "request does not fit the device-memory budget");
       return true;
     }
-    if (s->used + est > s->budget && !make_room(s, est, nullptr)) return false;
+    if (s->used + est > s->budget && !make_room(s, est, base)) return false;
     bzq_plan p = nullptr;
-    const double bc = power_kernel_constant(d.s);
-    bzq_status st = create_plan(&p, d.N, d.L, d.R, d.gamma, bc, d.s, 0.0, 64, d.N_rho, d.M, d.precision,
-                                sl.stream);
+    bzq_status st;
+    if (base) {
+      st = derive_plan(*base->plan, d.gamma, &p, sl.stream);
+    } else {
+      const double bc = power_kernel_constant(d.s);
+      st = create_plan(&p, d.N, d.L, d.R, d.gamma, bc, d.s, 0.0, 64, d.N_rho, d.M, d.precision, sl.stream);
+    }
     if (st != BZQ_OK) {
       finish(s, r, 3, st, bzq_last_error());
       return true;
     }
-    const size_t pb = bzq_plan_device_bytes(p);
+    const size_t shared = bzq_plan_shared_bytes(p);
+    const size_t pb = bzq_plan_device_bytes(p) - shared;
     auto e = std::make_unique<PlanEntry>();
     e->key = key;
+    e->tkey = tkey;
     e->plan = p;
     e->plan_bytes = pb;
     e->ws_bytes = p->ws.arena.bytes;
     s->used += pb;
+    auto& t = s->tables[tkey];
+    if (t.second++ == 0) {
+      t.first = shared;
+      s->used += shared;
+    }
     pe = e.get();
     s->plans[key] = std::move(e);
   } else {

@@ -166,3 +166,31 @@ def test_nonfinite_detection(bzq):
     assert plan.check_finite(_dev(f))
     f[1, 2, 3] = np.nan
     assert not plan.check_finite(_dev(f))
+
+
+def test_derived_gamma_plan_shares_tables_bitwise(bzq):
+    """A plan derived for another gamma (bzq_plan_derive_gamma) holds no tables
+    of its own and gives bitwise the result of a plan built from scratch; it
+    outlives its base."""
+    N, L, R, s, N_rho, M = 16, 8.0, 4.0, 0.5, 16, 38
+    f = _dev(_input(N, L, 2))
+    base = bzq.Plan(N, L, R, 0.0, s, N_rho, M, precision="fp64")
+    for gamma in (-1.0, 0.5):
+        der = base.with_gamma(gamma)
+        fresh = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision="fp64")
+        qa = _host(der.collision(f))
+        qb = _host(fresh.collision(f))
+        assert np.array_equal(qa, qb)
+        assert der.shared_bytes() == base.shared_bytes() > 0
+        assert der.device_bytes() - der.shared_bytes() < fresh.device_bytes() - 0.5 * fresh.shared_bytes()
+        if gamma == -1.0:
+            assert _rel(qa, _oracle_Q(N, L, R, gamma, s, N_rho, M, 2)) < TOL64
+            keep = der
+        else:
+            der.destroy()
+        fresh.destroy()
+    base.destroy()
+    # the derived plan keeps the shared tables alive
+    qa = _host(keep.collision(f))
+    assert _rel(qa, _oracle_Q(N, L, R, -1.0, s, N_rho, M, 2)) < TOL64
+    keep.destroy()
