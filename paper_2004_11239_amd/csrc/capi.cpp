@@ -465,8 +465,8 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
   // f(v) on the padded grid, shared by every pair
   TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
   TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st));
-  // the S partial accumulators of every cell start at zero
-  TIMED(ST_PREP, launch_fill(w.Qpart, 0.0, ((cells - 1) * cs.qp + (size_t)p.S * p.nh * p.n1) * 2, st));
+  // the first last-stage launch writes the S partial accumulators of every
+  // cell, later ones add to them
   for (int c0 = 0; c0 < p.npt; c0 += p.G) {
     const int n = std::min(p.G, p.npt - c0);
     TIMED(ST_ZINV, launch_zinv(w.fc, p.ph, w.A, p.tw_pad, g, 2 * c0, n, ZINV_PAIRS, p.fp32, cs, st, p.var[0]));
@@ -481,11 +481,11 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
         TIMED(ST_ZFWD, launch_wgen(w.Vc, p.coef, p.pdv, p.terms, p.mt, p.N, p.Mh, p.nreal, pair0, 2 * m,
                                    p.ncoef, p.fp32, st));
         TIMED(ST_ZFWD, launch_zfwd(Bw, w.Vc, p.ph, p.cp, w.Qpart, p.tw_pad, g, pair0, m, p.S, p.fp32, cs, st,
-                                   p.var[2], pair0));
+                                   p.var[2], pair0, c0 == 0 && w0 == 0));
       }
     } else {
       TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, p.S, p.fp32, cs, st,
-                                 p.var[2]));
+                                 p.var[2], 0, c0 == 0));
     }
   }
   TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, p.S, st));

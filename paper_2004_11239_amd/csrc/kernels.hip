@@ -225,7 +225,8 @@ template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const T* __restrict__ V,
                                              const double2* __restrict__ ph, const double* __restrict__ cp,
                                              double2* __restrict__ Qpart, const cx<T>* __restrict__ twg,
-                                             int N, int pair0, int vpair0, int npt, int S, CellStrides cs) {
+                                             int N, int pair0, int vpair0, int npt, int S, int first,
+                                             CellStrides cs) {
   constexpr int LD = P + 1;
   B += blockIdx.z * cs.b;
   Qpart += blockIdx.z * cs.qp;
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
     if (o < nq * n1) {
       const int q = o / n1, i3 = o - q * n1;
       const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + q;
-      double2 v = Qpart[qi];
+      double2 v = first ? double2{0.0, 0.0} : Qpart[qi];
       v.x += accx[b];
       v.y += accy[b];
       Qpart[qi] = v;
@@ -719,7 +720,7 @@ template <typename T, int N, int P>
 __global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
     const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
     const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
-    CellStrides cs) {
+    int first, CellStrides cs) {
   using C = ZfwdPipeCfg<P>;
   constexpr int TQ = C::TQ, PW = C::PW, NC = 64 * C::CW;
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
@@ -829,7 +830,7 @@ __global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
       const int i3 = o / TQ, qq = o - i3 * TQ;
       if (o < TQ * n1 && c0 + qq < nh) {
         const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + qq;
-        double2 v = Qpart[qi];
+        double2 v = first ? double2{0.0, 0.0} : Qpart[qi];
         v.x += accx[bb];
         v.y += accy[bb];
         Qpart[qi] = v;
@@ -856,7 +857,7 @@ template <typename T, int N, int P>
 __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
     const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
     const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
-    CellStrides cs) {
+    int first, CellStrides cs) {
   using C = ZfwdCfg<T, P>;
   B += blockIdx.z * cs.b;
   Qpart += blockIdx.z * cs.qp;
@@ -948,7 +949,7 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
       const int i3 = o / TQ, qq = o - i3 * TQ;
       if (c0 + qq < nh) {
         const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + qq;
-        double2 v = Qpart[qi];
+        double2 v = first ? double2{0.0, 0.0} : Qpart[qi];
         v.x += accx[b];
         v.y += accy[b];
         Qpart[qi] = v;
@@ -1350,7 +1351,7 @@ hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, con
 
 template <typename T, int P>
 hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
-                  const void* tw, int N, int pair0, int vpair0, int npt, int S, int variant,
+                  const void* tw, int N, int pair0, int vpair0, int npt, int S, int first, int variant,
                   const CellStrides& cs, hipStream_t st) {
   const int v = variant ? variant : defaultVariant<T, P>(2);
   if constexpr (hasTwo<P>())
@@ -1360,7 +1361,7 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
       constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
       dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
       hipLaunchKernelGGL((k_zfwd_pipe<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
-                         (const double2*)ph, cp, (double2*)Qpart, pair0, vpair0, npt, S, cs);
+                         (const double2*)ph, cp, (double2*)Qpart, pair0, vpair0, npt, S, first, cs);
       return hipGetLastError();
     }
   if constexpr (RegFit<T, P>::value && isPad<P>()) {
@@ -1369,14 +1370,14 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
     constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
     dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
     hipLaunchKernelGGL((k_zfwd_reg<T, NN, P>), grid, dim3(C::NT), 0, st, (const cx<T>*)B, (const T*)V,
-                       (const double2*)ph, cp, (double2*)Qpart, pair0, vpair0, npt, S, cs);
+                       (const double2*)ph, cp, (double2*)Qpart, pair0, vpair0, npt, S, first, cs);
     return hipGetLastError();
   }
   const int nn = (N - 1) * (N - 1), nh = (nn + 1) / 2;
   dim3 grid((nh + K3_TQ - 1) / K3_TQ, S, cs.cells);
   hipLaunchKernelGGL((k_zfwd<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)B,
                      (const T*)V, (const double2*)ph, cp, (double2*)Qpart, (const cx<T>*)tw, N, pair0,
-                     vpair0, npt, S, cs);
+                     vpair0, npt, S, first, cs);
   return hipGetLastError();
 }
 
@@ -1421,11 +1422,11 @@ hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout
 
 hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const double* cp, double* Qpart,
                        const void* tw, Geometry g, int pair0, int npt, int S, bool fp32,
-                       const CellStrides& cs, hipStream_t st, int variant, int vpair0) {
+                       const CellStrides& cs, hipStream_t st, int variant, int vpair0, bool first) {
 #define CASE(PP)                                                                                      \
   case PP:                                                                                            \
-    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, variant, cs, st) \
-                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, variant, cs, st);
+    return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, first, variant, cs, st) \
+                : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, first, variant, cs, st);
   switch (g.P) { BZQ_PAD_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;

@@ -53,10 +53,13 @@ hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout
 // Step 3: forward along axis 3, split the two packed pairs, apply the stored
 // weights and the phase e^{i a k.sigma}, accumulate in FP64 into Qpart[s].
 // The weight of pair j is row j - vpair0 of V (0 for a plan-wide table, the
-// chunk's first pair for weights generated per chunk).
+// chunk's first pair for weights generated per chunk).  With first = true the
+// launch writes every partial Qpart[s < S] instead of adding to it (the first
+// launch of an evaluation, so that no clearing pass is needed).
 hipError_t launch_zfwd(const void* B, const void* V, const double* phase, const double* cp,
                        double* Qpart, const void* tw, Geometry g, int pair0, int npt, int S,
-                       bool fp32, const CellStrides& cs, hipStream_t st, int variant = 0, int vpair0 = 0);
+                       bool fp32, const CellStrides& cs, hipStream_t st, int variant = 0, int vpair0 = 0,
+                       bool first = false);
 
 // Weights of pairs j0 .. j0+nj-1 into Vc[j - j0][n1][nh] (compute precision)
 // from the series of the angular weight in Chebyshev form:
