@@ -101,16 +101,20 @@ bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, dou
 
 /* The same plan with its weights evaluated on the fly (beyond the paper):
  * no table of J N^3 / 2 weights is stored or built.  Before the last stage of
- * each chunk of pairs, a kernel evaluates the weights of that chunk from the
- * Funk-Hecke series of the exact weight of eq. FF,
+ * each block of pairs (at most 128 MiB of weights, or $BZQ_OTF_MB), a kernel
+ * evaluates that block's weights from the Funk-Hecke series of the exact
+ * weight of eq. FF,
  *   Re(e^{-ix} F) = sum_{l even} (2l+1) (-1)^{l/2} mu_l j_l(a|k|) P_l(k.sigma/|k|),
  *   mu_l = 2 pi \int b(u) (P_l(u) - 1) du  (finite for every s < 1),
- * truncated where the terms fall below 1e-13 of the sum (at most 126 even
- * terms: a |k| <= ~80).  The plan then holds N_rho x terms x 3(N/2-1)^2
- * coefficients (70 MB at N = 64, N_rho = 64) instead of the weight table
- * (4.8 GB in FP64), and its workspace one chunk of weights.  Same arguments
- * and limits as bzq_plan_create_general (n_jacobi is not used); every other
- * call accepts the plan unchanged.  BZQ_EUNSUPPORTED if a |k| is too large. */
+ * truncated at l <= r + 8 r^{1/3} + 12, r = a|k| (below 1e-13 of the sum; at
+ * most 64 even terms, r <= ~80).  The plan then holds N_rho x (terms rounded
+ * up to 8) x (3 (N/2-1)^2 + 1) coefficients (71 MB at N = 64, N_rho = 64)
+ * instead of the weight table (4.8 GB FP32, 9.7 GB FP64 at N = 64, M = 302),
+ * and its workspace one block of weights.  Same arguments and limits as
+ * bzq_plan_create_general (there is no n_jacobi: the series moments use their
+ * own exact Gauss-Jacobi rule); every other call accepts the plan unchanged.
+ * BZQ_EUNSUPPORTED, before any device work, if the series would need more
+ * than 64 terms. */
 bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, double b_c,
                                double b_s, double b_r, int N_rho, int M, int precision, void* stream);
 
