@@ -207,14 +207,18 @@ def whole_path(N, npairs, esz, per_eval_ms):
 
 
 # ---------------------------------------------------------------- CPU oracle
+def _blas_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(cfg, fhat_np, n_modes=1536, seed=0):
     import numpy as np
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        blas_threads = os.cpu_count() or 1
+    blas_threads = _blas_threads()
     d = oracle.Discretization.power(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"],
                                     cfg["N_rho"], cfg["M"])
     modes = oracle.mode_vectors(cfg["N"])
@@ -224,7 +228,7 @@ def cpu_baseline(cfg, fhat_np, n_modes=1536, seed=0):
     q = oracle.collision_direct(fhat_np, d, k_out=ks, k_block=256)
     t = time.perf_counter() - t0
     value = n_modes / (t * len(modes))
-    return ks, q, t, {"value": value, "unit": "Q evals/s", "cores": int(max(blas_threads, 8)),
+    return ks, q, t, {"value": value, "unit": "Q evals/s", "cores": int(blas_threads),
                       "kind": "oracle",
                       "sample": f"{n_modes} of {len(modes)} output modes of one evaluation at the "
                                 f"medium workload in {t:.1f} s (direct weighted sum, FP64, weight "
@@ -288,9 +292,43 @@ def bench_2d(bzq, torch, n_evals=20):
         qphys = np.real(np.fft.ifft2(qn * sgn[:, None] * sgn[None, :])) * N * N
         out[prec] = {"evals_per_s": round(1e3 / ms, 2), "ms_per_eval": round(ms, 4),
                      "table1_linf_error": float(np.max(np.abs(qphys - exact)))}
+        # whole-evaluation roofline: per pair-two 2 (N-1+P) length-P transforms
+        # and the P^2 product; bytes: the weight table and f, Q
+        P, n1 = 3 * N // 2, N - 1
+        npairs = N * 16                      # N_rho = N radii x N_sigma / 2 circle pairs
+        flops = npairs // 2 * (2 * (n1 + P) * fft_flops(P) + 2.0 * P * P)
+        nbytes = npairs * ((n1 * n1 + 1) // 2) * (4 if prec == "fp32" else 8) + 2 * N * N * 16
+        peak = PEAK["fp32" if prec == "fp32" else "fp64"]
+        t_alu, t_hbm = flops / (peak * 1e12), nbytes / HBM_PEAK
+        out[prec]["roofline"] = {"bound": "alu" if t_alu >= t_hbm else "hbm",
+                                 "alg_gflop": round(flops / 1e9, 3), "alg_mb": round(nbytes / 1e6, 2),
+                                 "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                                 "frac": round(max(t_alu, t_hbm) / (ms * 1e-3), 4)}
         plan.destroy()
     out["table1_paper_b3_N64"] = 3.1950e-09
     return out
+
+
+def cpu_baseline_2d(n_modes=64, seed=0):
+    """The 2-D oracle (direct weighted sum, FP64) at the 2-D bench setting,
+    timed over a sample of output modes, scaled to evals/s."""
+    import numpy as np
+    import oracle
+    import workloads
+    N, R = 64, 6.0
+    L = (3 + math.sqrt(2)) * R / 4
+    f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L, 0.5))
+    d = oracle.collision2d.Discretization2D(N, L, R, 0.0, oracle.collision2d.PAPER_KERNELS_2D["b3"], N, 32)
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(-(N // 2 - 1), N // 2, size=(n_modes, 2))
+    t0 = time.perf_counter()
+    oracle.collision2d.collision_direct2d(f, d, k_out=ks)
+    t = time.perf_counter() - t0
+    total = (N - 1) ** 2
+    return {"value": round(n_modes / (t * total), 6), "unit": "Q evals/s", "cores": int(_blas_threads()),
+            "kind": "oracle",
+            "sample": f"{n_modes} of {total} output modes of one 2-D evaluation (N=64, N_rho=64, N_sigma=32) "
+                      f"in {t:.1f} s (direct weighted sum, FP64, weight table included)"}
 
 
 def bench_otf(bzq, torch, cfg, fhat_np, q_ref, n_evals=3):
@@ -412,6 +450,18 @@ def main():
                  "other_roof": ({"alu_tflops": round(tflops, 3), "alu_frac": round(tflops / PEAK["fp32"], 4)}
                                 if roof["bound"] == "hbm" else
                                 {"hbm_gbps": round(gbps, 1), "hbm_frac": round(gbps / (HBM_PEAK / 1e9), 4)})})
+    # the paper's integrator: classical RK4 steps (4 evaluations each) with the tuned plan
+    fd_rk = torch.from_numpy(fhat).to("cuda")
+    p32.step(fd_rk, DT, 1, method="rk4")
+    torch.cuda.synchronize()
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_rk = max(2, args.steps // 2)
+    r0.record()
+    p32.step(fd_rk, DT, n_rk, method="rk4")
+    r1.record()
+    torch.cuda.synchronize()
+    rk_ms = r0.elapsed_time(r1) / n_rk
+    rk4 = {"ms_per_step": round(rk_ms, 4), "evals_per_s": round(4e3 / rk_ms, 2), "steps": n_rk}
     per_eval_ms = ms32 / evals32
     whole = whole_path(cfg["N"], npairs, 4, ms32 / evals32)
     stage_ms = {k: round(v[0] / evals32, 4) for k, v in st32.items()}
@@ -439,6 +489,7 @@ def main():
         "fp64": {"value": round(value64, 3), "ms_per_step": round(ms64 / steps64, 4),
                  "stage_ms_per_eval": {k: round(v[0] / (2 * steps64), 4) for k, v in st64.items()}},
         "err_fp32_vs_fp64": err32_64,
+        "rk4_step": rk4,
         "stage_ms_per_eval": stage_ms,
         "whole_path": whole,
         "wall_s": {"fp32": round(wall32, 3), "fp64": round(wall64, 3)},
@@ -480,6 +531,8 @@ def main():
             "fp64": float(np.linalg.norm(q64n[idx] - qo) / np.linalg.norm(qo))}
         out["cpu_baseline"] = cb
         out["cpu_fft_baseline"] = cpu_fft_baseline(cfg, fhat)
+        if args.two_d:
+            out["two_d"]["cpu_baseline"] = cpu_baseline_2d()
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
