@@ -19,8 +19,8 @@ Every function here is pinned by a CPU test against something other than
 itself (closed forms, library routines on special cases, brute force, the BKW
 solution, the conservation laws).
 """
-from .angular import (AngularKernel, PAPER_KERNELS, bkw_lambda, cutoff_kernel, power_kernel,
-                      psi, F_weight, F_sphere, psi_cutoff_closed_form, psi_small_argument,
+from .angular import (AngularKernel, DEBYE_KERNELS, DebyeKernel, PAPER_KERNELS, bkw_lambda, cutoff_kernel,
+                      power_kernel, psi, F_weight, F_sphere, psi_cutoff_closed_form, psi_small_argument,
                       F_eps_split)
 from .collision import (Discretization, collision_direct, mode_vectors, quadrature_nodes,
                         weight_table)

@@ -20,6 +20,9 @@ whose integrand is smooth.  K is evaluated without cancellation:
 e^{2ixt} - 1 = -2 sin^2(xt) + i sin(2xt) and J0(Y) - 1 = -Y^2 j1m(Y) with
 j1m(Y) = (1 - J0(Y)) / Y^2 summed as a series for small Y.
 
+The Debye-Yukawa kernel of Section 5.6 and its cutoff (`DebyeKernel`) use
+the same K with a composite rule for their logarithmic weight.
+
 Also here, as independent pins of Psi:
   * `F_sphere`: eq. FF3D1 done as a 2-D (t, azimuth) product rule, no Bessel
     function (the paper's azimuthal route);
@@ -86,6 +89,84 @@ PAPER_KERNELS = {
 }
 
 
+@dataclasses.dataclass(frozen=True)
+class DebyeKernel:
+    """The Debye-Yukawa kernel of Section 5.6 (eq. ApproximatedDebye):
+    sin th B = |q| |log(2 sin(th/2))| / (2 sin(th/2)), i.e. Phi = |q| (gamma = 1)
+    and sin th b = |log(2 sin(th/2))| / (2 sin(th/2)); zero for th < theta_cut
+    (eq. ApproximatedDebyecutoff uses theta_cut = pi/10).
+
+    With t = sin^2(th/2) (sin th d th = 2 dt) the weight is
+        Psi = pi \\int_{t_c}^1 w(t) K(t) dt,  w(t) = |log(2 sqrt t)| (1-t)^{-1/2},
+    K as for the power kernels.  w has a logarithmic singularity at t = 0, a
+    kink at t = 1/4 and an inverse square root at t = 1; `rule` integrates it
+    by a composite rule: Gauss-Jacobi for (1-t)^{-1/2} on [1/4, 1], Gauss-
+    Legendre panels in geometric progression (ratio 8) on [t0, 1/4] (or
+    [t_c, 1/4]), and on [0, t0] (t0 = 1e-6, no cutoff) Gauss-Laguerre after
+    t = t0 e^{-u}, where |log(2 sqrt t)| is linear in u."""
+    theta_cut: float = 0.0
+    name: str = "debye"
+
+    def b_of_theta(self, th):
+        th = np.asarray(th, dtype=np.float64)
+        sb = np.abs(np.log(2.0 * np.sin(0.5 * th))) / (2.0 * np.sin(0.5 * th))
+        return np.where(th >= self.theta_cut, sb / np.sin(th), 0.0)
+
+    prefactor = math.pi
+
+    def rule(self, n_jacobi: int = 64):
+        from scipy.special import roots_laguerre
+        t0, ratio, nL = 1e-6, 8.0, 20
+        ts, ws = [], []
+        sB, wB = gauss_jacobi_unit(n_jacobi, 0.0, 0.5)
+        tB = 0.25 + 0.75 * sB
+        ts.append(tB)
+        ws.append(wB * math.sqrt(0.75) * np.log(2.0 * np.sqrt(tB)))
+
+        def panel(a, b, n):
+            x, w = np.polynomial.legendre.leggauss(n)
+            t = a + (b - a) * (x + 1.0) / 2.0
+            return t, w * (b - a) / 2.0 * np.abs(np.log(2.0 * np.sqrt(t))) / np.sqrt(1.0 - t)
+
+        tc = math.sin(0.5 * self.theta_cut) ** 2
+        hi, k = 0.25, 0
+        while True:
+            lo = hi / ratio
+            n = 32 if k == 0 else 24 if k == 1 else 16
+            if self.theta_cut > 0.0 and lo <= tc:
+                t, w = panel(tc, hi, n)
+                ts.append(t)
+                ws.append(w)
+                break
+            if lo <= t0:
+                t, w = panel(t0, hi, n)
+                ts.append(t)
+                ws.append(w)
+                if self.theta_cut == 0.0:
+                    u, om = roots_laguerre(nL)
+                    tL = t0 * np.exp(-u)
+                    ts.append(tL)
+                    ws.append(om * t0 * (u + math.log(1.0 / (4.0 * t0))) / 2.0 / np.sqrt(1.0 - tL))
+                break
+            t, w = panel(lo, hi, n)
+            ts.append(t)
+            ws.append(w)
+            hi, k = lo, k + 1
+        return np.concatenate(ts), np.concatenate(ws)
+
+
+DEBYE_KERNELS = {"debye": DebyeKernel(0.0, "debye"), "debye_cut": DebyeKernel(math.pi / 10.0, "debye_cut")}
+
+
+def _rule(kern, n_jacobi: int):
+    """Nodes, weights and prefactor: Psi = prefactor * sum_i w_i K(t_i)."""
+    if isinstance(kern, DebyeKernel):
+        t, w = kern.rule(n_jacobi)
+        return t, w, kern.prefactor
+    t, w = gauss_jacobi_unit(n_jacobi, kern.s, kern.r)
+    return t, w, 4.0 * math.pi * kern.c
+
+
 def bkw_lambda(kern: AngularKernel) -> float:
     """lambda = 1/4 \\int_{S^2} (1 - (sigma.q)^2) b d sigma (Section 5.1)
     = 4 pi c B(1-s, 2-r) for b = c t^{-1-s}(1-t)^{-r}."""
@@ -116,14 +197,15 @@ def j1m(Y):
 # --------------------------------------------------------------------------
 # Psi(x, y): the exact weight, Bessel route
 # --------------------------------------------------------------------------
-def psi(x, y, kern: AngularKernel, n_jacobi: int = 64):
-    """F(k,|q|,q) = Psi(x, y) for arrays x = a k.q, y = a|k_perp| (same shape)."""
+def psi(x, y, kern, n_jacobi: int = 64):
+    """F(k,|q|,q) = Psi(x, y) for arrays x = a k.q, y = a|k_perp| (same shape);
+    kern is an AngularKernel or a DebyeKernel."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     shape = np.broadcast(x, y).shape
     x = np.broadcast_to(x, shape).reshape(-1)
     y = np.broadcast_to(y, shape).reshape(-1)
-    t, w = gauss_jacobi_unit(n_jacobi, kern.s, kern.r)
+    t, w, pref = _rule(kern, n_jacobi)
     out = np.empty(x.shape, dtype=np.complex128)
     step = max(1, 2_000_000 // len(t))
     for i0 in range(0, x.size, step):
@@ -140,7 +222,7 @@ def psi(x, y, kern: AngularKernel, n_jacobi: int = 64):
         K_re = e_re * J + jm1_t
         K_im = e_im * J
         out[i0:i0 + step] = (K_re @ w) + 1j * (K_im @ w)
-    out *= 4.0 * math.pi * kern.c
+    out *= pref
     return out.reshape(shape)
 
 

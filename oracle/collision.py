@@ -36,7 +36,7 @@ from typing import Optional
 
 import numpy as np
 
-from .angular import AngularKernel, power_kernel, psi
+from .angular import AngularKernel, DebyeKernel, power_kernel, psi
 from .quadrature import radial_gauss_legendre, sphere_lebedev
 
 
@@ -54,6 +54,11 @@ class Discretization:
     @staticmethod
     def power(N, L, R, gamma, s, N_rho, M, n_jacobi=64):
         return Discretization(N, L, R, gamma, power_kernel(s), N_rho, M, n_jacobi)
+
+    @staticmethod
+    def debye(N, L, R, theta_cut, N_rho, M):
+        """The Debye-Yukawa kernel of Section 5.6: Phi = |q| (gamma = 1)."""
+        return Discretization(N, L, R, 1.0, DebyeKernel(theta_cut), N_rho, M)
 
 
 def mode_vectors(N: int) -> np.ndarray:

@@ -120,3 +120,52 @@ def test_paper_eps_split_converges_to_exact_weight():
             for e in (math.pi / 100, math.pi / 1000)]
     assert errs[1] < errs[0]
     assert errs[1] < 1e-6
+
+
+# ---------------------------------------------------------------- Debye-Yukawa
+def _debye_theta_mp(x, y, theta_cut):
+    """eq. FF with the azimuth done (J0), in theta, for eq. ApproximatedDebye:
+    2 pi \\int_{theta_cut}^pi |log(2 sin(th/2))| / (2 sin(th/2)) [e^{ix(1-cos th)} J0(y sin th) - 1] d th."""
+    import mpmath as mp
+    with mp.workdps(30):
+        def f(th):
+            sb = abs(mp.log(2 * mp.sin(th / 2))) / (2 * mp.sin(th / 2))
+            return 2 * mp.pi * sb * (mp.expj(x * (1 - mp.cos(th))) * mp.besselj(0, y * mp.sin(th)) - 1)
+        pts = [mp.mpf(theta_cut)] + [mp.pi * k / 24 for k in range(1, 25) if mp.pi * k / 24 > theta_cut]
+        return complex(mp.quad(f, pts))
+
+
+@pytest.mark.parametrize("name", ["debye", "debye_cut"])
+def test_debye_against_theta_quadrature(name):
+    """The composite rule for the logarithmic weight against a 30-digit
+    quadrature of the paper's theta-form, up to x, y ~ 70."""
+    pytest.importorskip("mpmath")
+    from oracle.angular import DEBYE_KERNELS
+    kern = DEBYE_KERNELS[name]
+    for x, y in [(0.2, 0.1), (3.0, 2.0), (-12.0, 9.0), (30.0, 25.0), (0.0, 60.0), (70.0, 30.0)]:
+        ref = _debye_theta_mp(x, y, kern.theta_cut)
+        got = complex(psi(x, y, kern))
+        assert abs(got - ref) <= 2e-12 * max(1.0, abs(ref)), (name, x, y, got, ref)
+
+
+def test_debye_structure():
+    from oracle.angular import DEBYE_KERNELS, DebyeKernel
+    k0, kc = DEBYE_KERNELS["debye"], DEBYE_KERNELS["debye_cut"]
+    assert kc.theta_cut == pytest.approx(math.pi / 10)
+    assert psi(0.0, 0.0, k0) == 0.0 and psi(0.0, 0.0, kc) == 0.0
+    x = RNG.uniform(-40, 40, 20)
+    y = RNG.uniform(0, 40, 20)
+    np.testing.assert_allclose(psi(-x, y, k0), np.conj(psi(x, y, k0)), rtol=0, atol=1e-13)
+    # the cutoff rule has no node below t_c = sin^2(pi/20); b vanishes there
+    t, w = kc.rule()
+    assert t.min() >= math.sin(math.pi / 20) ** 2 * (1 - 1e-15)
+    assert kc.b_of_theta(0.9 * math.pi / 10) == 0.0
+    # sin th b is the paper's expression above the cut
+    th = 1.1
+    assert abs(kc.b_of_theta(th) * math.sin(th) - abs(math.log(2 * math.sin(th / 2))) / (2 * math.sin(th / 2))) < 1e-15
+    # the rule integrates the weight exactly on constants: \int_0^1 |log(2 sqrt t)| (1-t)^{-1/2} dt
+    from scipy.integrate import quad
+    exact = (quad(lambda t: -math.log(2 * math.sqrt(t)) / math.sqrt(1 - t), 0, 0.25, limit=200)[0]
+             + quad(lambda t: math.log(2 * math.sqrt(t)) / math.sqrt(1 - t), 0.25, 1, limit=200)[0])
+    assert abs(np.sum(k0.rule()[1]) - exact) < 1e-12
+    assert DebyeKernel(0.0).prefactor == math.pi
