@@ -99,6 +99,17 @@ bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, dou
                                    double b_c, double b_s, double b_r, int n_jacobi,
                                    int N_rho, int M, int precision, void* stream);
 
+/* A plan for the Debye-Yukawa kernel of Section 5.6 (eq. ApproximatedDebye),
+ *   sin(theta) B(|q|, cos theta) = |q| |log(2 sin(theta/2))| / (2 sin(theta/2)),
+ * i.e. Phi = |q| (gamma = 1) and a logarithmic angular singularity, set to
+ * zero below theta_cut (eq. ApproximatedDebyecutoff: theta_cut = pi/10; 0 for
+ * the non-cutoff kernel; 0 <= theta_cut < pi/3, else BZQ_EINVAL).  The weight
+ * F of eq. FF is integrated in t = sin^2(theta/2) with a composite rule for
+ * |log(2 sqrt t)| (1-t)^{-1/2} (204 nodes; 120 with the cutoff).  Other
+ * arguments and limits as for bzq_plan_create. */
+bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, double theta_cut, int N_rho, int M,
+                                 int precision, void* stream);
+
 /* The same plan with its weights evaluated on the fly (beyond the paper):
  * no table of J N^3 / 2 weights is stored or built.  Before the last stage of
  * each block of pairs (at most 128 MiB of weights, or $BZQ_OTF_MB), a kernel

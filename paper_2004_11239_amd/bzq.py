@@ -49,6 +49,7 @@ def _load():
         "bzq_plan_create": ([ctypes.POINTER(vp), i, d, d, d, d, i, i, i, vp], i),
         "bzq_plan_create_general": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, i, vp], i),
         "bzq_plan_create_otf": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, vp], i),
+        "bzq_plan_create_debye": ([ctypes.POINTER(vp), i, d, d, d, i, i, i, vp], i),
         "bzq_plan_derive_gamma": ([ctypes.POINTER(vp), vp, d, vp], i),
         "bzq_plan_shared_bytes": ([vp], sz),
         "bzq_collision": ([vp, vp, vp, vp], i),
@@ -107,7 +108,8 @@ EXPORTED_EXTRA = ("bzq_workspace_create", "bzq_collision_ws", "bzq_step_ws", "bz
                   "bzq_batch_groups", "bzq_batch_group_info", "bzq_batch_device_bytes",
                   "bzq_batch_destroy", "bzq_server_create", "bzq_server_submit", "bzq_server_poll",
                   "bzq_server_wait", "bzq_server_stats", "bzq_server_destroy", "bzq_plan_bytes_estimate")
-EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_plan_create_otf", "bzq_plan_derive_gamma",
+EXPORTED = ("bzq_plan_create", "bzq_plan_create_general", "bzq_plan_create_otf", "bzq_plan_create_debye",
+            "bzq_plan_derive_gamma",
             "bzq_plan_shared_bytes", "bzq_collision", "bzq_step", "bzq_step_rk4", "bzq_moments",
             "bzq_check_finite", "bzq_collision_batch", "bzq_plan_device_bytes",
             "bzq_request_device_bytes", "bzq_plan_info", "bzq_plan_pairs", "bzq_plan_weights",
@@ -182,6 +184,22 @@ class Plan:
         if self._h is None:
             raise RuntimeError("plan destroyed")
         return self._h
+
+    @classmethod
+    def debye(cls, N: int, L: float, R: float, theta_cut: float, N_rho: int, M: int, precision="fp64",
+              stream=None) -> "Plan":
+        """The Debye-Yukawa kernel of Section 5.6 (gamma = 1), zero below theta_cut
+        (pi/10 for the paper's cutoff version, 0 for the non-cutoff kernel)."""
+        h = ctypes.c_void_p()
+        prec = _PREC[precision]
+        _check(_lib.bzq_plan_create_debye(ctypes.byref(h), int(N), float(L), float(R), float(theta_cut),
+                                          int(N_rho), int(M), prec, _stream(stream)))
+        p = cls.__new__(cls)
+        p.N, p.L, p.R, p.gamma = int(N), float(L), float(R), 1.0
+        p.N_rho, p.M, p.precision = int(N_rho), int(M), prec
+        p.weights_mode, p.kernel = "table", ("debye", float(theta_cut))
+        p._h = h
+        return p
 
     def with_gamma(self, gamma: float, stream=None) -> "Plan":
         """A plan for another gamma sharing this plan's tables (bzq_plan_derive_gamma)."""

@@ -217,6 +217,7 @@ bzq_status derive_plan(const Plan& base, double gamma, bzq_plan* out, hipStream_
   p->L = base.L; p->R = base.R; p->gamma = gamma;
   p->bc = base.bc; p->bs = base.bs; p->br = base.br;
   p->N_rho = base.N_rho; p->M = base.M; p->nj = base.nj; p->fp32 = base.fp32;
+  p->kind = base.kind; p->theta_cut = base.theta_cut;
   p->npairs = base.npairs; p->npt = base.npt; p->G = base.G; p->S = base.S; p->S_cap = base.S_cap;
   for (int i = 0; i < 3; ++i) p->var[i] = base.var[i];
   p->s_target = base.s_target; p->esz = base.esz;
@@ -342,7 +343,12 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
   const int Mh = lebedev_half(leb, half);
   if (Mh < 1) return fail(BZQ_EINVAL, "sphere rule is not centrally symmetric");
   std::vector<double> gt, gw;
-  if (!gauss_jacobi01(p->nj, p->bs, p->br, gt, gw)) return fail(BZQ_EINVAL, "Gauss-Jacobi rule failed");
+  if (p->kind == 1) {
+    if (!debye_rule(p->theta_cut, gt, gw)) return fail(BZQ_EINVAL, "theta_cut must lie in [0, pi/3)");
+    p->nj = (int)gt.size();
+  } else if (!gauss_jacobi01(p->nj, p->bs, p->br, gt, gw)) {
+    return fail(BZQ_EINVAL, "Gauss-Jacobi rule failed");
+  }
   const int nreal = p->N_rho * Mh;
   p->npairs = nreal + (nreal & 1);
   p->npt = p->npairs / 2;
@@ -541,7 +547,8 @@ bzq_status enqueue_step_rk4(Plan& p, Workspace& w, const PtrPack& f, int cells, 
 }
 
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
-                       double br, int nj, int N_rho, int M, int precision, void* stream, bool otf) {
+                       double br, int nj, int N_rho, int M, int precision, void* stream, bool otf, int kind,
+                       double theta_cut) {
   if (!out) return fail(BZQ_EINVAL, "out is NULL");
   *out = nullptr;
   if (N < 8 || (N & 1)) return fail(BZQ_EINVAL, "N must be even and >= 8");
@@ -568,6 +575,8 @@ bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, d
   p->N_rho = N_rho; p->M = M;
   p->fp32 = precision == BZQ_FP32_ACC64;
   p->otf = otf;
+  p->kind = kind;
+  p->theta_cut = theta_cut;
   bzq_status s = build_plan(p, (hipStream_t)stream);
   if (s != BZQ_OK) {
     delete p;
@@ -614,6 +623,15 @@ bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, dou
                                    double b_s, double b_r, int n_jacobi, int N_rho, int M, int precision,
                                    void* stream) {
   return create_plan(out, N, L, R, gamma, b_c, b_s, b_r, n_jacobi, N_rho, M, precision, stream);
+}
+
+bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, double theta_cut, int N_rho, int M,
+                                 int precision, void* stream) {
+  if (!(theta_cut >= 0.0 && theta_cut < (double)(kPi / 3))) {
+    if (out) *out = nullptr;
+    return fail(BZQ_EINVAL, "theta_cut must lie in [0, pi/3)");
+  }
+  return create_plan(out, N, L, R, 1.0, 0.25, 0.0, 0.0, 64, N_rho, M, precision, stream, false, 1, theta_cut);
 }
 
 bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, double b_c, double b_s,

@@ -62,6 +62,10 @@ struct Plan {
   int N = 0, P = 0, n1 = 0, nn = 0, nh = 0, nhp = 0;
   double L = 0, R = 0, gamma = 0, bc = 0, bs = 0, br = 0;
   int N_rho = 0, M = 0, nj = 0;
+  // angular kernel: 0 = c t^{-1-s} (1-t)^{-r}; 1 = the Debye-Yukawa kernel of
+  // Section 5.6, zero below theta_cut (then bc = 1/4 so that 4 pi bc = pi)
+  int kind = 0;
+  double theta_cut = 0.0;
   bool fp32 = false;
   int npairs = 0;   // antipodal pairs incl. a zero pad to an even count
   int npt = 0;      // pairs of pairs (packed into one complex transform)
@@ -121,7 +125,8 @@ void tune_cache_write(const std::map<std::string, int>& m);
 void set_chunking(Plan& p);
 size_t plan_footprint(int N, int N_rho, int M, int precision);
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
-                       double br, int nj, int N_rho, int M, int precision, void* stream, bool otf = false);
+                       double br, int nj, int N_rho, int M, int precision, void* stream, bool otf = false,
+                       int kind = 0, double theta_cut = 0.0);
 // A plan for another gamma that shares base's gamma-independent tables (the
 // weights, phases and twiddles); only its c_p table and scratch are new.
 bzq_status derive_plan(const Plan& base, double gamma, bzq_plan* out, hipStream_t st);

@@ -141,6 +141,104 @@ bool gauss_jacobi01(int n, double s, double r, std::vector<double>& t, std::vect
   return true;
 }
 
+void gauss_laguerre(int n, std::vector<long double>& u, std::vector<long double>& w) {
+  // Jacobi matrix of the Laguerre polynomials: diagonal 2k+1, off-diagonal k
+  std::vector<long double> d(n), e2(n, 0.0L);
+  for (int k = 0; k < n; ++k) {
+    d[k] = 2.0L * k + 1.0L;
+    if (k >= 1) e2[k] = (long double)k * k;
+  }
+  u.assign(n, 0.0L);
+  w.assign(n, 0.0L);
+  const long double hi0 = 4.0L * n + 4.0L;   // every node lies below 4n + 2
+  for (int i = 0; i < n; ++i) {
+    long double lo = 0, hi = hi0;
+    for (int it = 0; it < 90; ++it) {
+      const long double mid = 0.5L * (lo + hi);
+      if (sturm_count(d, e2, mid) > i) hi = mid; else lo = mid;
+    }
+    long double x = 0.5L * (lo + hi);
+    // Newton on L_n, with L_{n-1} for the derivative: x L_n' = n (L_n - L_{n-1})
+    long double ln = 0, lm = 0;
+    for (int it = 0; it < 6; ++it) {
+      long double p0 = 1, p1 = 1 - x;
+      for (int k = 1; k < n; ++k) {
+        const long double p2 = ((2 * k + 1 - x) * p1 - k * p0) / (k + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      ln = n == 0 ? 1 : p1;
+      lm = n == 0 ? 0 : p0;
+      const long double dp = n * (ln - lm) / x;
+      const long double dx = ln / dp;
+      x -= dx;
+      if (fabsl(dx) < 1e-21L * (1 + x)) break;
+    }
+    // w = x / ((n+1)^2 L_{n+1}(x)^2)
+    long double p0 = 1, p1 = 1 - x;
+    for (int k = 1; k <= n; ++k) {
+      const long double p2 = ((2 * k + 1 - x) * p1 - k * p0) / (k + 1);
+      p0 = p1;
+      p1 = p2;
+    }
+    u[i] = x;
+    w[i] = x / ((long double)(n + 1) * (n + 1) * p1 * p1);
+  }
+}
+
+bool debye_rule(double theta_cut, std::vector<double>& t, std::vector<double>& w) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  if (!(theta_cut >= 0.0 && theta_cut < (double)(pi / 3))) return false;
+  t.clear();
+  w.clear();
+  auto wlog = [](long double x) { return fabsl(logl(2.0L * sqrtl(x))) / sqrtl(1.0L - x); };
+  // [1/4, 1]: t = 1/4 + 3s/4, (1-t)^{-1/2} = (3/4)^{-1/2} (1-s)^{-1/2}, dt = 3/4 ds
+  std::vector<double> sj, wj;
+  if (!gauss_jacobi01(64, 0.0, 0.5, sj, wj)) return false;
+  for (size_t i = 0; i < sj.size(); ++i) {
+    const long double ti = 0.25L + 0.75L * sj[i];
+    t.push_back((double)ti);
+    w.push_back((double)(wj[i] * sqrtl(0.75L) * logl(2.0L * sqrtl(ti))));
+  }
+  // Gauss-Legendre panels [a, b] with the whole weight in the integrand
+  auto panel = [&](long double a, long double b, int n) {
+    std::vector<double> x, g;
+    gauss_legendre(n, 1.0, x, g);          // on [0, 1]
+    for (int i = 0; i < n; ++i) {
+      const long double ti = a + (b - a) * x[i];
+      t.push_back((double)ti);
+      w.push_back((double)((b - a) * g[i] * wlog(ti)));
+    }
+  };
+  const long double tc = powl(sinl(0.5L * theta_cut), 2), t0 = 1e-6L;
+  long double hi = 0.25L;
+  for (int k = 0;; ++k) {
+    const long double lo = hi / 8.0L;
+    const int n = k == 0 ? 32 : k == 1 ? 24 : 16;
+    if (theta_cut > 0.0 && lo <= tc) {
+      panel(tc, hi, n);
+      break;
+    }
+    if (lo <= t0) {
+      panel(t0, hi, n);
+      if (theta_cut == 0.0) {
+        // [0, t0]: t = t0 e^{-u}, |log(2 sqrt t)| = (u + log(1/(4 t0)))/2, dt = t du
+        std::vector<long double> u, om;
+        gauss_laguerre(20, u, om);
+        for (int i = 0; i < 20; ++i) {
+          const long double ti = t0 * expl(-u[i]);
+          t.push_back((double)ti);
+          w.push_back((double)(om[i] * t0 * (u[i] + logl(1.0L / (4.0L * t0))) / 2.0L / sqrtl(1.0L - ti)));
+        }
+      }
+      break;
+    }
+    panel(lo, hi, n);
+    hi = lo;
+  }
+  return true;
+}
+
 bool lebedev_rule(int M, std::vector<double>& xyzw) {
   for (int i = 0; i < kLebedevCount; ++i) {
     if (kLebedevIndex[i][0] == M) {

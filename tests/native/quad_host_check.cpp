@@ -1,7 +1,8 @@
 // Host-side check of the plan's quadrature rules (quadrature.cpp): exactness
 // of Gauss-Legendre and Gauss-Jacobi on polynomials (closed-form integrals),
 // exactness of every Lebedev rule on spherical monomials up to its degree,
-// and the antipodal split.
+// and the antipodal split; Gauss-Laguerre exactness and the composite rule of
+// the Debye-Yukawa weight against a fine quadrature after smoothing substitutions.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -67,6 +68,54 @@ int main() {
   }
   std::vector<double> r;
   if (bzq::lebedev_rule(37, r)) ++bad;
+  // Gauss-Laguerre: exact for u^k, k < 2n (\int e^{-u} u^k du = k!)
+  for (int n : {8, 20, 32}) {
+    std::vector<long double> u, w;
+    bzq::gauss_laguerre(n, u, w);
+    long double fact = 1;
+    for (int k = 0; k < 2 * n && k < 40; ++k) {
+      if (k > 0) fact *= k;
+      long double sum = 0;
+      for (int i = 0; i < n; ++i) sum += w[i] * powl(u[i], k);
+      if (fabsl(sum - fact) > 1e-15L * fact) { std::printf("Laguerre n=%d k=%d err=%Lg\n", n, k, (sum - fact) / fact); ++bad; }
+    }
+  }
+  // Debye rule: nodes in [t_c, 1), positive weights, and \int_0^1 w(t) g(t) dt for
+  // g = 1, t, t^2 against a fine quadrature after t = x^4 / 4 on [0, 1/4] and
+  // t = 1 - 3 y^2 / 4 on [1/4, 1] (both integrands smooth there)
+  for (double tcut : {0.0, 0.3141592653589793}) {
+    std::vector<double> t, w;
+    if (!bzq::debye_rule(tcut, t, w)) { ++bad; continue; }
+    const double tc = std::pow(std::sin(0.5 * tcut), 2);
+    for (size_t i = 0; i < t.size(); ++i)
+      if (!(t[i] >= tc * (1 - 1e-15) && t[i] < 1.0 && w[i] > 0)) { std::printf("debye node %zu\n", i); ++bad; break; }
+    std::vector<double> gx, gw;
+    bzq::gauss_legendre(400, 1.0, gx, gw);
+    for (int k = 0; k < 3; ++k) {
+      long double ref = 0;
+      for (int i = 0; i < 400; ++i) {
+        const long double x = gx[i], ta = x * x * x * x / 4;        // [0, 1/4]
+        if (ta >= tc) ref += gw[i] * (-logl(2 * sqrtl(ta))) / sqrtl(1 - ta) * powl(ta, k) * x * x * x;
+        const long double y = gx[i], tb = 1 - 0.75L * y * y;          // [1/4, 1]
+        ref += gw[i] * logl(2 * sqrtl(tb)) * powl(tb, k) * 1.5L / sqrtl(0.75L);
+      }
+      if (tcut > 0) {   // the part of [0, 1/4] below t_c is excluded; redo [t_c, 1/4] directly
+        ref = 0;
+        for (int i = 0; i < 400; ++i) {
+          const long double ta = tc + (0.25L - tc) * gx[i];
+          ref += gw[i] * (0.25L - tc) * (-logl(2 * sqrtl(ta))) / sqrtl(1 - ta) * powl(ta, k);
+          const long double y = gx[i], tb = 1 - 0.75L * y * y;
+          ref += gw[i] * logl(2 * sqrtl(tb)) * powl(tb, k) * 1.5L / sqrtl(0.75L);
+        }
+      }
+      long double sum = 0;
+      for (size_t i = 0; i < t.size(); ++i) sum += w[i] * powl((long double)t[i], k);
+      if (fabsl(sum - ref) > 1e-13L * fabsl(ref)) {
+        std::printf("debye rule theta_cut=%g k=%d: %.18Lg vs %.18Lg\n", tcut, k, sum, ref);
+        ++bad;
+      }
+    }
+  }
   std::printf("quadrature host check: %d failures\n", bad);
   return bad ? 1 : 0;
 }
