@@ -24,6 +24,8 @@ paper's 2-D kernels b1-b4 all qualify).  Pinned by the cutoff closed form
 (eq. cutoff2D), a 50-digit quadrature of eq. FF2D1 in theta, the BKW rate
 lambda = 1/8 of Section 5.2, a literal loop over eq. sum with F integrated
 over the circle as in eq. FF, the invariants, and the paper's Table 1.
+`F2d_eps_split` is the paper's own approximate precompute of F (Section 4.1),
+kept as a labelled variant whose convergence to `psi2d` is measured.
 
 Test infrastructure only: nothing in the GPU product path imports this file.
 """
@@ -98,6 +100,34 @@ def psi2d_cutoff_closed_form(x, y, C):
     """Eq. cutoff2D: b = C gives F = 2 pi C [ e^{ix} J0(sqrt(x^2 + y^2)) - 1 ]."""
     from scipy.special import j0
     return 2.0 * math.pi * C * (np.exp(1j * np.asarray(x)) * j0(np.hypot(x, y)) - 1.0)
+
+
+def F2d_eps_split(x, y, kern: AngularKernel, eps: float = math.pi / 1000, n_outer: int = 400):
+    """The paper's 2-D precompute (Section 4.1): on [0, eps] and [2 pi - eps, 2 pi]
+    the exponential of eq. FF2D1 is replaced by its second-order Taylor
+    polynomial and integrated exactly; [eps, 2 pi - eps] by plain quadrature.
+    An approximation of F whose error is reported, not used for parity.
+
+    The two end pieces together (the odd terms in y cancel): in t = sin^2(th/2),
+    4c \\int_0^{t_eps} t^{-s-1/2}(1-t)^{-r-1/2} [ i x - x^2 t - y^2 (1-t) ] dt,
+    written with incomplete beta functions (needs s, r < 1/2)."""
+    from numpy.polynomial.legendre import leggauss
+    from scipy.special import beta as beta_fn, betainc
+    s, r, c = kern.s, kern.r, kern.c
+    te = math.sin(0.5 * eps) ** 2
+
+    def ib(p_, q_):   # \\int_0^te t^{p-1} (1-t)^{q-1} dt
+        return betainc(p_, q_, te) * beta_fn(p_, q_)
+
+    ends = 4.0 * c * (1j * x * ib(0.5 - s, 0.5 - r) - x * x * ib(1.5 - s, 0.5 - r) - y * y * ib(0.5 - s, 1.5 - r))
+    u, wu = leggauss(n_outer)
+    mid = 0.0j
+    for a, b_ in ((eps, math.pi), (math.pi, 2.0 * math.pi - eps)):
+        th = a + 0.5 * (b_ - a) * (u + 1.0)
+        t = np.sin(0.5 * th) ** 2
+        bb = c * t ** (-1.0 - s) * (1.0 - t) ** (-r)
+        mid += 0.5 * (b_ - a) * np.sum(wu * bb * (np.exp(1j * (x * (1 - np.cos(th)) - y * np.sin(th))) - 1.0))
+    return ends + mid
 
 
 def bkw_lambda_2d(kern: AngularKernel, n: int = 200) -> float:

@@ -7,6 +7,8 @@ share none of its arithmetic.
     two halves of the circle folded together (theta and 2 pi - theta), which is
     what makes the integral converge for nu >= 1;
   - F(0) = 0, F(-x, y) = conj F(x, y), F(x, -y) = F(x, y);
+  - the paper's own precompute (epsilon split with Taylor ends, Section 4.1)
+    converges to it as epsilon shrinks;
 * the kernels of Section 5.2 as typed from their theta-forms, and their common
   BKW rate lambda = 1/8 (eq. KK2) by scipy quadrature of its definition;
 * a literal loop over eq. sum with G(l, m) of eq. GG and F integrated over the
@@ -80,6 +82,22 @@ def test_symmetries_and_zero(name):
     np.testing.assert_allclose(o2.psi2d(-x, y, kern), np.conj(F), rtol=0, atol=1e-13 * np.abs(F).max())
     np.testing.assert_allclose(o2.psi2d(x, -y, kern), F, rtol=0, atol=1e-13 * np.abs(F).max())
     assert o2.psi2d(0.0, 0.0, kern) == 0.0
+
+
+@pytest.mark.parametrize("name", KERNELS)
+def test_paper_eps_split_converges_to_exact_weight(name):
+    """Section 4.1's 2-D precompute: the Taylor ends drop the terms of order three
+    and up; the odd ones cancel between the two ends, so the first one left is of
+    order theta^4, and against b ~ theta^(-2-2s) it costs O(eps^(3-2s)).  A tenfold
+    smaller eps must shrink the error by that order (10^5 for b1 .. 316 for b4)."""
+    kern = o2.PAPER_KERNELS_2D[name]
+    order = 3.0 - 2.0 * kern.s
+    for x, y in ((5.0, 3.0), (-2.0, 9.0)):
+        exact = complex(o2.psi2d(x, y, kern))
+        errs = [abs(o2.F2d_eps_split(x, y, kern, eps=e, n_outer=600) - exact) / abs(exact)
+                for e in (math.pi / 100, math.pi / 1000)]
+        assert 0.7 * 10 ** order < errs[0] / errs[1] < 1.4 * 10 ** order, (name, x, y, errs)
+        assert errs[1] < 1e-5, (name, x, y, errs)
 
 
 # ------------------------------------------------------------ kernels, lambda
