@@ -346,4 +346,30 @@ __host__ __device__ __forceinline__ void dft_half_dif(Get get, cx<T>* u) {
   fft_reg<Q, SIGN>(u);
 }
 
+// A quarter of a length-P transform, P = 4 Q4, by one radix-4 decimation step
+// in frequency: with u[n] = w_P^{R n} sum_{a < 4} i^{SIGN a R} x[n + a Q4],
+// n < Q4, the outputs of class R are X[4j + R] = DFT_Q4(u)[j].  `get(n)` as
+// for dft_half_dif.  On return u[j] = X[4j + R].
+template <int P, int SIGN, int R, typename T, typename Get>
+__host__ __device__ __forceinline__ void dft_quarter_dif(Get get, cx<T>* u) {
+  constexpr int Q4 = P / 4;
+  static_assert(P % 4 == 0 && R >= 0 && R < 4, "quarter split needs P = 4 Q4 and R < 4");
+#pragma unroll
+  for (int n = 0; n < Q4; ++n) {
+    const cx<T> x0 = get(n), x1 = get(n + Q4), x2 = get(n + 2 * Q4), x3 = get(n + 3 * Q4);
+    cx<T> v;
+    if constexpr (R == 0) {
+      v = cadd(cadd(x0, x2), cadd(x1, x3));
+    } else if constexpr (R == 2) {
+      v = csub(cadd(x0, x2), cadd(x1, x3));
+    } else if constexpr (R == 1) {
+      v = cadd(csub(x0, x2), rot<SIGN>(csub(x1, x3)));      // i^{SIGN a}: 1, i^SIGN, -1, -i^SIGN
+    } else {
+      v = cadd(csub(x0, x2), rot<-SIGN>(csub(x1, x3)));     // i^{3 SIGN a}: 1, i^-SIGN, -1, -i^-SIGN
+    }
+    u[n] = twiddle_mul<P, SIGN>(v, n * R);
+  }
+  fft_reg<Q4, SIGN>(u);
+}
+
 }  // namespace bzq

@@ -549,6 +549,46 @@ __device__ __forceinline__ void half_rows_fwd(const cx<T>* row, cx<T>* __restric
   }
 }
 
+// The row passes of the plane have only N - 1 rows, one wave's worth: with
+// the parity split half of the workgroup's waves would sit idle in them.  At
+// P = 96 (four waves) each wave takes one class R of a radix-4 decimation in
+// frequency instead (outputs 4j + R, dft_quarter_dif), so all four work.
+template <int P>
+struct QuarterRows {
+  static constexpr bool value = P == 96;
+};
+
+template <typename T, int N, int P, int R>
+__device__ __forceinline__ void quarter_rows_inv(const cx<T>* __restrict__ Ain, cx<T>* row) {
+  constexpr int n1 = N - 1, Q4 = P / 4;
+  cx<T> u[Q4];
+  dft_quarter_dif<P, +1, R>(
+      [&](int n) -> cx<T> {
+        const int i2 = keptK<N, P>(n);
+        return i2 >= 0 ? ld_nt(Ain + (size_t)i2 * n1) : cx<T>{0, 0};
+      },
+      u);
+#pragma unroll
+  for (int j = 0; j < Q4; ++j) row[4 * j + R] = u[j];
+}
+
+template <typename T, int N, int P, int R>
+__device__ __forceinline__ void quarter_rows_fwd(const cx<T>* row, cx<T>* __restrict__ Bout, int k1) {
+  constexpr int n1 = N - 1, nn = n1 * n1, Q4 = P / 4;
+  constexpr int nhp = ((nn + 1) / 2 + 15) / 16 * 16, cmid = (nn - 1) / 2;
+  cx<T> u[Q4];
+  dft_quarter_dif<P, -1, R>([&](int n) -> cx<T> { return row[n]; }, u);
+#pragma unroll
+  for (int j = 0; j < Q4; ++j) {
+    const int k2 = keptK<N, P>(4 * j + R);
+    if (k2 >= 0) {
+      const int c = k2 * n1 + k1;
+      st_nt(Bout + (c <= cmid ? c : nhp + (nn - 1 - c)), u[j]);
+      if (c == cmid) st_nt(Bout + nhp + cmid, u[j]);
+    }
+  }
+}
+
 // Modulation and inverse FFT along axis 3 with two waves per 64 pencils: both
 // waves form the modulated pencil (63 values), the wave of parity PAR
 // transforms it to the heights z = 2j + PAR (dft_half_dif).
@@ -615,7 +655,19 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
   const int z = blockIdx.x, pt = blockIdx.y;
   const int par = __builtin_amdgcn_readfirstlane((int)threadIdx.x / (64 * C::WPP));
   const int l = (int)threadIdx.x - par * 64 * C::WPP;
-  if (l < n1) {
+  constexpr bool quarter = QuarterRows<P>::value;
+  static_assert(!quarter || (C::NT == 256 && n1 <= 64), "quarter rows need four waves and one row per lane");
+  const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
+  if constexpr (quarter) {
+    if (lq < n1) {
+      const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + lq;
+      cx<T>* row = sm + lq * LD;
+      if (wq == 0) quarter_rows_inv<T, N, P, 0>(Ain, row);
+      else if (wq == 1) quarter_rows_inv<T, N, P, 1>(Ain, row);
+      else if (wq == 2) quarter_rows_inv<T, N, P, 2>(Ain, row);
+      else quarter_rows_inv<T, N, P, 3>(Ain, row);
+    }
+  } else if (l < n1) {
     const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + l;
     if (par == 0) half_rows_inv<T, N, P, 0>(Ain, sm + l * LD);
     else half_rows_inv<T, N, P, 1>(Ain, sm + l * LD);
@@ -664,8 +716,16 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
     else half_cols_store<T, N, P, 1>(u, sm + l);
   }
   __syncthreads();
-  if (l < n1) {
-    cx<T>* Bout = B + ((size_t)pt * P + z) * 2 * (((nn + 1) / 2 + 15) / 16 * 16);
+  cx<T>* Bout = B + ((size_t)pt * P + z) * 2 * (((nn + 1) / 2 + 15) / 16 * 16);
+  if constexpr (quarter) {
+    if (lq < n1) {
+      const cx<T>* row = sm + lq * LD;
+      if (wq == 0) quarter_rows_fwd<T, N, P, 0>(row, Bout, lq);
+      else if (wq == 1) quarter_rows_fwd<T, N, P, 1>(row, Bout, lq);
+      else if (wq == 2) quarter_rows_fwd<T, N, P, 2>(row, Bout, lq);
+      else quarter_rows_fwd<T, N, P, 3>(row, Bout, lq);
+    }
+  } else if (l < n1) {
     if (par == 0) half_rows_fwd<T, N, P, 0>(sm + l * LD, Bout, l);
     else half_rows_fwd<T, N, P, 1>(sm + l * LD, Bout, l);
   }

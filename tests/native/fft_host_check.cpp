@@ -103,6 +103,39 @@ double check_dit_exchange() {
   return err;
 }
 
+// quarter transforms by one radix-4 decimation step in frequency: outputs 4j + R
+template <int P, int SIGN, int R>
+double check_quarter() {
+  std::mt19937_64 g(P * 17 + SIGN * 5 + R);
+  std::uniform_real_distribution<double> ud(-1, 1);
+  cx<double> x[P];
+  for (int i = 0; i < P; ++i) x[i] = {ud(g), ud(g)};
+  cx<double> u[P / 4];
+  dft_quarter_dif<P, SIGN, R>([&](int n) { return x[n]; }, u);
+  double err = 0;
+  for (int j = 0; j < P / 4; ++j) {
+    const int k = 4 * j + R;
+    C acc = 0;
+    for (int n = 0; n < P; ++n) {
+      long double a = SIGN * 2.0L * 3.141592653589793238462643383279502884L * ((long double)n * k) / P;
+      acc += C(x[n].x, x[n].y) * C(cosl(a), sinl(a));
+    }
+    err = std::fmax(err, (double)std::abs(C(u[j].x, u[j].y) - acc));
+  }
+  return err;
+}
+
+#define QUARTER(P)                                                                                    \
+  {                                                                                                   \
+    double e = 0;                                                                                     \
+    e = std::fmax(e, std::fmax(check_quarter<P, -1, 0>(), check_quarter<P, -1, 1>()));              \
+    e = std::fmax(e, std::fmax(check_quarter<P, -1, 2>(), check_quarter<P, -1, 3>()));              \
+    e = std::fmax(e, std::fmax(check_quarter<P, +1, 0>(), check_quarter<P, +1, 1>()));              \
+    e = std::fmax(e, std::fmax(check_quarter<P, +1, 2>(), check_quarter<P, +1, 3>()));              \
+    std::printf("P=%d quarter=%.3e\n", P, e);                                                       \
+    worst = std::fmax(worst, e / std::sqrt((double)P));                                               \
+  }
+
 #define HALF(P)                                                                                       \
   {                                                                                                   \
     double e = std::fmax(std::fmax(check_half<P, -1, 0>(), check_half<P, -1, 1>()),                  \
@@ -123,6 +156,7 @@ int main() {
   double worst = 0;
   RUN(8) RUN(12) RUN(16) RUN(24) RUN(32) RUN(36) RUN(48) RUN(64) RUN(72) RUN(96)
   HALF(48) HALF(72) HALF(96)
+  QUARTER(32) QUARTER(48) QUARTER(96)
   std::printf("worst %.3e\n", worst);
   return worst < 1e-14 ? 0 : 1;
 }
