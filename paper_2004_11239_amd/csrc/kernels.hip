@@ -87,6 +87,22 @@ __device__ __forceinline__ cx<T> to_cx(double2 v) {
   return {(T)v.x, (T)v.y};
 }
 __device__ __forceinline__ cx<double> d2c(double2 v) { return {v.x, v.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cvt(cx<double> v) {
+  return {(T)v.x, (T)v.y};
+}
+// Element i of an array whose base is the same for the whole wave, addressed
+// by a 32-bit offset: the access takes the scalar-base plus vector-offset form,
+// so unrolled loops over strided elements do not hold one 64-bit address
+// constant per element in scalar registers.  The byte offset must be < 2^32.
+template <typename U>
+__device__ __forceinline__ U* at32(U* base, unsigned i) {
+  return reinterpret_cast<U*>(reinterpret_cast<char*>(base) + i * (unsigned)sizeof(U));
+}
+template <typename U>
+__device__ __forceinline__ const U* at32(const U* base, unsigned i) {
+  return reinterpret_cast<const U*>(reinterpret_cast<const char*>(base) + i * (unsigned)sizeof(U));
+}
 
 struct RowAddr {
   int ld;
@@ -331,22 +347,29 @@ __global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, c
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
   fc += blockIdx.z * cs.fc;
   A += blockIdx.z * cs.a;
+  const int pt = blockIdx.y;
+  // axis-3 factors of the pair-two in LDS, in the compute type (see k_zinv_half)
+  __shared__ cx<T> s3[MODE == ZINV_PAIRS ? 2 * n1 : 1];
+  const double2* phA = MODE == ZINV_PAIRS ? ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2) : nullptr;
+  const double2* phB = MODE == ZINV_PAIRS ? phA + 3 * PL : nullptr;
+  if constexpr (MODE == ZINV_PAIRS) {
+    for (int t = threadIdx.x; t < 2 * n1; t += NT) {
+      const int i3 = t < n1 ? t : t - n1;
+      s3[t] = to_cx<T>((t < n1 ? phA : phB)[2 * PL - 2 * (i3 - h + 1)]);
+    }
+    __syncthreads();
+  }
   const int c = blockIdx.x * NT + threadIdx.x;
   if (c >= nn) return;
-  const int pt = blockIdx.y;
   const int i2 = c / n1, i1 = c - i2 * n1;
   const int k1 = i1 - h + 1, k2 = i2 - h + 1;
   cx<T> v[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
-  cx<double> eA12 = {1.0, 0.0}, eB12 = {0.0, 0.0};
-  const double2* phA = nullptr;
-  const double2* phB = nullptr;
+  cx<T> eA12 = {1, 0}, eB12 = {0, 0};
   if constexpr (MODE == ZINV_PAIRS) {
-    phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
-    phB = phA + 3 * PL;
-    eA12 = cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2]));
-    eB12 = cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2]));
+    eA12 = cvt<T>(cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2])));
+    eB12 = cvt<T>(cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2])));
   }
 #pragma unroll
   for (int i3 = 0; i3 < n1; ++i3) {
@@ -354,9 +377,9 @@ __global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, c
     const cx<T> f = fc[(size_t)i3 * nn + c];
     cx<T> z;
     if constexpr (MODE == ZINV_PAIRS) {
-      const cx<double> eA = cmul(eA12, d2c(phA[2 * PL - 2 * k3]));
-      const cx<double> eB = cmul(eB12, d2c(phB[2 * PL - 2 * k3]));
-      const cx<T> m = {(T)(eA.x - eB.y), (T)(eA.y + eB.x)};     // E_A + i E_B
+      const cx<T> eA = cmul(eA12, s3[i3]);
+      const cx<T> eB = cmul(eB12, s3[n1 + i3]);
+      const cx<T> m = {eA.x - eB.y, eA.y + eB.x};     // E_A + i E_B
       z = cmul(f, m);
     } else if constexpr (MODE == ZINV_GRID_SIGN) {
       z = ((k1 + k2 + k3) & 1) ? cx<T>{-f.x, -f.y} : f;
@@ -592,47 +615,58 @@ __device__ __forceinline__ void quarter_rows_fwd(const cx<T>* row, cx<T>* __rest
 // Modulation and inverse FFT along axis 3 with two waves per 64 pencils: both
 // waves form the modulated pencil (63 values), the wave of parity PAR
 // transforms it to the heights z = 2j + PAR (dft_half_dif).
+// The axis-3 factors of the two pairs are the same for every lane: they are
+// staged once per workgroup in LDS (sA3, sB3, by i3).  The modulation runs in
+// the compute type: the factors are unit complex numbers computed in FP64, and
+// one product of two of them rounded to FP32 is as accurate as the FP32 input
+// it multiplies.
 template <typename T, int N, int P, int PAR>
-__device__ __forceinline__ void zinv_half_body(const cx<T>* __restrict__ fcc, const double2* __restrict__ phA,
-                                               const double2* __restrict__ phB, cx<double> eA12,
-                                               cx<double> eB12, cx<T>* __restrict__ Aout) {
-  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3, Q = P / 2;
+__device__ __forceinline__ void zinv_half_body(const cx<T>* __restrict__ fcb, unsigned c, const cx<T>* sA3,
+                                               const cx<T>* sB3, cx<T> eA12, cx<T> eB12,
+                                               cx<T>* __restrict__ Ab) {
+  constexpr int nn = (N - 1) * (N - 1), Q = P / 2;
   cx<T> u[Q];
   dft_half_dif<P, +1, PAR>(
       [&](int n) -> cx<T> {
         const int i3 = keptK<N, P>(n);
         if (i3 < 0) return cx<T>{0, 0};
-        const int k3 = i3 - h + 1;
-        const cx<T> f = fcc[(size_t)i3 * nn];
-        const cx<double> eA = cmul(eA12, d2c(phA[2 * PL - 2 * k3]));
-        const cx<double> eB = cmul(eB12, d2c(phB[2 * PL - 2 * k3]));
-        const cx<T> m = {(T)(eA.x - eB.y), (T)(eA.y + eB.x)};     // E_A + i E_B
+        const cx<T> f = *at32(fcb, c + (unsigned)(i3 * nn));
+        const cx<T> eA = cmul(eA12, sA3[i3]);
+        const cx<T> eB = cmul(eB12, sB3[i3]);
+        const cx<T> m = {eA.x - eB.y, eA.y + eB.x};     // E_A + i E_B
         return cmul(f, m);
       },
       u);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) Aout[(size_t)(2 * j + PAR) * nn] = u[j];
+  for (int j = 0; j < Q; ++j) *at32(Ab, c + (unsigned)((2 * j + PAR) * nn)) = u[j];
 }
 
 template <typename T, int N, int P>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_zinv_half(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
                                                    cx<T>* __restrict__ A, int pair0, CellStrides cs) {
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
+  static_assert((size_t)P * nn * sizeof(cx<T>) < (1ull << 32), "32-bit offsets");
   fc += blockIdx.z * cs.fc;
   A += blockIdx.z * cs.a;
+  const int pt = blockIdx.y;
+  const double2* phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
+  const double2* phB = phA + 3 * PL;
+  __shared__ cx<T> s3[2 * n1];   // axis-3 factors of pair A (i3 < n1), then of pair B
+  for (int t = threadIdx.x; t < 2 * n1; t += 128) {
+    const int i3 = t < n1 ? t : t - n1;
+    s3[t] = to_cx<T>((t < n1 ? phA : phB)[2 * PL - 2 * (i3 - h + 1)]);
+  }
+  __syncthreads();
   const int par = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int c = blockIdx.x * 64 + (threadIdx.x & 63);
   if (c >= nn) return;
-  const int pt = blockIdx.y;
   const int i2 = c / n1, i1 = c - i2 * n1;
   const int k1 = i1 - h + 1, k2 = i2 - h + 1;
-  const double2* phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
-  const double2* phB = phA + 3 * PL;
-  const cx<double> eA12 = cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2]));
-  const cx<double> eB12 = cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2]));
-  cx<T>* Aout = A + (size_t)pt * P * nn + c;
-  if (par == 0) zinv_half_body<T, N, P, 0>(fc + c, phA, phB, eA12, eB12, Aout);
-  else zinv_half_body<T, N, P, 1>(fc + c, phA, phB, eA12, eB12, Aout);
+  const cx<T> eA12 = cvt<T>(cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2])));
+  const cx<T> eB12 = cvt<T>(cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2])));
+  cx<T>* Ab = A + (size_t)pt * P * nn;
+  if (par == 0) zinv_half_body<T, N, P, 0>(fc, (unsigned)c, s3, s3 + n1, eA12, eB12, Ab);
+  else zinv_half_body<T, N, P, 1>(fc, (unsigned)c, s3, s3 + n1, eA12, eB12, Ab);
 }
 
 // One (pair-two, z) plane per workgroup, as k_plane_reg (mode PLANE_PRODUCT).
