@@ -137,10 +137,18 @@ int effective_variant(const Plan& p, int stage) {
   return p.var[stage] ? p.var[stage] : stage_default_variant(stage, p.P, p.fp32);
 }
 
+// z-forward workgroup targets a schedule can choose
+constexpr int kSTargets[3] = {512, 1024, 2048};
+
 // Splits of the z-forward stage for kernel variant zv: about s_target
 // workgroups of tq pencils, at most one per group of pair-twos.  Pipelined
 // kernel: 32 pencils, one pair-two per step; other register kernels: 32 or 16
 // pencils, 2 or 4 pair-twos per step; LDS kernels (FP64 P > 48): 8 pencils.
+// When the kernel's residency is known and at most s_target, the workgroups
+// fill whole rounds of the chip: s_target is rounded down to a multiple of the
+// resident workgroups and S down to what fits it, so that no launch ends with
+// a nearly empty round (64^3 FP32: 1008 workgroups on 512 slots instead of
+// 1071).  S never exceeds its value without the rounding.
 int zfwd_splits(const Plan& p, int zv, int s_target) {
   const bool pipe = zv == 2 && (p.P == 48 || p.P == 72 || p.P == 96);
   const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
@@ -148,6 +156,8 @@ int zfwd_splits(const Plan& p, int zv, int s_target) {
   const int pt_group = pipe ? 1 : reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
   const int groups = (p.G + pt_group - 1) / pt_group;
   const int tiles = (p.nh + tq - 1) / tq;
+  const int slots = p.cus * (zv >= 1 && zv <= 2 ? p.zfwd_bpc[zv] : 0);
+  if (slots > 0 && slots <= s_target) return std::max(1, std::min(groups, s_target / slots * slots / tiles));
   return std::max(1, std::min(groups, (s_target + tiles - 1) / tiles));
 }
 
@@ -171,7 +181,8 @@ void set_chunking(Plan& p) {
   p.S = zfwd_splits(p, effective_variant(p, 2), p.s_target);
   p.S_cap = p.S;
   for (int v = 1; v <= 2; ++v)
-    if (stage_variants(2, p.P, p.fp32) >> v & 1) p.S_cap = std::max(p.S_cap, zfwd_splits(p, v, 2048));
+    if (stage_variants(2, p.P, p.fp32) >> v & 1)
+      for (int t : kSTargets) p.S_cap = std::max(p.S_cap, zfwd_splits(p, v, t));
 }
 
 // Device bytes a plan will hold (tables, its workspace, grid scratch), from
@@ -221,6 +232,8 @@ bzq_status derive_plan(const Plan& base, double gamma, bzq_plan* out, hipStream_
   p->npairs = base.npairs; p->npt = base.npt; p->G = base.G; p->S = base.S; p->S_cap = base.S_cap;
   for (int i = 0; i < 3; ++i) p->var[i] = base.var[i];
   p->s_target = base.s_target; p->esz = base.esz;
+  p->cus = base.cus;
+  for (int i = 0; i < 3; ++i) p->zfwd_bpc[i] = base.zfwd_bpc[i];
   p->otf = base.otf; p->mt = base.mt; p->Gw = base.Gw; p->Mh = base.Mh; p->nreal = base.nreal;
   p->ncoef = base.ncoef; p->coef = base.coef; p->pdv = base.pdv; p->terms = base.terms;
   p->V = base.V; p->ph = base.ph; p->tw_pad = base.tw_pad; p->tw_grid = base.tw_grid;
@@ -388,6 +401,17 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
         ph[o] = (double)cosl(ang);
         ph[o + 1] = (double)sinl(ang);
       }
+  }
+  // residency of the z-forward kernels on this device (sizes the splits S)
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+      for (int v = 1; v <= 2; ++v)
+        if (stage_variants(2, p->P, p->fp32) >> v & 1) p->zfwd_bpc[v] = zfwd_blocks_per_cu(p->P, p->fp32, v);
+    } else {
+      p->cus = 0;
+    }
   }
   set_chunking(*p);
   // -- tables
@@ -662,8 +686,6 @@ bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* str
 }
 
 namespace {
-
-constexpr int kSTargets[3] = {512, 1024, 2048};
 
 int encode_schedule(const Plan& p) {
   int t = 0;

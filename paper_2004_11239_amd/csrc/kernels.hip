@@ -1478,6 +1478,30 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
   return hipGetLastError();
 }
 
+template <typename T, int P>
+int zfwd_blocks_t(int variant) {
+  const int v = variant ? variant : defaultVariant<T, P>(2);
+  int nb = 0;
+  hipError_t e = hipSuccess;
+  bool done = false;
+  if constexpr (hasTwo<P>())
+    if (v == 2) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&k_zfwd_pipe<T, padN<P>(), P>), ZfwdPipeCfg<P>::NT, 0);
+      done = true;
+    }
+  if constexpr (RegFit<T, P>::value && isPad<P>())
+    if (!done) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&k_zfwd_reg<T, padN<P>(), P>), ZfwdCfg<T, P>::NT, 0);
+      done = true;
+    }
+  if (!done)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_zfwd<T, P, NT_SMALL>),
+                                                     NT_SMALL, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
 #define BZQ_ALL_P(X) X(8) X(12) X(16) X(24) X(32) X(36) X(48) X(64) X(72) X(96)
 #define BZQ_PAD_P(X) X(12) X(24) X(36) X(48) X(72) X(96)
 
@@ -1527,6 +1551,15 @@ hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const dou
   switch (g.P) { BZQ_PAD_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
+}
+
+int zfwd_blocks_per_cu(int P, bool fp32, int variant) {
+#define CASE(PP) \
+  case PP:       \
+    return fp32 ? zfwd_blocks_t<float, PP>(variant) : zfwd_blocks_t<double, PP>(variant);
+  switch (P) { BZQ_PAD_P(CASE) }
+#undef CASE
+  return 0;
 }
 
 int stage_default_variant(int stage, int P, bool fp32) {

@@ -61,6 +61,10 @@ hipError_t launch_zfwd(const void* B, const void* V, const double* phase, const 
                        bool fp32, const CellStrides& cs, hipStream_t st, int variant = 0, int vpair0 = 0,
                        bool first = false);
 
+// Workgroups of the z-forward kernel of `variant` (0 = default) that one
+// compute unit holds at once on the current device (0 if the query fails).
+int zfwd_blocks_per_cu(int P, bool fp32, int variant);
+
 // Weights of pairs j0 .. j0+nj-1 into Vc[j - j0][n1][nh] (compute precision)
 // from the series of the angular weight in Chebyshev form:
 // Re(e^{-ix} F) = sum_k coef[p][n][k] T_k(2 t^2 - 1), t = k.sigma/|k|, for

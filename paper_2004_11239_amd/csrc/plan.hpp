@@ -76,6 +76,10 @@ struct Plan {
   // default, see stage_variants) and the z-forward workgroups aimed at
   int var[3] = {0, 0, 0};
   int s_target = 1024;
+  // compute units of the plan's device and the z-forward workgroups one of
+  // them holds, per kernel variant (0: unknown)
+  int cus = 0;
+  int zfwd_bpc[3] = {0, 0, 0};
   size_t esz = 0;   // bytes per real element (4 or 8)
   std::vector<double> pair_host;  // [npairs][6] for introspection
   // weights on the fly: no table V; per chunk, k_wgen evaluates the series
