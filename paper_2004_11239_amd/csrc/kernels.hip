@@ -116,6 +116,39 @@ struct ColAddr {
   __device__ int operator()(int p) const { return p; }
 };
 
+// Adds a thread's FP64 sums acc[b] into Qpart[idx(b)] (idx < 0: none), or
+// writes them when `first`.  Every old value is read before any is written
+// (in one read-add-write loop each read would wait for the write before it,
+// since the compiler cannot tell that the elements differ), and the sums are
+// formed outside the guarded stores, so that no store waits for the one
+// before it.
+template <int OPT, typename Idx>
+__device__ __forceinline__ void add_partials(double2* __restrict__ Qpart, const double* accx,
+                                             const double* accy, bool first, Idx idx) {
+  long long qi[OPT];
+  double2 v[OPT];
+#pragma unroll
+  for (int b = 0; b < OPT; ++b) {
+    qi[b] = idx(b);
+    v[b] = double2{0.0, 0.0};
+  }
+  if (!first) {
+#pragma unroll
+    for (int b = 0; b < OPT; ++b)
+      if (qi[b] >= 0) v[b] = Qpart[qi[b]];
+  }
+#pragma unroll
+  for (int b = 0; b < OPT; ++b) {
+    v[b] = double2{v[b].x + accx[b], v[b].y + accy[b]};
+    // an empty statement that uses the sums keeps them from being moved into
+    // the guarded stores (where each would wait for the store before it)
+    asm volatile("" ::"v"(v[b].x), "v"(v[b].y));
+  }
+#pragma unroll
+  for (int b = 0; b < OPT; ++b)
+    if (qi[b] >= 0) Qpart[qi[b]] = v[b];
+}
+
 // ------------------------------------------------------------------ ingest
 template <typename T>
 __global__ void k_ingest(PtrPack fin, cx<T>* __restrict__ fc, size_t fc_stride, int N) {
@@ -302,18 +335,12 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int b = 0; b < OPT; ++b) {
+  add_partials<OPT>(Qpart, accx, accy, first, [&](int b) -> long long {
     const int o = threadIdx.x + b * NT;
-    if (o < nq * n1) {
-      const int q = o / n1, i3 = o - q * n1;
-      const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + q;
-      double2 v = first ? double2{0.0, 0.0} : Qpart[qi];
-      v.x += accx[b];
-      v.y += accy[b];
-      Qpart[qi] = v;
-    }
-  }
+    if (o >= nq * n1) return -1;
+    const int q = o / n1, i3 = o - q * n1;
+    return ((long long)s * n1 + i3) * nh + c0 + q;
+  });
 }
 
 
@@ -921,18 +948,12 @@ __global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
       }
       lds_barrier();
     }
-#pragma unroll
-    for (int bb = 0; bb < OPT; ++bb) {
+    add_partials<OPT>(Qpart, accx, accy, first, [&](int bb) -> long long {
       const int o = t + bb * NC;
       const int i3 = o / TQ, qq = o - i3 * TQ;
-      if (o < TQ * n1 && c0 + qq < nh) {
-        const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + qq;
-        double2 v = first ? double2{0.0, 0.0} : Qpart[qi];
-        v.x += accx[bb];
-        v.y += accy[bb];
-        Qpart[qi] = v;
-      }
-    }
+      if (!(o < TQ * n1 && c0 + qq < nh)) return -1;
+      return ((long long)s * n1 + i3) * nh + c0 + qq;
+    });
   }
 }
 
@@ -1039,20 +1060,13 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int b = 0; b < OPT; ++b) {
+  add_partials<OPT>(Qpart, accx, accy, first, [&](int b) -> long long {
     const int o = tid + b * NT;
-    if (o < TQ * n1) {
-      const int i3 = o / TQ, qq = o - i3 * TQ;
-      if (c0 + qq < nh) {
-        const size_t qi = ((size_t)s * n1 + i3) * nh + c0 + qq;
-        double2 v = first ? double2{0.0, 0.0} : Qpart[qi];
-        v.x += accx[b];
-        v.y += accy[b];
-        Qpart[qi] = v;
-      }
-    }
-  }
+    if (o >= TQ * n1) return -1;
+    const int i3 = o / TQ, qq = o - i3 * TQ;
+    if (c0 + qq >= nh) return -1;
+    return ((long long)s * n1 + i3) * nh + c0 + qq;
+  });
 }
 
 
