@@ -1071,43 +1071,48 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
 
 
 // ---------------------------------------------------------------- finalize
-// Four lanes per half-spectrum mode (c, i3) sum interleaved quarters of the S
-// partial accumulators; lane 0 adds the four quarter sums in fixed order and
-// writes Q(k) and, conjugated, Q(-k).  The centre pencil (k1 = k2 = 0) is
-// written from k3 >= 0 only, so Q(-k) is exactly conj Q(k) everywhere.  The
-// remaining threads zero the Nyquist planes.
+// Sixteen lanes per half-spectrum mode (c, i3), 16 modes per workgroup: lane
+// r (4 per wave, over the 4 waves) sums the partial accumulators s = r, r + 16,
+// ...; the first lane of the mode adds the 16 sums in a fixed order and writes
+// Q(k) and, conjugated, Q(-k).  The centre pencil (k1 = k2 = 0) is written
+// from k3 >= 0 only, so Q(-k) is exactly conj Q(k) everywhere.  The remaining
+// workgroups zero the Nyquist planes.
+constexpr int kFinModes = 16, kFinLanes = 16;
 __global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qpart, PtrPack qout, int N, int S,
                                                   size_t qp_stride) {
-  __shared__ double2 red[256];
+  __shared__ double2 red[kFinLanes][kFinModes];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, cmid = (nn - 1) / 2;
   Qpart += blockIdx.y * qp_stride;
   double2* __restrict__ Q = (double2*)qout.p[blockIdx.y];
   const int nmain = nh * n1;
   const int nnyq = 3 * N * N - 3 * N + 1;
-  const int lane = threadIdx.x & 3;
-  const int slotw = threadIdx.x >> 2;                  // 64 modes per block
-  const int nblk_main = (nmain + 63) / 64;
+  const int slot = threadIdx.x & (kFinModes - 1);                       // mode within the workgroup
+  const int lane = (threadIdx.x >> 6) * 4 + ((threadIdx.x >> 4) & 3);  // residue of s, 0..15
+  const int nblk_main = (nmain + kFinModes - 1) / kFinModes;
   if ((int)blockIdx.x < nblk_main) {
-    const int e = blockIdx.x * 64 + slotw;
+    const int e = blockIdx.x * kFinModes + slot;
     double x = 0.0, y = 0.0;
     if (e < nmain) {
       const int i3 = e / nh, c = e - i3 * nh;
-      for (int s = lane; s < S; s += 4) {
+      for (int s = lane; s < S; s += kFinLanes) {
         const double2 v = Qpart[((size_t)s * n1 + i3) * nh + c];
         x += v.x;
         y += v.y;
       }
     }
-    red[threadIdx.x] = double2{x, y};
+    red[lane][slot] = double2{x, y};
     __syncthreads();
-    if (lane == 0 && e < nmain) {
+    if (threadIdx.x < kFinModes && e < nmain) {
       const int i3 = e / nh, c = e - i3 * nh;
       const int i2 = c / n1, i1 = c - i2 * n1;
       const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
       if (c == cmid && k3 < 0) return;
-      const double2 a0 = red[threadIdx.x], a1 = red[threadIdx.x + 1], a2 = red[threadIdx.x + 2],
-                    a3 = red[threadIdx.x + 3];
-      const double sx = ((a0.x + a1.x) + a2.x) + a3.x, sy = ((a0.y + a1.y) + a2.y) + a3.y;
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int r = 0; r < kFinLanes; ++r) {
+        sx += red[r][slot].x;
+        sy += red[r][slot].y;
+      }
       const int a = (k1 + N) % N, b = (k2 + N) % N, d = (k3 + N) % N;
       const int am = (N - k1) % N, bm = (N - k2) % N, dm = (N - k3) % N;
       Q[((size_t)a * N + b) * N + d] = double2{sx, sy};
@@ -1595,7 +1600,7 @@ hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stri
                            hipStream_t st) {
   const size_t nh = ((size_t)(N - 1) * (N - 1) + 1) / 2;
   const size_t nmain = nh * (N - 1), nnyq = 3 * (size_t)N * N - 3 * N + 1;
-  dim3 grid((unsigned)((nmain + 63) / 64 + (nnyq + 255) / 256), cells);
+  dim3 grid((unsigned)((nmain + kFinModes - 1) / kFinModes + (nnyq + 255) / 256), cells);
   hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, st, (const double2*)Qpart, Q, N, S, qp_stride);
   return hipGetLastError();
 }
