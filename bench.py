@@ -392,8 +392,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "bench.py measures one GPU: this build has no multi-GPU path "
-                                   "(the pair-sharded design is described in DESIGN.md); run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU: the library has no multi-GPU path "
+                                   "(an evaluation would shard its quadrature pairs across GPUs and sum "
+                                   "the partial Q with one all-reduce); run with --gpus 1"}))
         sys.exit(2)
 
     import numpy as np
