@@ -491,9 +491,14 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
   const Geometry g{p.N, p.P};
   CellStrides cs = w.cs;
   cs.cells = cells;
-  TIMED(ST_PREP, launch_ingest(f, w.fc, cs.fc, cells, p.N, p.fp32, st));
-  // f(v) on the padded grid, shared by every pair
-  TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
+  // the compact spectrum fc, then f(v) on the padded grid, shared by every
+  // pair (the copy and the first transform in one launch where they fit)
+  if (zinv_ingest_fits(p.P, p.fp32)) {
+    TIMED(ST_PREP, launch_zinv_ingest(f, w.fc, w.A, g, p.fp32, cs, st));
+  } else {
+    TIMED(ST_PREP, launch_ingest(f, w.fc, cs.fc, cells, p.N, p.fp32, st));
+    TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
+  }
   TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st));
   // the first last-stage launch writes the S partial accumulators of every
   // cell, later ones add to them

@@ -421,6 +421,36 @@ __global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, c
   for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * nn] = v[zi];
 }
 
+// The first step of an evaluation in one launch: the compact copy of f (as
+// k_ingest) and its inverse transform along axis 3 (as k_zinv_reg in mode
+// ZINV_PLAIN, into the slot of pair-two 0); one thread per pencil c.
+template <typename T, int N, int P, int NT>
+__global__ __launch_bounds__(NT) void k_zinv_ingest(PtrPack fin, cx<T>* __restrict__ fc, cx<T>* __restrict__ A,
+                                                    CellStrides cs) {
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1;
+  const double2* __restrict__ f = (const double2*)fin.p[blockIdx.z];
+  fc += blockIdx.z * cs.fc;
+  A += blockIdx.z * cs.a;
+  const int c = blockIdx.x * NT + threadIdx.x;
+  if (c >= nn) return;
+  const int i2 = c / n1, i1 = c - i2 * n1;
+  const int a = (i1 - h + 1 + N) % N, b = (i2 - h + 1 + N) % N;
+  const double2* __restrict__ fp = f + ((size_t)a * N + b) * N;
+  cx<T> v[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
+#pragma unroll
+  for (int i3 = 0; i3 < n1; ++i3) {
+    const cx<T> x = to_cx<T>(fp[(i3 - h + 1 + N) % N]);
+    fc[(size_t)i3 * nn + c] = x;
+    v[posKc<N, P>(i3)] = x;
+  }
+  fft_reg<P, +1>(v);
+  cx<T>* Aout = A + c;
+#pragma unroll
+  for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * nn] = v[zi];
+}
+
 template <typename T, int P>
 struct PlaneCfg {
   static constexpr int Z = P == 8 ? 8 : P == 12 ? 12 : P == 16 ? 8 : P == 24 ? 8 : P == 32 ? 4
@@ -1383,6 +1413,18 @@ hipError_t zinv_reg_t(const void* fc, const double* ph, void* A, int pair0, int 
   return hipGetLastError();
 }
 
+template <typename T, int P>
+hipError_t zinv_ingest_t(const PtrPack& f, void* fc, void* A, int N, const CellStrides& cs, hipStream_t st) {
+  if constexpr (RegFit<T, P>::value && isPad<P>()) {
+    constexpr int NN = padN<P>(), nn = (NN - 1) * (NN - 1), NT = 64;
+    if (N != NN) return hipErrorInvalidValue;
+    dim3 grid((nn + NT - 1) / NT, 1, cs.cells);
+    hipLaunchKernelGGL((k_zinv_ingest<T, NN, P, NT>), grid, dim3(NT), 0, st, f, (cx<T>*)fc, (cx<T>*)A, cs);
+    return hipGetLastError();
+  }
+  return hipErrorNotSupported;
+}
+
 template <typename T, int P, int N>
 hipError_t plane_reg_t(const void* A, void* B, const void* fgrid, void* gridout, int npt, int mode,
                        const CellStrides& cs, hipStream_t st) {
@@ -1535,6 +1577,20 @@ hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells
   else
     hipLaunchKernelGGL(k_ingest<double>, grid, dim3(256), 0, st, f, (cx<double>*)fc, fc_stride, N);
   return hipGetLastError();
+}
+
+bool zinv_ingest_fits(int P, bool fp32) {
+  return (P == 12 || P == 24 || P == 36 || P == 48 || P == 72 || P == 96) && (fp32 ? 4 : 8) * P <= 4 * 96;
+}
+
+hipError_t launch_zinv_ingest(const PtrPack& f, void* fc, void* A, Geometry g, bool fp32, const CellStrides& cs,
+                              hipStream_t st) {
+#define CASE(PP) \
+  case PP:       \
+    return fp32 ? zinv_ingest_t<float, PP>(f, fc, A, g.N, cs, st) : zinv_ingest_t<double, PP>(f, fc, A, g.N, cs, st);
+  switch (g.P) { BZQ_PAD_P(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_zinv(const void* fc, const double* ph, void* A, const void* tw, Geometry g, int pair0,

@@ -37,6 +37,13 @@ struct PtrPack {
 hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells, int N, bool fp32,
                          hipStream_t st);
 
+// launch_ingest and launch_zinv(mode ZINV_PLAIN, one pair-two) in one launch,
+// for the lengths whose pencil fits the register file (zinv_ingest_fits):
+// fc as launch_ingest writes it, A[pair-two 0] as launch_zinv writes it.
+bool zinv_ingest_fits(int P, bool fp32);
+hipError_t launch_zinv_ingest(const PtrPack& f, void* fc, void* A, Geometry g, bool fp32, const CellStrides& cs,
+                              hipStream_t st);
+
 // Step 1 of the pipeline: modulate (mode ZINV_PAIRS) and inverse-transform along
 // axis 3; writes A[pt][z][c] for pt < npt, z < P, c < (N-1)^2.
 hipError_t launch_zinv(const void* fc, const double* phase, void* A, const void* tw, Geometry g,
