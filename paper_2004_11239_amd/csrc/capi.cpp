@@ -486,7 +486,7 @@ hipError_t mark(Plan& p, int stage, bool begin, hipStream_t st) {
 
 // Enqueue one evaluation of eq. realQ for `cells` cells of plan p.
 bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrPack& Q, int cells,
-                             hipStream_t st) {
+                             hipStream_t st, const FinUpdate& upd) {
   if (cells < 1 || cells > w.cells) return fail(BZQ_EINVAL, "more cells than the workspace holds");
   const Geometry g{p.N, p.P};
   CellStrides cs = w.cs;
@@ -523,7 +523,7 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
                                  p.var[2], 0, c0 == 0));
     }
   }
-  TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, p.S, st));
+  TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, p.S, st, upd));
   return BZQ_OK;
 }
 
@@ -536,12 +536,23 @@ bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, doub
     q2.p[c] = w.q2 + c * n3 * 2;
     fs.p[c] = w.fs + c * n3 * 2;
   }
+  // the two updates of the step ride on the finalize launches: fs = f + dt q1
+  // with the first evaluation, f += dt/2 (q1 + q2) with the second
+  FinUpdate stage, heun;
+  stage.mode = FIN_STAGE;
+  stage.a = dt;
+  stage.ws = w.fs;
+  stage.wstride = n3 * 2;
+  stage.f = f;
+  heun.mode = FIN_HEUN;
+  heun.a = 0.5 * dt;
+  heun.ws = w.q1;
+  heun.wstride = n3 * 2;
+  heun.f = f;
   for (int i = 0; i < n_steps; ++i) {
     bzq_status s;
-    if ((s = enqueue_collision(p, w, f, q1, cells, st)) != BZQ_OK) return s;
-    BZQ_HIP_TRY(launch_axpy_cells(fs, f, dt, q1, n3, cells, st));
-    if ((s = enqueue_collision(p, w, fs, q2, cells, st)) != BZQ_OK) return s;
-    BZQ_HIP_TRY(launch_heun_cells(f, q1, q2, 0.5 * dt, n3, cells, st));
+    if ((s = enqueue_collision(p, w, f, q1, cells, st, stage)) != BZQ_OK) return s;
+    if ((s = enqueue_collision(p, w, fs, q2, cells, st, heun)) != BZQ_OK) return s;
   }
   return BZQ_OK;
 }

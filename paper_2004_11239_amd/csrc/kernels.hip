@@ -1108,8 +1108,21 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
 // from k3 >= 0 only, so Q(-k) is exactly conj Q(k) everywhere.  The remaining
 // workgroups zero the Nyquist planes.
 constexpr int kFinModes = 16, kFinLanes = 16;
+// the fused update at element i of cell c where Q = (qx, qy)
+__device__ __forceinline__ void fin_update(const FinUpdate& u, int c, size_t i, double qx, double qy) {
+  double2* __restrict__ F = (double2*)u.f.p[c];
+  double2* __restrict__ W = (double2*)(u.ws + (size_t)c * u.wstride);
+  const double2 x = F[i];
+  if (u.mode == FIN_STAGE) {
+    W[i] = double2{x.x + u.a * qx, x.y + u.a * qy};
+  } else {
+    const double2 y = W[i];
+    F[i] = double2{x.x + u.a * (y.x + qx), x.y + u.a * (y.y + qy)};
+  }
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qpart, PtrPack qout, int N, int S,
-                                                  size_t qp_stride) {
+                                                  size_t qp_stride, FinUpdate upd) {
   __shared__ double2 red[kFinLanes][kFinModes];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, cmid = (nn - 1) / 2;
   Qpart += blockIdx.y * qp_stride;
@@ -1145,8 +1158,14 @@ __global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qp
       }
       const int a = (k1 + N) % N, b = (k2 + N) % N, d = (k3 + N) % N;
       const int am = (N - k1) % N, bm = (N - k2) % N, dm = (N - k3) % N;
-      Q[((size_t)a * N + b) * N + d] = double2{sx, sy};
-      if (k1 != 0 || k2 != 0 || k3 != 0) Q[((size_t)am * N + bm) * N + dm] = double2{sx, -sy};
+      const size_t ip = ((size_t)a * N + b) * N + d, im = ((size_t)am * N + bm) * N + dm;
+      const bool mirror = k1 != 0 || k2 != 0 || k3 != 0;
+      Q[ip] = double2{sx, sy};
+      if (mirror) Q[im] = double2{sx, -sy};
+      if (upd.mode != FIN_NONE) {
+        fin_update(upd, blockIdx.y, ip, sx, sy);
+        if (mirror) fin_update(upd, blockIdx.y, im, sx, -sy);
+      }
     }
     return;
   }
@@ -1157,6 +1176,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qp
     else if ((r -= N * N) < N * (N - 1)) { a = r / N; a += a >= h; b = h; d = r % N; }
     else { r -= N * (N - 1); a = r / (N - 1); a += a >= h; b = r % (N - 1); b += b >= h; d = h; }
     Q[((size_t)a * N + b) * N + d] = double2{0.0, 0.0};
+    if (upd.mode != FIN_NONE) fin_update(upd, blockIdx.y, ((size_t)a * N + b) * N + d, 0.0, 0.0);
   }
 }
 
@@ -1653,11 +1673,11 @@ unsigned stage_variants(int stage, int P, bool fp32) {
 }
 
 hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,
-                           hipStream_t st) {
+                           hipStream_t st, const FinUpdate& upd) {
   const size_t nh = ((size_t)(N - 1) * (N - 1) + 1) / 2;
   const size_t nmain = nh * (N - 1), nnyq = 3 * (size_t)N * N - 3 * N + 1;
   dim3 grid((unsigned)((nmain + kFinModes - 1) / kFinModes + (nnyq + 255) / 256), cells);
-  hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, st, (const double2*)Qpart, Q, N, S, qp_stride);
+  hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, st, (const double2*)Qpart, Q, N, S, qp_stride, upd);
   return hipGetLastError();
 }
 

@@ -89,9 +89,25 @@ hipError_t launch_wgen(void* Vc, const double* coef, const double* pdv, const in
 unsigned stage_variants(int stage, int P, bool fp32);
 int stage_default_variant(int stage, int P, bool fp32);
 
-// Sum of the S partial accumulators and Hermitian completion into Q (N^3 FFT order).
+// A time-step update fused into the finalize launch, applied at every element
+// the launch writes of Q (N^3 complex128 per cell, cell c of a workspace buffer
+// at ws + c * wstride doubles; f is the state):
+//   FIN_STAGE: ws = f + a Q       (ws: the intermediate state)
+//   FIN_HEUN:  f  = f + a (ws + Q) (ws: the first stage's Q)
+// the same arithmetic as launch_axpy_cells / launch_heun_cells.
+enum FinUpdateMode { FIN_NONE = 0, FIN_STAGE = 1, FIN_HEUN = 2 };
+struct FinUpdate {
+  int mode = FIN_NONE;
+  double a = 0.0;
+  double* ws = nullptr;
+  size_t wstride = 0;
+  PtrPack f{};
+};
+
+// Sum of the S partial accumulators and Hermitian completion into Q (N^3 FFT
+// order), with an optional fused update (FinUpdate).
 hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,
-                           hipStream_t st);
+                           hipStream_t st, const FinUpdate& upd = FinUpdate{});
 // per cell: out = x + a y and f += h (q1 + q2)  (n complex128 each)
 hipError_t launch_axpy_cells(const PtrPack& out, const PtrPack& x, double a, const PtrPack& y, size_t n,
                              int cells, hipStream_t st);

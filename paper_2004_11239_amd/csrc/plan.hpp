@@ -139,8 +139,9 @@ size_t plan_shared_bytes_estimate(int N, int N_rho, int M, int precision);
 double power_kernel_constant(double s);
 
 // Enqueue Q = Q(f) for `cells` cells sharing plan p, using workspace w.
+// With upd, the finalize launch also applies that time-step update.
 bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrPack& Q, int cells,
-                             hipStream_t st);
+                             hipStream_t st, const FinUpdate& upd = FinUpdate{});
 // Enqueue n_steps Heun steps in place for `cells` cells.
 bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
                         hipStream_t st);
