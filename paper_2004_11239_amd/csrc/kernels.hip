@@ -822,6 +822,184 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
   }
 }
 
+// The two-dimensional operator (d = 2) at P = 96 with the passes of
+// k_plane_half: workgroup s carries pair-two s through the whole pipeline in
+// one plane of LDS (one pair-two per workgroup: with a loop over several the
+// compiler keeps the loop-invariant addresses of every pass in registers and
+// spills).  Per pair-two: the y-factors of the two
+// pairs' phases staged in LDS; the four-way inverse row passes (axis 2) with
+// the modulation f_m (E_A(m) + i E_B(m)) formed on load; the two-parity
+// column pass (axis 1: inverse, product with f on the grid, forward, kept
+// modes); the four-way forward row passes, whose kept outputs go back into
+// their row after every row has been read; then the split of the two pairs,
+// the weights and the FP64 accumulation of the half-spectrum modes, as in the
+// LDS kernel of the 2-D path.  Layouts as there: compact spectra with mode
+// c = i2 (N-1) + i1, f on the grid [x][y], phases ph[pair][axis][2N-3].
+template <typename T, int N>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_collide2d_reg(const cx<T>* __restrict__ fc, const T* __restrict__ fgrid,
+                                                       const T* __restrict__ V, const double2* __restrict__ ph,
+                                                       const double* __restrict__ cp, double2* __restrict__ Qpart,
+                                                       int npt, int S) {
+  constexpr int P = 3 * N / 2, n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  constexpr int LD = P + 1, Q = P / 2, QH = Q / 2, Q4 = P / 4;
+  constexpr int OPT = (nh + 255) / 256;
+  static_assert(P == 96 && HalfCfg<P>::NT == 256 && n1 <= 64, "four waves, one row per lane");
+  __shared__ cx<T> sm[n1 * LD];
+  __shared__ cx<T> ey[2][n1];
+  const int s = blockIdx.x;
+  const int par = __builtin_amdgcn_readfirstlane((int)threadIdx.x / 128);
+  const int l = (int)threadIdx.x - par * 128;
+  const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
+  // the pair-two's contribution is this workgroup's row of Qpart
+  double2* __restrict__ Qs = Qpart + (size_t)s * nh;
+  if (s >= npt) {   // uniform over the workgroup
+    for (int c = threadIdx.x; c < nh; c += 256) Qs[c] = double2{0.0, 0.0};
+    return;
+  }
+  {
+    const int pt = s;
+    const int jA = 2 * pt, jB = jA + 1;
+    const double2* phA = ph + (size_t)jA * 2 * PL + (N - 2);
+    const double2* phB = phA + 2 * PL;
+    for (int t = threadIdx.x; t < 2 * n1; t += 256) {
+      const int i2 = t < n1 ? t : t - n1;
+      ey[t < n1 ? 0 : 1][i2] = to_cx<T>((t < n1 ? phA : phB)[PL - 2 * (i2 - h + 1)]);
+    }
+    __syncthreads();
+    // the modulated spectrum into the plane: row i1, column i2 (compact)
+#pragma unroll 2
+    for (int c = threadIdx.x; c < nn; c += 256) {
+      const int i2 = c / n1, i1 = c - i2 * n1;
+      const int k1 = i1 - h + 1;
+      const cx<T> eA = cmul(to_cx<T>(phA[-2 * k1]), ey[0][i2]), eB = cmul(to_cx<T>(phB[-2 * k1]), ey[1][i2]);
+      sm[i1 * LD + i2] = cmul(fc[c], cx<T>{eA.x - eB.y, eA.y + eB.x});
+    }
+    __syncthreads();
+    // rows: inverse along axis 2, row i1 = lq; every row is read before any output is written back
+    {
+      cx<T> u[Q4];
+      const cx<T>* row = sm + lq * LD;
+      auto get = [&](int n) -> cx<T> {
+        const int i2 = keptK<N, P>(n);
+        return i2 >= 0 ? row[i2] : cx<T>{0, 0};
+      };
+      if (lq < n1) {
+        if (wq == 0) dft_quarter_dif<P, +1, 0>(get, u);
+        else if (wq == 1) dft_quarter_dif<P, +1, 1>(get, u);
+        else if (wq == 2) dft_quarter_dif<P, +1, 2>(get, u);
+        else dft_quarter_dif<P, +1, 3>(get, u);
+      }
+      __syncthreads();
+      if (lq < n1) {
+        cx<T>* out = sm + lq * LD;
+        const int R = wq;
+#pragma unroll
+        for (int j = 0; j < Q4; ++j) out[4 * j + R] = u[j];
+      }
+    }
+    __syncthreads();
+    // columns (axis 1): as in k_plane_half
+    {
+      cx<T> u[Q];
+      const bool col = l < P;
+      if (col) {
+        const T* fz = fgrid + l;
+        if (par == 0) half_cols<T, N, P, 0>(sm + l, fz, u);
+        else half_cols<T, N, P, 1>(sm + l, fz, u);
+      }
+      __syncthreads();
+      cx<T>* xa = sm;
+      cx<T>* xb = sm + QH * P;
+      if (col) {
+        if (par == 0) {
+#pragma unroll
+          for (int i = 0; i < QH; ++i) xa[i * P + l] = u[QH + i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < QH; ++i) xb[i * P + l] = u[i];
+        }
+      }
+      __syncthreads();
+      if (col) {
+        if (par == 0) {
+#pragma unroll
+          for (int i = 0; i < QH; ++i) {
+            const cx<T> e = u[i], t = xb[i * P + l];
+            u[i] = cadd(e, t);
+            u[QH + i] = csub(e, t);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < QH; ++i) {
+            const cx<T> e = xa[i * P + l], t = u[QH + i];
+            u[i] = cadd(e, t);
+            u[QH + i] = csub(e, t);
+          }
+        }
+      }
+      __syncthreads();
+      if (col) {
+        if (par == 0) half_cols_store<T, N, P, 0>(u, sm + l);
+        else half_cols_store<T, N, P, 1>(u, sm + l);
+      }
+      __syncthreads();
+    }
+    // rows: forward along axis 2; every row is read before any output is written back
+    {
+      cx<T> u[Q4];
+      const cx<T>* row = sm + lq * LD;
+      auto get = [&](int n) -> cx<T> { return row[n]; };
+      if (lq < n1) {
+        if (wq == 0) dft_quarter_dif<P, -1, 0>(get, u);
+        else if (wq == 1) dft_quarter_dif<P, -1, 1>(get, u);
+        else if (wq == 2) dft_quarter_dif<P, -1, 2>(get, u);
+        else dft_quarter_dif<P, -1, 3>(get, u);
+      }
+      __syncthreads();
+      if (lq < n1) {
+        cx<T>* out = sm + lq * LD;
+        if (wq == 0) {
+#pragma unroll
+          for (int j = 0; j < Q4; ++j) if (keptK<N, P>(4 * j) >= 0) out[keptK<N, P>(4 * j)] = u[j];
+        } else if (wq == 1) {
+#pragma unroll
+          for (int j = 0; j < Q4; ++j) if (keptK<N, P>(4 * j + 1) >= 0) out[keptK<N, P>(4 * j + 1)] = u[j];
+        } else if (wq == 2) {
+#pragma unroll
+          for (int j = 0; j < Q4; ++j) if (keptK<N, P>(4 * j + 2) >= 0) out[keptK<N, P>(4 * j + 2)] = u[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < Q4; ++j) if (keptK<N, P>(4 * j + 3) >= 0) out[keptK<N, P>(4 * j + 3)] = u[j];
+        }
+      }
+      __syncthreads();
+    }
+    // the two pairs, the weights and the accumulation; mode (i1, i2) is sm[i1][i2]
+    // (two modes per thread at a time: unrolled fully, the loads of all eight
+    // would be hoisted and need more registers than the transforms)
+    const double cA = cp[jA], cB = cp[jB];
+#pragma unroll 2
+    for (int b = 0; b < OPT; ++b) {
+      const int c = threadIdx.x + b * 256;
+      if (c < nh) {
+        const int i2 = c / n1, i1 = c - i2 * n1;
+        const int k1 = i1 - h + 1, k2 = i2 - h + 1;
+        const cx<T> w1 = sm[i1 * LD + i2];
+        const cx<T> w2 = sm[(n1 - 1 - i1) * LD + (n1 - 1 - i2)];
+        // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
+        const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
+        const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
+        const double vA = cA * (double)V[(size_t)jA * nh + c];
+        const double vB = cB * (double)V[(size_t)jB * nh + c];
+        const cx<double> eA = cmul(d2c(phA[k1]), d2c(phA[PL + k2]));
+        const cx<double> eB = cmul(d2c(phB[k1]), d2c(phB[PL + k2]));
+        const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
+        Qs[c] = double2{0.0 + (vA * tA.x + vB * tB.x), 0.0 + (vA * tA.y + vB * tB.y)};
+      }
+    }
+  }
+}
+
 template <typename T, int N, int P, int PAR>
 __device__ __forceinline__ void zfwd_half_fft(const cx<T>* __restrict__ Bin, cx<T> (*Wp)[64], int r) {
   constexpr int n1 = N - 1, nn = n1 * n1, Q = P / 2;
@@ -1596,6 +1774,18 @@ hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells
     hipLaunchKernelGGL(k_ingest<float>, grid, dim3(256), 0, st, f, (cx<float>*)fc, fc_stride, N);
   else
     hipLaunchKernelGGL(k_ingest<double>, grid, dim3(256), 0, st, f, (cx<double>*)fc, fc_stride, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_collide2d_reg(const void* fc, const void* fgrid, const void* V, const double* ph, const double* cp,
+                                double* Qpart, int N, int npt, int S, bool fp32, hipStream_t st) {
+  if (N != 64 || S < npt) return hipErrorInvalidValue;   // one pair-two per workgroup
+  if (fp32)
+    hipLaunchKernelGGL((k_collide2d_reg<float, 64>), dim3(S), dim3(256), 0, st, (const cx<float>*)fc,
+                       (const float*)fgrid, (const float*)V, (const double2*)ph, cp, (double2*)Qpart, npt, S);
+  else
+    hipLaunchKernelGGL((k_collide2d_reg<double, 64>), dim3(S), dim3(256), 0, st, (const cx<double>*)fc,
+                       (const double*)fgrid, (const double*)V, (const double2*)ph, cp, (double2*)Qpart, npt, S);
   return hipGetLastError();
 }
 

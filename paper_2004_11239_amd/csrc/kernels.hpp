@@ -41,6 +41,13 @@ hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells
 // for the lengths whose pencil fits the register file (zinv_ingest_fits):
 // fc as launch_ingest writes it, A[pair-two 0] as launch_zinv writes it.
 bool zinv_ingest_fits(int P, bool fp32);
+
+// The two-dimensional operator's pipeline at N = 64 (P = 96) with register FFTs
+// (one workgroup of 256 threads per pair-two loop s, s + S, ...): fc and fgrid
+// as the 2-D prep writes them, V the 2-D weight table, ph the 2-D phases,
+// Qpart[S][nh] the partial sums (written).
+hipError_t launch_collide2d_reg(const void* fc, const void* fgrid, const void* V, const double* ph, const double* cp,
+                                double* Qpart, int N, int npt, int S, bool fp32, hipStream_t st);
 hipError_t launch_zinv_ingest(const PtrPack& f, void* fc, void* A, Geometry g, bool fp32, const CellStrides& cs,
                               hipStream_t st);
 

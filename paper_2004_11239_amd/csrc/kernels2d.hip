@@ -11,12 +11,15 @@
 // and c_p = w_rho rho^{1+gamma}, and FP64 accumulation in registers over the
 // pair-twos s, s + S, ... of workgroup s.  A last kernel sums the S partial
 // accumulators in a fixed order and completes the spectrum by Hermitian
-// symmetry.  The FFTs are the LDS Stockham passes of fft.hpp.
+// symmetry.  The FFTs are the LDS Stockham passes of fft.hpp; at N = 64 the
+// same pipeline runs with the register passes of the 3-D plane kernel
+// (k_collide2d_reg in kernels.hip).
 //
 // Layouts: compact spectra are centred, index i <-> k = i - (N/2 - 1); mode c =
 // i2 (N-1) + i1 (i1 fastest), mirror nn - 1 - c; the half spectrum is c <=
 // (nn - 1)/2.  In LDS the plane is buf[x (P+1) + y], x along axis 1.
 #include "fft.hpp"
+#include "kernels.hpp"
 #include "kernels2d.hpp"
 
 namespace bzq {
@@ -292,6 +295,9 @@ hipError_t collide2d_t(const double* f_hat, void* fc, void* fgrid, const void* V
                      (T*)fgrid, N);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // N = 64 with one pair-two per workgroup: the register-FFT pipeline (kernels.hip)
+  if constexpr (P == 96)
+    if (N == 64 && S >= npt) return launch_collide2d_reg(fc, fgrid, V, ph, cp, Qpart, N, npt, S, sizeof(T) == 4, st);
   hipLaunchKernelGGL((k_collide2d<T, P, NT>), dim3(S), dim3(NT), 0, st, (const cx<T>*)fc, (const T*)fgrid,
                      (const T*)V, (const double2*)ph, cp, (const cx<T>*)tw, (double2*)Qpart, N, npt, S);
   return hipGetLastError();
