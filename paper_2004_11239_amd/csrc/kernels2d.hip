@@ -95,13 +95,19 @@ __global__ void k_table2d(TV* __restrict__ V, const double* __restrict__ pd, con
 // grid column x2 = blockIdx.x: first R(k1) = sum_{k2} f_{k1 k2} e^{2 pi i k2 x2 / P}
 // for the N-1 mode rows, then f(x1, x2) = sum_{k1} R(k1) e^{2 pi i k1 x1 / P} for
 // all P rows: direct sums in FP64 (N (N + P) terms per column), rounded to T
-// once.  The workgroups also copy the compact spectrum fc (T precision).
+// once.  Each sum is split over kPrepSplitR (first) or kPrepSplitX (second)
+// threads, whose partial sums are added in a fixed order.  The workgroups
+// also copy the compact spectrum fc (T precision).
+constexpr int kPrepSplitR = 4, kPrepSplitX = 2;
 template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_prep2d(const double2* __restrict__ f, cx<T>* __restrict__ fc,
                                                T* __restrict__ fgrid, int N) {
   constexpr int N1MAX = (2 * P) / 3 - 1;
+  static_assert(NT >= kPrepSplitR * N1MAX && NT >= kPrepSplitX * P, "one partial sum per thread");
   __shared__ double2 tw[P];          // e^{+2 pi i m / P}
+  __shared__ double2 part[kPrepSplitR][N1MAX];
   __shared__ double2 row[N1MAX];
+  __shared__ double partx[kPrepSplitX][P];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1;
   const int x2 = blockIdx.x;
   for (int i = threadIdx.x; i < P; i += NT) {
@@ -116,10 +122,11 @@ __global__ __launch_bounds__(NT) void k_prep2d(const double2* __restrict__ f, cx
     fc[c] = cvt<T>(f[(size_t)a * N + b]);
   }
   __syncthreads();
-  for (int i1 = threadIdx.x; i1 < n1; i1 += NT) {
+  if (threadIdx.x < kPrepSplitR * n1) {
+    const int q = threadIdx.x / n1, i1 = threadIdx.x - q * n1;
     const int a = (i1 - h + 1 + N) % N;
     double ax = 0.0, ay = 0.0;
-    for (int i2 = 0; i2 < n1; ++i2) {
+    for (int i2 = q; i2 < n1; i2 += kPrepSplitR) {
       const int k2 = i2 - h + 1, b = (k2 + N) % N;
       int m = (k2 * x2) % P;
       if (m < 0) m += P;
@@ -127,24 +134,38 @@ __global__ __launch_bounds__(NT) void k_prep2d(const double2* __restrict__ f, cx
       ax += v.x * w.x - v.y * w.y;
       ay += v.x * w.y + v.y * w.x;
     }
-    row[i1] = double2{ax, ay};
+    part[q][i1] = double2{ax, ay};
   }
   __syncthreads();
-  for (int x1 = threadIdx.x; x1 < P; x1 += NT) {
+  if (threadIdx.x < n1) {
+    double2 t = part[0][threadIdx.x];
+    for (int q = 1; q < kPrepSplitR; ++q) {
+      t.x += part[q][threadIdx.x].x;
+      t.y += part[q][threadIdx.x].y;
+    }
+    row[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPrepSplitX * P) {
+    const int q = threadIdx.x / P, x1 = threadIdx.x - q * P;
     double acc = 0.0;
-    for (int i1 = 0; i1 < n1; ++i1) {
+    for (int i1 = q; i1 < n1; i1 += kPrepSplitX) {
       const int k1 = i1 - h + 1;
       int m = (k1 * x1) % P;
       if (m < 0) m += P;
       const double2 w = tw[m];
       acc += row[i1].x * w.x - row[i1].y * w.y;    // Re(row e^{+i phi})
     }
+    partx[q][x1] = acc;
+  }
+  __syncthreads();
+  for (int x1 = threadIdx.x; x1 < P; x1 += NT) {
+    double acc = partx[0][x1];
+    for (int q = 1; q < kPrepSplitX; ++q) acc += partx[q][x1];
     fgrid[x1 * P + x2] = (T)acc;
   }
 }
 
-// The whole pipeline for pair-twos s, s + S, ... of workgroup s = blockIdx.x.
-// ph[pair][axis][2N-3]: e^{i a sigma_d n}, n = -(N-2) .. N-2; cp[pair] = c_p.
 template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_collide2d(const cx<T>* __restrict__ fc, const T* __restrict__ fgrid,
                                                   const T* __restrict__ V, const double2* __restrict__ ph,
@@ -291,7 +312,7 @@ template <typename T, int P>
 hipError_t collide2d_t(const double* f_hat, void* fc, void* fgrid, const void* V, const double* ph,
                        const double* cp, const void* tw, double* Qpart, int N, int npt, int S, hipStream_t st) {
   constexpr int NT = collideThreads<T, P>();
-  hipLaunchKernelGGL((k_prep2d<T, P, 128>), dim3(P), dim3(128), 0, st, (const double2*)f_hat, (cx<T>*)fc,
+  hipLaunchKernelGGL((k_prep2d<T, P, 256>), dim3(P), dim3(256), 0, st, (const double2*)f_hat, (cx<T>*)fc,
                      (T*)fgrid, N);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
