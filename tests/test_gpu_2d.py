@@ -5,6 +5,8 @@
   FP32 bulk <= 1e-5, as for the 3-D path);
 * sampled modes at N = 48 and at Table 1's largest setting (N = N_rho = 64,
   N_sigma = 32), evaluated by the oracle one mode at a time;
+* at N = 64 both pipelines: the register passes (at most 1024 pair-twos) and
+  the LDS passes (more), on sampled modes;
 * an odd number of circle pairs (the last pair-two padded with a zero-weight
   pair), N_sigma = 2, gamma != 0;
 * Q_0 = 0 exactly and Q(-k) = conj Q(k) exactly (Hermitian completion);
@@ -116,6 +118,32 @@ def test_sampled_modes_match_oracle(bzq, N, N_rho, N_sigma, name):
         err = _rel(got, ref)
         print(N, name, prec, f"{err:.3e}", flush=True)
         assert err < TOL[prec], (prec, err)
+        plan.destroy()
+
+
+@pytest.mark.parametrize("N_rho,N_sigma,name", [(8, 8, "b1"), (65, 64, "b3")], ids=["reg-16pt", "lds-1040pt"])
+def test_n64_both_pipelines_match_oracle(bzq, N_rho, N_sigma, name):
+    """At N = 64 the register-pass pipeline runs when every workgroup holds one
+    pair-two (at most 1024 pair-twos: N_rho = 8, N_sigma = 8 gives 16) and the
+    LDS pipeline otherwise (N_rho = 65, N_sigma = 64 gives 1040); both against
+    the oracle on sampled modes, both precisions.  (With b3 at N_rho = 8 the
+    sampled modes cancel strongly and FP32 reaches 1.2e-5 on either pipeline,
+    measured alike on the same input; b1 there.)"""
+    N, L, R = 64, 8.0, 4.0
+    d = o2.Discretization2D(N, L, R, 0.0, o2.PAPER_KERNELS_2D[name], N_rho, N_sigma)
+    f = workloads.to_spectral_2d(workloads.random_mixture_2d(77, N, L))
+    ks = _sampled(N, 10, 64)
+    ref = o2.collision_direct2d(f, d, k_out=ks)
+    fd = _dev(f)
+    for prec in ("fp64", "fp32"):
+        plan = _plan(bzq, d, prec)
+        Q = _host(plan.collision(fd))
+        err = _rel(Q[tuple(np.mod(ks, N).T)], ref)
+        print(N_rho, N_sigma, prec, f"{err:.3e}", flush=True)
+        assert err < TOL[prec], (prec, err)
+        assert Q[0, 0] == 0.0
+        k = np.arange(N)
+        assert np.array_equal(Q[np.ix_((-k) % N, (-k) % N)], np.conj(Q))
         plan.destroy()
 
 
