@@ -1,5 +1,6 @@
 """Batched and served forms: every cell's / request's result must equal the
-single-cell path bit for bit, whatever else runs with it; graph replays must
+single-cell path bit for bit, whatever else runs with it (also on the FP64
+LDS path with several cells per launch); graph replays must
 equal eager execution at every replay; admission must queue (not fail) what
 fits later and fail what can never fit.
 """
@@ -70,6 +71,42 @@ def test_batch_step_graph_replays_equal_eager(bzq):
     for rep in range(3):
         for p, r in zip(plans, ref):
             p.step(r, dt, 1)
+        be.step(dt, 1, use_graph=False)
+        bg.step(dt, 1, use_graph=True)
+        R = [_host(x) for x in ref]
+        for a, b, c in zip(R, eager, graph):
+            assert np.array_equal(a, _host(b)), rep
+            assert np.array_equal(a, _host(c)), rep
+    be.destroy()
+    bg.destroy()
+
+
+def test_batch_fp64_lds_path_bitwise_equals_solo(bzq):
+    """FP64 at N = 48 (P = 72): the pencils do not fit the register file, so the
+    evaluation takes the separate ingest and the LDS z-inverse, here with three
+    cells in one launch; Q and two Heun steps (the update inside finalize), eager
+    and graph-replayed, bitwise equal to the single-cell path."""
+    import torch
+    plan = bzq.Plan(48, 9.0, 4.5, 0.0, 0.5, 4, 6, precision="fp64")
+    plans = [plan, plan, plan]
+    fs = [_f(48, 9.0, 300 + i) for i in range(3)]
+    solo = [_host(plan.collision(_dev(f))) for f in fs]
+    fd = [_dev(f) for f in fs]
+    batch = bzq.Batch(plans, fd, cells_per_launch=3)
+    outs = [torch.empty_like(f) for f in fd]
+    batch.collision(outs)
+    for a, b in zip(solo, outs):
+        assert np.array_equal(a, _host(b))
+    batch.destroy()
+    dt = 0.01
+    ref = [_dev(f) for f in fs]
+    eager = [_dev(f) for f in fs]
+    graph = [_dev(f) for f in fs]
+    be = bzq.Batch(plans, eager, cells_per_launch=3)
+    bg = bzq.Batch(plans, graph, cells_per_launch=3)
+    for rep in range(2):
+        for r in ref:
+            plan.step(r, dt, 1)
         be.step(dt, 1, use_graph=False)
         bg.step(dt, 1, use_graph=True)
         R = [_host(x) for x in ref]
