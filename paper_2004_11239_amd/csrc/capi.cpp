@@ -748,7 +748,7 @@ bzq_status bzq_plan_set_schedule(bzq_plan p, const int* sched) {
   if (!p || !sched) return fail(BZQ_EINVAL, "NULL argument");
   for (int st = 0; st < 3; ++st) {
     const int v = sched[st];
-    if (v < 0 || v > 2 || (v && !(stage_variants(st, p->P, p->fp32) >> v & 1)))
+    if (v < 0 || v > 3 || (v && !(stage_variants(st, p->P, p->fp32) >> v & 1)))
       return fail(BZQ_EINVAL, "kernel variant not available for this plan");
   }
   if (sched[3] != kSTargets[0] && sched[3] != kSTargets[1] && sched[3] != kSTargets[2])
@@ -789,7 +789,7 @@ bzq_status bzq_plan_autotune(bzq_plan p, const double* f_hat, int use_cache, voi
   // one stage at a time, the others kept at their best so far
   for (int stage = 0; stage < 3; ++stage) {
     const unsigned avail = stage_variants(stage, p->P, p->fp32);
-    for (int v = 1; v <= 2; ++v) {
+    for (int v = 1; v <= 3; ++v) {
       for (int t = 0; t < 3; ++t) {
         if (!(avail >> v & 1)) continue;
         if (stage < 2 && t != 1) continue;   // s_target matters to the z-forward only

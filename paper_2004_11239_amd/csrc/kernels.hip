@@ -25,6 +25,7 @@
 // zero padding folds away) used wherever a pencil fits the register file, and
 // an LDS Stockham one used otherwise (FP64 at P >= 72) and by the last stage.
 #include <algorithm>
+#include <type_traits>
 
 #include "fft.hpp"
 #include "funk_hecke.hpp"
@@ -77,6 +78,15 @@ template <typename T>
 __device__ __forceinline__ cx<T> ld_nt(const cx<T>* p) {
   const vec2<T> v = __builtin_nontemporal_load(reinterpret_cast<const vec2<T>*>(p));
   return cx<T>{v.x, v.y};
+}
+// A row input of the plane's four-way row passes, which four waves of a
+// workgroup read: non-temporal in FP32 (measured faster at P = 96), ordinary
+// in FP64, where streaming it made every wave fetch it again (64^3 plane
+// 35.4 -> 32.3 ms with ordinary loads in the four-wave kernel).
+template <typename T>
+__device__ __forceinline__ cx<T> ld_row(const cx<T>* p) {
+  if constexpr (sizeof(T) == 8) return *p;
+  else return ld_nt(p);
 }
 template <typename T>
 __device__ __forceinline__ void st_nt(cx<T>* p, cx<T> v) {
@@ -645,7 +655,7 @@ __device__ __forceinline__ void quarter_rows_inv(const cx<T>* __restrict__ Ain, 
   dft_quarter_dif<P, +1, R>(
       [&](int n) -> cx<T> {
         const int i2 = keptK<N, P>(n);
-        return i2 >= 0 ? ld_nt(Ain + (size_t)i2 * n1) : cx<T>{0, 0};
+        return i2 >= 0 ? ld_row(Ain + (size_t)i2 * n1) : cx<T>{0, 0};
       },
       u);
 #pragma unroll
@@ -820,6 +830,189 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
     if (par == 0) half_rows_fwd<T, N, P, 0>(sm + l * LD, Bout, l);
     else half_rows_fwd<T, N, P, 1>(sm + l * LD, Bout, l);
   }
+}
+
+// ------------------------------- the plane by column parity (FP64, P = 96)
+// The four-wave FP64 plane of k_plane_half fills 97.8 KB of LDS, one
+// workgroup per CU, and each of its barriers then idles the CU.  This kernel
+// takes the columns y of the plane in two phases by parity p (y = 2c + p), in
+// a half plane of LDS, so that two workgroups share a CU:
+// * rows, inverse along axis 2: classes R = p and p + 2 of the radix-4 split
+//   give the outputs y = 4j + R, i.e. c = 2j + (R - p) / 2 (waves 0, 1);
+// * columns c, axis 1: wave R inverts to the heights x = 4i + R, multiplies by
+//   f, takes the P/4-point forward transform and twiddles it (quarter_cols);
+//   the four classes combine their partials through a separate exchange
+//   buffer in three rounds, and the kept outputs go back into column c;
+// * rows, forward along axis 2: the P/2-point forward transform over c of
+//   this phase, D_p, split four ways (wave R: D_p[4j' + R]).  Phase 0 keeps
+//   D_0 in registers; phase 1 forms X[k] = D_0[k] + w^{-k} D_1[k] and
+//   X[k + P/2] = D_0[k] - w^{-k} D_1[k] and writes the kept modes.
+// Rounding differs from the other plane kernels (another split of the same
+// transforms); the result is deterministic.  Measured at 64^3 FP64: plane
+// stage 27.0 ms against 32.3 ms for k_plane_half (same loads); the default
+// there.
+template <typename T, int N, int P, int LDC, int R>
+__device__ __forceinline__ void quarter_cols(const cx<T>* col, const T* __restrict__ fz, cx<T>* u) {
+  constexpr int Q4 = P / 4;
+  dft_quarter_dif<P, +1, R>(
+      [&](int n) -> cx<T> {
+        const int i1 = keptK<N, P>(n);
+        return i1 >= 0 ? col[i1 * LDC] : cx<T>{0, 0};
+      },
+      u);
+#pragma unroll
+  for (int j = 0; j < Q4; ++j) u[j] = cscale(u[j], fz[(size_t)(4 * j + R) * P]);
+  fft_reg<Q4, -1>(u);
+  if constexpr (R > 0) {
+#pragma unroll
+    for (int k = 1; k < Q4; ++k) u[k] = twiddle_mul<P, -1>(u[k], k * R);
+  }
+}
+
+// (-i)^e x; e is a constant once the callers' loops are unrolled
+template <typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> x, int e) {
+  switch (e & 3) {
+    case 0: return x;
+    case 1: return rot<-1>(x);
+    case 2: return cx<T>{-x.x, -x.y};
+    default: return rot<+1>(x);
+  }
+}
+
+// Column pass of class R on column c (valid lanes: col).  With
+// u_S[k] = w_P^{-S k} D_S[k] from quarter_cols, the forward transform is
+// X[k + (P/4) m] = sum_S (-i)^{S m} u_S[k]; class R forms it for k = R + 4t.
+// Round rd exchanges t = 2 rd, 2 rd + 1: slot ((Rt * 2 + tt) * 4 + S) * NC + c
+// of xch holds u_S[Rt + 4 (2 rd + tt)].
+template <typename T, int N, int P, int NC, int LDC, int R>
+__device__ __forceinline__ void split_cols_pass(cx<T>* sm, cx<T>* xch, const T* __restrict__ fz, int c,
+                                                bool col) {
+  constexpr int Q4 = P / 4, NR = Q4 / 8;   // rounds of two frequencies per class
+  static_assert(Q4 % 8 == 0, "two frequencies of each class per round");
+  cx<T> u[Q4];
+  if (col) quarter_cols<T, N, P, LDC, R>(sm + c, fz, u);
+  __syncthreads();   // every column input read before outputs overwrite them
+#pragma unroll
+  for (int rd = 0; rd < NR; ++rd) {
+    if (col) {
+#pragma unroll
+      for (int Rt = 0; Rt < 4; ++Rt) {
+        if (Rt == R) continue;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) xch[((Rt * 2 + tt) * 4 + R) * NC + c] = u[Rt + 4 * (2 * rd + tt)];
+      }
+    }
+    __syncthreads();
+    if (col) {
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        const int k = R + 4 * (2 * rd + tt);
+        cx<T> sv[4];
+#pragma unroll
+        for (int S = 0; S < 4; ++S) sv[S] = S == R ? u[k] : xch[((R * 2 + tt) * 4 + S) * NC + c];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int k1 = keptK<N, P>(k + Q4 * m);
+          if (k1 < 0) continue;
+          sm[k1 * LDC + c] = cadd(cadd(sv[0], mul_mi(sv[1], m)), cadd(mul_mi(sv[2], 2 * m), mul_mi(sv[3], 3 * m)));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int N, int P, int PH>
+__device__ __forceinline__ void split_phase(const cx<T>* __restrict__ Ain0, cx<T>* __restrict__ Bout,
+                                            const T* __restrict__ fz0, cx<T>* sm, cx<T>* xch, int wq, int lq,
+                                            cx<T>* d0) {
+  constexpr int n1 = N - 1, nn = n1 * n1, NC = P / 2, LDC = NC + 1, Q4 = P / 4, Q8 = NC / 4;
+  constexpr int nhp = ((nn + 1) / 2 + 15) / 16 * 16, cmid = (nn - 1) / 2;
+  // rows, inverse: classes PH (wave 0) and PH + 2 (wave 1) of the P-point split
+  if (wq < 2 && lq < n1) {
+    cx<T> u[Q4];
+    const cx<T>* Ain = Ain0 + lq;
+    auto get = [&](int n) -> cx<T> {
+      const int i2 = keptK<N, P>(n);
+      return i2 >= 0 ? ld_row(Ain + (size_t)i2 * n1) : cx<T>{0, 0};
+    };
+    cx<T>* row = sm + lq * LDC;
+    if (wq == 0) {
+      dft_quarter_dif<P, +1, PH>(get, u);
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) row[2 * j] = u[j];
+    } else {
+      dft_quarter_dif<P, +1, PH + 2>(get, u);
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) row[2 * j + 1] = u[j];
+    }
+  }
+  __syncthreads();
+  // columns c (y = 2c + PH), class wq of the heights
+  {
+    const bool col = lq < NC;
+    const int c = col ? lq : 0;
+    const T* fz = fz0 + 2 * c + PH;
+    if (wq == 0) split_cols_pass<T, N, P, NC, LDC, 0>(sm, xch, fz, c, col);
+    else if (wq == 1) split_cols_pass<T, N, P, NC, LDC, 1>(sm, xch, fz, c, col);
+    else if (wq == 2) split_cols_pass<T, N, P, NC, LDC, 2>(sm, xch, fz, c, col);
+    else split_cols_pass<T, N, P, NC, LDC, 3>(sm, xch, fz, c, col);
+  }
+  // rows, forward over this phase's columns: D_PH[4j' + wq]
+  if (lq < n1) {
+    const cx<T>* row = sm + lq * LDC;
+    auto get = [&](int n) -> cx<T> { return row[n]; };
+    auto fwd = [&](auto RC) {
+      constexpr int R = decltype(RC)::value;
+      cx<T> d[Q8];
+      dft_quarter_dif<NC, -1, R>(get, d);
+      if constexpr (PH == 0) {
+#pragma unroll
+        for (int j = 0; j < Q8; ++j) d0[j] = d[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < Q8; ++j) {
+          const int k = 4 * j + R;
+          const cx<T> b = twiddle_mul<P, -1>(d[j], k);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int k2 = keptK<N, P>(k + h * NC);
+            if (k2 < 0) continue;
+            const cx<T> w = h == 0 ? cadd(d0[j], b) : csub(d0[j], b);
+            const int cc = k2 * n1 + lq;
+            st_nt(Bout + (cc <= cmid ? cc : nhp + (nn - 1 - cc)), w);
+            if (cc == cmid) st_nt(Bout + nhp + cmid, w);
+          }
+        }
+      }
+    };
+    if (wq == 0) fwd(std::integral_constant<int, 0>{});
+    else if (wq == 1) fwd(std::integral_constant<int, 1>{});
+    else if (wq == 2) fwd(std::integral_constant<int, 2>{});
+    else fwd(std::integral_constant<int, 3>{});
+  }
+  __syncthreads();   // the half plane is free for the next phase
+}
+
+template <typename T, int N, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_plane_split(
+    const cx<T>* __restrict__ A, cx<T>* __restrict__ B, const T* __restrict__ fgrid, CellStrides cs) {
+  constexpr int n1 = N - 1, nn = n1 * n1, NC = P / 2, LDC = NC + 1;
+  static_assert(P == 96 && n1 <= 64 && NC <= 64, "one row or column per lane");
+  A += blockIdx.z * cs.a;
+  B += blockIdx.z * cs.b;
+  fgrid += blockIdx.z * cs.fg;
+  __shared__ cx<T> sm[n1 * LDC];
+  __shared__ cx<T> xch[4 * 2 * 4 * NC];
+  const int z = blockIdx.x, pt = blockIdx.y;
+  const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
+  const cx<T>* Ain = A + ((size_t)pt * P + z) * nn;
+  cx<T>* Bout = B + ((size_t)pt * P + z) * 2 * (((nn + 1) / 2 + 15) / 16 * 16);
+  const T* fz = fgrid + (size_t)z * P * P;
+  cx<T> d0[NC / 4];
+  split_phase<T, N, P, 0>(Ain, Bout, fz, sm, xch, wq, lq, d0);
+  split_phase<T, N, P, 1>(Ain, Bout, fz, sm, xch, wq, lq, d0);
 }
 
 // The two-dimensional operator (d = 2) at P = 96 with the passes of
@@ -1646,12 +1839,22 @@ hipError_t plane_half_t(const void* A, void* B, const void* fgrid, int npt, cons
   return hipGetLastError();
 }
 
+template <typename T, int P, int N>
+hipError_t plane_split_t(const void* A, void* B, const void* fgrid, int npt, const CellStrides& cs,
+                         hipStream_t st) {
+  dim3 grid(P, npt, cs.cells);
+  hipLaunchKernelGGL((k_plane_split<T, N, P>), grid, dim3(256), 0, st, (const cx<T>*)A, (cx<T>*)B,
+                     (const T*)fgrid, cs);
+  return hipGetLastError();
+}
+
 // FP32 pencils of 72 and 96 points use the two-wave kernels
 // Kernel variants of the three pipeline stages: 1 = one whole pencil per lane
 // (register kernels; LDS kernels where a pencil does not fit the register
 // file), 2 = two waves per pencil (z-inverse, plane) and the pipelined
-// z-forward, for P = 48, 72, 96.  0 selects the default below (the faster one
-// in measurements at 32^3 and 64^3); plans can be autotuned to another.
+// z-forward, for P = 48, 72, 96; 3 = the plane by column parity
+// (k_plane_split, FP64 at P = 96 only).  0 selects the default below (the
+// fastest in measurements at 32^3 and 64^3); plans can be autotuned to another.
 template <int P>
 constexpr bool hasTwo() { return P == 48 || P == 72 || P == 96; }
 template <typename T, int P>
@@ -1660,7 +1863,7 @@ constexpr int defaultVariant(int stage) {
     if (stage == 2) return P == 48 || P == 72 || P == 96 ? 2 : 1;   // z-forward
     return P == 72 || P == 96 ? 2 : 1;                               // z-inverse, plane
   }
-  if (stage == 1) return P == 72 || P == 96 ? 2 : 1;                 // FP64 plane
+  if (stage == 1) return P == 96 ? 3 : P == 72 ? 2 : 1;               // FP64 plane
   if (stage == 2) return P == 48 ? 2 : 1;                            // FP64 z-forward
   return 1;
 }
@@ -1694,6 +1897,8 @@ hipError_t plane_t(const void* A, void* B, const void* fgrid, void* gridout, con
   const int v = variant ? variant : defaultVariant<T, P>(1);
   if constexpr (hasTwo<P>())
     if (v == 2 && N == padN<P>() && mode == PLANE_PRODUCT) return plane_half_t<T, P, padN<P>()>(A, B, fgrid, npt, cs, st);
+  if constexpr (sizeof(T) == 8 && P == 96)
+    if (v == 3 && N == padN<P>() && mode == PLANE_PRODUCT) return plane_split_t<T, P, padN<P>()>(A, B, fgrid, npt, cs, st);
   if constexpr (RegFit<T, P>::value && isPad<P>())
     if (N == padN<P>()) return plane_reg_t<T, P, padN<P>()>(A, B, fgrid, gridout, npt, mode, cs, st);
   if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
@@ -1857,8 +2062,7 @@ int stage_default_variant(int stage, int P, bool fp32) {
 }
 
 unsigned stage_variants(int stage, int P, bool fp32) {
-  (void)stage;
-  (void)fp32;
+  if (stage == 1 && P == 96 && !fp32) return 0xEu;   // 3: the plane by column parity (k_plane_split)
   return (P == 48 || P == 72 || P == 96) ? 0x6u : 0x2u;
 }
 

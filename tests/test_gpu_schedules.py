@@ -84,6 +84,34 @@ def test_every_schedule_matches_oracle(bzq, case48, which, prec):
     plan.destroy()
 
 
+@pytest.mark.parametrize("sched", [(1, 3, 1, 1024), (2, 3, 1, 512), (1, 3, 2, 2048)])
+def test_parity_split_plane_fp64_matches_oracle(bzq, sched):
+    """FP64 at P = 96: the plane taken by column parity (variant 3), with its
+    four-way column pass assembled through LDS and the two parities' row
+    transforms combined in registers, against the stored oracle samples at
+    64^3."""
+    params, f, ks, ref = _golden("large_s050")
+    N = params[0]
+    plan = bzq.Plan(*params, precision="fp64")
+    got_s = plan.set_schedule(*sched)
+    assert got_s["plane"] == 3
+    Q = _host(plan.collision(_dev(f)))
+    got = Q[tuple(np.mod(ks, N).T)]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"large fp64 {sched}: {err:.3e}", flush=True)
+    assert err < TOL["fp64"], (sched, err)
+    assert Q[0, 0, 0] == 0.0
+    plan.destroy()
+
+
+def test_parity_split_plane_only_fp64_at_p96(bzq):
+    for N, prec in ((64, "fp32"), (32, "fp64"), (48, "fp64")):
+        plan = bzq.Plan(N, 8.0, 4.0, 0.0, 0.5, 4, 6, precision=prec)
+        with pytest.raises(bzq.BzqError):
+            plan.set_schedule(1, 3, 1, 1024)
+        plan.destroy()
+
+
 def test_schedule_rejects_missing_variants(bzq):
     plan = bzq.Plan(16, 8.0, 4.0, 0.0, 0.5, 8, 14, precision="fp32")
     with pytest.raises(bzq.BzqError):
