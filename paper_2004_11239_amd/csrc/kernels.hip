@@ -1861,8 +1861,10 @@ template <typename T, int P>
 constexpr int defaultVariant(int stage) {
   if constexpr (sizeof(T) == 4) {
     if (stage == 2) return P == 48 || P == 72 || P == 96 ? 2 : 1;   // z-forward
-    return P == 72 || P == 96 ? 2 : 1;                               // z-inverse, plane
+    if (stage == 1) return P == 96 ? 2 : 1;                          // plane
+    return 1;                                                        // z-inverse
   }
+  if (stage == 0) return P == 72 || P == 96 ? 2 : 1;                 // FP64 z-inverse
   if (stage == 1) return P == 96 ? 3 : P == 72 ? 2 : 1;               // FP64 plane
   if (stage == 2) return P == 48 ? 2 : 1;                            // FP64 z-forward
   return 1;
