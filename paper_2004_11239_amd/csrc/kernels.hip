@@ -839,8 +839,9 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
 // a half plane of LDS, so that two workgroups share a CU:
 // * rows, inverse along axis 2: classes R = p and p + 2 of the radix-4 split
 //   give the outputs y = 4j + R, i.e. c = 2j + (R - p) / 2 (waves 0, 1);
-// * columns c, axis 1: wave R inverts to the heights x = 4i + R, multiplies by
-//   f, takes the P/4-point forward transform and twiddles it (quarter_cols);
+// * columns c, axis 1: wave R inverts to the points x = 4i + R of the column,
+//   multiplies by f, takes the P/4-point forward transform and twiddles it
+//   (quarter_cols);
 //   the four classes combine their partials through a separate exchange
 //   buffer in three rounds, and the kept outputs go back into column c;
 // * rows, forward along axis 2: the P/2-point forward transform over c of
@@ -949,7 +950,7 @@ __device__ __forceinline__ void split_phase(const cx<T>* __restrict__ Ain0, cx<T
     }
   }
   __syncthreads();
-  // columns c (y = 2c + PH), class wq of the heights
+  // columns c (y = 2c + PH), class wq of the points along axis 1
   {
     const bool col = lq < NC;
     const int c = col ? lq : 0;
