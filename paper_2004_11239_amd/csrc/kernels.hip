@@ -1016,7 +1016,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   split_phase<T, N, P, 1>(Ain, Bout, fz, sm, xch, wq, lq, d0);
 }
 
-// The two-dimensional operator (d = 2) at P = 96 with the passes of
+// The two-dimensional operator (d = 2) at P = 96 in FP32 (FP64 takes
+// k_collide2d_split) with the passes of
 // k_plane_half: workgroup s carries pair-two s through the whole pipeline in
 // one plane of LDS (one pair-two per workgroup: with a loop over several the
 // compiler keeps the loop-invariant addresses of every pass in registers and
@@ -1030,7 +1031,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // LDS kernel of the 2-D path.  Layouts as there: compact spectra with mode
 // c = i2 (N-1) + i1, f on the grid [x][y], phases ph[pair][axis][2N-3].
 template <typename T, int N>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_collide2d_reg(const cx<T>* __restrict__ fc, const T* __restrict__ fgrid,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_collide2d_reg(const cx<T>* __restrict__ fc, const T* __restrict__ fgrid,
                                                        const T* __restrict__ V, const double2* __restrict__ ph,
                                                        const double* __restrict__ cp, double2* __restrict__ Qpart,
                                                        int npt, int S) {
@@ -1038,6 +1039,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   constexpr int LD = P + 1, Q = P / 2, QH = Q / 2, Q4 = P / 4;
   constexpr int OPT = (nh + 255) / 256;
   static_assert(P == 96 && HalfCfg<P>::NT == 256 && n1 <= 64, "four waves, one row per lane");
+  static_assert(sizeof(T) == 4, "FP64 takes k_collide2d_split");
   __shared__ cx<T> sm[n1 * LD];
   __shared__ cx<T> ey[2][n1];
   const int s = blockIdx.x;
@@ -1190,6 +1192,149 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
         Qs[c] = double2{0.0 + (vA * tA.x + vB * tB.x), 0.0 + (vA * tA.y + vB * tB.y)};
       }
+    }
+  }
+}
+
+// One parity phase of k_collide2d_split (columns y = 2c + PH): rows inverse
+// from the modulated spectrum (classes PH, PH + 2 on waves 0, 1), the four-way
+// column pass, and the rows forward over this phase's columns (D_PH, class
+// wq); phase 0 keeps D_0 in d0, phase 1 forms the kept modes into xo.
+template <typename T, int N, int PH>
+__device__ __forceinline__ void collide2d_phase(const cx<T>* __restrict__ fc, const T* __restrict__ fgrid,
+                                                cx<T>* sm, cx<T>* xch, const cx<T> (*ey)[N - 1], cx<T> pA1,
+                                                cx<T> pB1, int wq, int lq, cx<T>* d0, cx<T>* xo) {
+  constexpr int P = 3 * N / 2, n1 = N - 1, NC = P / 2, LDC = NC + 1, Q4 = P / 4, Q8 = NC / 4;
+  if (wq < 2 && lq < n1) {
+    cx<T> u[Q4];
+    auto get = [&](int n) -> cx<T> {
+      const int i2 = keptK<N, P>(n);
+      if (i2 < 0) return cx<T>{0, 0};
+      const cx<T> eA = cmul(pA1, ey[0][i2]), eB = cmul(pB1, ey[1][i2]);
+      return cmul(fc[i2 * n1 + lq], cx<T>{eA.x - eB.y, eA.y + eB.x});
+    };
+    cx<T>* row = sm + lq * LDC;
+    if (wq == 0) {
+      dft_quarter_dif<P, +1, PH>(get, u);
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) row[2 * j] = u[j];
+    } else {
+      dft_quarter_dif<P, +1, PH + 2>(get, u);
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) row[2 * j + 1] = u[j];
+    }
+  }
+  __syncthreads();
+  {
+    const bool col = lq < NC;
+    const int c = col ? lq : 0;
+    const T* fz = fgrid + 2 * c + PH;
+    if (wq == 0) split_cols_pass<T, N, P, NC, LDC, 0>(sm, xch, fz, c, col);
+    else if (wq == 1) split_cols_pass<T, N, P, NC, LDC, 1>(sm, xch, fz, c, col);
+    else if (wq == 2) split_cols_pass<T, N, P, NC, LDC, 2>(sm, xch, fz, c, col);
+    else split_cols_pass<T, N, P, NC, LDC, 3>(sm, xch, fz, c, col);
+  }
+  if (lq < n1) {
+    const cx<T>* row = sm + lq * LDC;
+    auto get = [&](int n) -> cx<T> { return row[n]; };
+    auto fwd = [&](auto RC) {
+      constexpr int R = decltype(RC)::value;
+      cx<T> d[Q8];
+      dft_quarter_dif<NC, -1, R>(get, d);
+      if constexpr (PH == 0) {
+#pragma unroll
+        for (int j = 0; j < Q8; ++j) d0[j] = d[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < Q8; ++j) {
+          const cx<T> b = twiddle_mul<P, -1>(d[j], 4 * j + R);
+          xo[2 * j] = cadd(d0[j], b);
+          xo[2 * j + 1] = csub(d0[j], b);
+        }
+      }
+    };
+    if (wq == 0) fwd(std::integral_constant<int, 0>{});
+    else if (wq == 1) fwd(std::integral_constant<int, 1>{});
+    else if (wq == 2) fwd(std::integral_constant<int, 2>{});
+    else fwd(std::integral_constant<int, 3>{});
+  }
+  __syncthreads();
+}
+
+// The two-dimensional operator at P = 96 in FP64 with the plane taken by
+// column parity, as k_plane_split: the plane of k_collide2d_reg fills 97.8 KB
+// of LDS (one workgroup per CU, its 512 workgroups in two rounds); here a half
+// plane and the exchange buffer (74 KB) hold two workgroups per CU.  The row
+// input is the modulated spectrum, formed on load; after phase 1 the kept
+// modes are gathered in the freed LDS as a compact (N-1) x (N-1) plane for the
+// split of the two pairs, the weights and the FP64 accumulation, which are
+// those of k_collide2d_reg.
+template <typename T, int N>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_collide2d_split(
+    const cx<T>* __restrict__ fc, const T* __restrict__ fgrid, const T* __restrict__ V,
+    const double2* __restrict__ ph, const double* __restrict__ cp, double2* __restrict__ Qpart, int npt, int S) {
+  constexpr int P = 3 * N / 2, n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  constexpr int NC = P / 2, LDC = NC + 1, Q8 = NC / 4, OPT = (nh + 255) / 256;
+  constexpr int NPL = n1 * LDC, NX = 4 * 2 * 4 * NC;
+  static_assert(P == 96 && n1 <= 64 && nn <= NPL + NX, "one row per lane; the compact plane fits the LDS");
+  __shared__ cx<T> lds[NPL + NX];
+  __shared__ cx<T> ey[2][n1];
+  const int s = blockIdx.x;
+  const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
+  double2* __restrict__ Qs = Qpart + (size_t)s * nh;
+  if (s >= npt) {   // uniform over the workgroup
+    for (int c = threadIdx.x; c < nh; c += 256) Qs[c] = double2{0.0, 0.0};
+    return;
+  }
+  const int jA = 2 * s, jB = jA + 1;
+  const double2* phA = ph + (size_t)jA * 2 * PL + (N - 2);
+  const double2* phB = phA + 2 * PL;
+  for (int t = threadIdx.x; t < 2 * n1; t += 256) {
+    const int i2 = t < n1 ? t : t - n1;
+    ey[t < n1 ? 0 : 1][i2] = to_cx<T>((t < n1 ? phA : phB)[PL - 2 * (i2 - h + 1)]);
+  }
+  __syncthreads();
+  const int k1l = (lq < n1 ? lq : 0) - h + 1;
+  const cx<T> pA1 = to_cx<T>(phA[-2 * k1l]), pB1 = to_cx<T>(phB[-2 * k1l]);
+  cx<T> d0[Q8], xo[2 * Q8];
+  collide2d_phase<T, N, 0>(fc, fgrid, lds, lds + NPL, ey, pA1, pB1, wq, lq, d0, xo);
+  collide2d_phase<T, N, 1>(fc, fgrid, lds, lds + NPL, ey, pA1, pB1, wq, lq, d0, xo);
+  // the kept modes of row i1 = lq, class wq: X[4j + wq] and X[4j + wq + P/2]
+  cx<T>* fin = lds;   // mode (i1, i2) at fin[i1 * n1 + i2]
+  if (lq < n1) {
+    auto put = [&](auto RC) {
+      constexpr int R = decltype(RC)::value;
+#pragma unroll
+      for (int j = 0; j < Q8; ++j) {
+        const int ka = keptK<N, P>(4 * j + R), kb = keptK<N, P>(4 * j + R + NC);
+        if (ka >= 0) fin[lq * n1 + ka] = xo[2 * j];
+        if (kb >= 0) fin[lq * n1 + kb] = xo[2 * j + 1];
+      }
+    };
+    if (wq == 0) put(std::integral_constant<int, 0>{});
+    else if (wq == 1) put(std::integral_constant<int, 1>{});
+    else if (wq == 2) put(std::integral_constant<int, 2>{});
+    else put(std::integral_constant<int, 3>{});
+  }
+  __syncthreads();
+  const double cA = cp[jA], cB = cp[jB];
+#pragma unroll 2
+  for (int b = 0; b < OPT; ++b) {
+    const int c = threadIdx.x + b * 256;
+    if (c < nh) {
+      const int i2 = c / n1, i1 = c - i2 * n1;
+      const int k1 = i1 - h + 1, k2 = i2 - h + 1;
+      const cx<T> w1 = fin[i1 * n1 + i2];
+      const cx<T> w2 = fin[(n1 - 1 - i1) * n1 + (n1 - 1 - i2)];
+      // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
+      const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
+      const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
+      const double vA = cA * (double)V[(size_t)jA * nh + c];
+      const double vB = cB * (double)V[(size_t)jB * nh + c];
+      const cx<double> eA = cmul(d2c(phA[k1]), d2c(phA[PL + k2]));
+      const cx<double> eB = cmul(d2c(phB[k1]), d2c(phB[PL + k2]));
+      const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
+      Qs[c] = double2{0.0 + (vA * tA.x + vB * tB.x), 0.0 + (vA * tA.y + vB * tB.y)};
     }
   }
 }
@@ -1985,6 +2130,8 @@ hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells
   return hipGetLastError();
 }
 
+// FP32: k_collide2d_reg; FP64: k_collide2d_split (two workgroups per CU; N = 64,
+// 512 pair-twos: 0.063 -> 0.058 ms per evaluation against the one-plane kernel)
 hipError_t launch_collide2d_reg(const void* fc, const void* fgrid, const void* V, const double* ph, const double* cp,
                                 double* Qpart, int N, int npt, int S, bool fp32, hipStream_t st) {
   if (N != 64 || S < npt) return hipErrorInvalidValue;   // one pair-two per workgroup
@@ -1992,7 +2139,7 @@ hipError_t launch_collide2d_reg(const void* fc, const void* fgrid, const void* V
     hipLaunchKernelGGL((k_collide2d_reg<float, 64>), dim3(S), dim3(256), 0, st, (const cx<float>*)fc,
                        (const float*)fgrid, (const float*)V, (const double2*)ph, cp, (double2*)Qpart, npt, S);
   else
-    hipLaunchKernelGGL((k_collide2d_reg<double, 64>), dim3(S), dim3(256), 0, st, (const cx<double>*)fc,
+    hipLaunchKernelGGL((k_collide2d_split<double, 64>), dim3(S), dim3(256), 0, st, (const cx<double>*)fc,
                        (const double*)fgrid, (const double*)V, (const double2*)ph, cp, (double2*)Qpart, npt, S);
   return hipGetLastError();
 }
