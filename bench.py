@@ -65,33 +65,57 @@ def flop_model(N: int, npairs: int):
     return out
 
 
-def plane_bytes_per_pt(N: int, esz: int) -> int:
-    """Algorithmic HBM bytes of the plane stage per pair-two: read the z-inverse
-    output A (P (N-1)^2 complex) and write B (P x 2 half spectra of
-    ((N-1)^2+1)/2 modes, complex)."""
-    P, n1 = 3 * N // 2, N - 1
-    nn = n1 * n1
-    nh = (nn + 1) // 2
-    return P * (nn + 2 * nh) * 2 * esz
-
-
 def table_bytes(N: int, npairs: int, esz: int) -> int:
     n1 = N - 1
     return npairs * ((n1 * n1 + 1) // 2) * n1 * esz
 
 
+STAGES = ("prep", "zinv", "plane", "zfwd", "finalize")
+
+
+def stage_model(N: int, npairs: int, esz: int):
+    """Algorithmic flops and HBM bytes per evaluation of each pipeline stage.
+
+    Flops are the method's own (flop_model: FFTs at 5 P log2 P, modulation,
+    product, split and weighting).  Bytes are the method's own HBM traffic
+    only: the weight table (read once by the z-forward stage), f_hat read by the
+    ingest and Q_hat written by the finalisation.  The pipeline intermediates
+    (the z-inverse output A and the plane output B, written once and read
+    once) are not algorithmic bytes: they appear as measured `traffic`."""
+    fm = flop_model(N, npairs)
+    n3 = N ** 3 * 16
+    return {"prep": (fm["prep"], n3), "zinv": (fm["zinv"], 0), "plane": (fm["plane"], 0),
+            "zfwd": (fm["zfwd"], table_bytes(N, npairs, esz)), "finalize": (0.0, n3)}
+
+
+def roof(flops: float, nbytes: float, seconds: float, peak_tflops: float):
+    """Roofline object of one kernel launch (or one evaluation): the bound is
+    the larger of the two algorithmic times (bytes / 8 TB/s, flops / vector
+    peak); `achieved` is that quantity per second, `frac` = achieved / peak."""
+    t_alu = flops / (peak_tflops * 1e12)
+    t_hbm = nbytes / HBM_PEAK
+    if t_alu >= t_hbm:
+        ach = flops / seconds / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": peak_tflops, "unit": "TFLOP/s",
+                "frac": round(ach / peak_tflops, 4)}
+    ach = nbytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": round(ach / (HBM_PEAK / 1e9), 4)}
+
+
 # --------------------------------------------------------------- GPU timing
 def time_steps(bzq, torch, cfg, prec, fhat_np, steps, warmup):
-    """Time `steps` Heun steps with HIP events around the plane-stage launches
-    only (the dominant kernel, for the roofline), then time the same steps again
-    with events around every launch for the per-stage breakdown."""
+    """Time `steps` Heun steps (one bzq_step call) with HIP events around the
+    plane-stage launches only (the dominant kernel, for the roofline), then run
+    the same steps again with events around every launch for the per-stage
+    breakdown."""
     plan = bzq.Plan(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"], cfg["N_rho"], cfg["M"],
                     precision=prec)
     f0 = torch.from_numpy(fhat_np).to("cuda")
     plan.autotune(f0)                           # kernel schedule (cached after the first run)
     f = f0.clone()
-    for _ in range(warmup):
-        plan.step(f, DT, 1)
+    if warmup:
+        plan.step(f, DT, warmup)
     f.copy_(f0)
     torch.cuda.synchronize()
     plan.set_timing(True, stages=("plane",))
@@ -100,8 +124,7 @@ def time_steps(bzq, torch, cfg, prec, fhat_np, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(st)
-    for _ in range(steps):
-        plan.step(f, DT, 1)
+    plan.step(f, DT, steps)
     e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -110,8 +133,7 @@ def time_steps(bzq, torch, cfg, prec, fhat_np, steps, warmup):
     # per-stage breakdown (events on every launch), outside the timed region
     f.copy_(f0)
     plan.set_timing(True)
-    for _ in range(steps):
-        plan.step(f, DT, 1)
+    plan.step(f, DT, steps)
     stages = plan.stage_times()
     plan.set_timing(False)
     stages["plane_timed_region"] = plane
@@ -128,26 +150,73 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_tag: str):
-    """HBM bytes per launch of the dominant kernel from the committed PMC summary,
-    or None when the summary is missing or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", "plane_traffic_medium.md")
+def sched_tag(sched: dict) -> str:
+    return f"{sched['zinv']}/{sched['plane']}/{sched['zfwd']}/{sched['s_target']}"
+
+
+def stage_variant_tag(sched: dict, stage: str) -> str:
+    """The part of a schedule that selects a stage's kernel and launch shape."""
+    if stage in ("zinv", "plane"):
+        return str(sched[stage])
+    if stage == "zfwd":
+        return f"{sched['zfwd']}/{sched['s_target']}"
+    return "-"
+
+
+def traffic_from_profiles(workload: str, prec: str, sched: dict):
+    """Measured HBM bytes per evaluation of each stage (FETCH_SIZE and WRITE_SIZE
+    counters, scaled by the copy calibration) from the committed summary
+    profiles/traffic_<workload>_<prec>.md: {stage: (read, write, launches per
+    evaluation, kernel)}.  Stages whose record was taken with other kernel
+    sources or another kernel variant are left out."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.md")
+    out = {}
     if not os.path.exists(path):
-        return None
-    vals = {}
+        return out
+    h = kernel_hash()
     with open(path) as fh:
         for line in fh:
-            if line.startswith("traffic:"):
-                for kv in line.split()[1:]:
-                    k, v = kv.split("=")
-                    vals[k] = v
-    # kernel names are written with '_' for blanks so that the line splits on whitespace
-    if vals.get("kernel_hash") != kernel_hash() or vals.get("kernel") != kernel_tag.replace(" ", "_"):
-        return None
-    try:
-        return float(vals["bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+            if not line.startswith("traffic:"):
+                continue
+            vals = dict(kv.split("=", 1) for kv in line.split()[1:])
+            st = vals.get("stage")
+            if vals.get("kernel_hash") != h or st not in STAGES or vals.get("variant") != stage_variant_tag(sched, st):
+                continue
+            try:
+                # kernel names are written without blanks
+                out[vals["stage"]] = (float(vals["read_per_eval"]), float(vals["write_per_eval"]),
+                                      float(vals["launches_per_eval"]), vals["kernel"])
+            except (KeyError, ValueError):
+                continue
+    return out
+
+
+def stage_rooflines(N: int, npairs: int, esz: int, stages: dict, n_evals: int, traffic: dict):
+    """Roofline object per stage from the HIP-event durations of its launches
+    (stages[name] = (total ms, launches) over n_evals evaluations): per launch,
+    the algorithmic flops and bytes of stage_model divided by the launches of
+    an evaluation, over the average launch duration; `traffic` is the measured
+    HBM bytes per launch (read + write) when a matching counter record exists,
+    with its ratio to the algorithmic bytes."""
+    model = stage_model(N, npairs, esz)
+    peak = PEAK["fp32"] if esz == 4 else PEAK["fp64"]
+    out = {}
+    for name in STAGES:
+        if name not in stages or stages[name][1] == 0:
+            continue
+        ms, launches = stages[name]
+        per_eval = launches / n_evals
+        fl, by = model[name]
+        avg_s = ms * 1e-3 / launches
+        r = roof(fl / per_eval, by / per_eval, avg_s, peak)
+        t = traffic.get(name)
+        r["traffic"] = round((t[0] + t[1]) / per_eval) if t else None
+        r["traffic_over_alg_bytes"] = (round((t[0] + t[1]) / by, 2) if (t and by > 0) else None)
+        r.update({"avg_launch_ms": round(avg_s * 1e3, 5), "launches_per_eval": round(per_eval, 3),
+                  "alg_flop_per_launch": fl / per_eval, "alg_bytes_per_launch": by / per_eval,
+                  "ms_per_eval": round(ms / n_evals, 4)})
+        out[name] = r
+    return out
 
 
 # ------------------------------------------------------- batched and served
@@ -190,20 +259,27 @@ def serve_bench(rates, duration, precision="fp32"):
             for r in rates]
 
 
-def whole_path(N, npairs, esz, per_eval_ms):
+def whole_path(N, npairs, esz, per_eval_ms, traffic=None):
     """Whole-evaluation roofline: the method's own HBM bytes (weight table, f in,
     Q out) and its flops (flop_model) against the MI355X peaks; the binding
-    roof is the larger of the two times."""
+    roof is the larger of the two times.  With a complete per-stage traffic
+    record, the measured HBM bytes per evaluation and their ratio to the
+    algorithmic bytes."""
     fm = flop_model(N, npairs)
     tb = table_bytes(N, npairs, esz) + 2 * N ** 3 * 16
     t = per_eval_ms * 1e-3
     peak = PEAK["fp32"] if esz == 4 else PEAK["fp64"]
     t_roof = max(tb / HBM_PEAK, fm["total"] / (peak * 1e12))
-    return {"alg_gflop_per_eval": round(fm["total"] / 1e9, 3),
-            "tflops_whole_path": round(fm["total"] / t / 1e12, 3),
-            "alg_bytes_per_eval": tb, "hbm_gbps_alg": round(tb / t / 1e9, 1),
-            "t_roof_ms": round(t_roof * 1e3, 4), "frac_of_roof": round(t_roof / t, 4),
-            "binding_roof": "valu" if fm["total"] / (peak * 1e12) > tb / HBM_PEAK else "hbm"}
+    out = {"alg_gflop_per_eval": round(fm["total"] / 1e9, 3),
+           "tflops_whole_path": round(fm["total"] / t / 1e12, 3),
+           "alg_bytes_per_eval": tb, "hbm_gbps_alg": round(tb / t / 1e9, 1),
+           "t_roof_ms": round(t_roof * 1e3, 4), "frac_of_roof": round(t_roof / t, 4),
+           "binding_roof": "alu" if fm["total"] / (peak * 1e12) > tb / HBM_PEAK else "hbm"}
+    if traffic and all(k in traffic for k in ("zinv", "plane", "zfwd")):
+        meas = sum(v[0] + v[1] for v in traffic.values())
+        out["traffic_per_eval"] = round(meas)
+        out["traffic_over_alg_bytes"] = round(meas / tb, 2)
+    return out
 
 
 # ---------------------------------------------------------------- CPU oracle
@@ -389,6 +465,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run 3 device-to-device copies of MIB MiB (reference kernel for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--profile-workload", choices=("medium", "large"), default=None,
+                    help="only run --profile-evals evaluations of that workload with the tuned schedule "
+                         "(for counter runs under rocprofv3) and exit")
+    ap.add_argument("--profile-prec", choices=("fp32", "fp64"), default="fp32")
+    ap.add_argument("--profile-evals", type=int, default=3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -412,6 +493,24 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}))
         return
 
+    if args.profile_workload:
+        cfg = MEDIUM if args.profile_workload == "medium" else LARGE
+        mix = workloads.two_maxwellians(0) if cfg is MEDIUM else workloads.random_mixture(0)
+        fd = torch.from_numpy(workloads.to_spectral(mix.sample(cfg["N"], cfg["L"]))).to("cuda")
+        plan = bzq.Plan(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"], cfg["N_rho"], cfg["M"],
+                        precision=args.profile_prec)
+        plan.autotune(fd)
+        q = torch.empty_like(fd)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_start": True}), flush=True)
+        for _ in range(args.profile_evals):
+            plan.collision(fd, q)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_workload": args.profile_workload, "precision": args.profile_prec,
+                          "evals": args.profile_evals, "schedule": plan.schedule(), "info": plan.info(),
+                          "kernel_hash": kernel_hash()}), flush=True)
+        return
+
     cfg = MEDIUM
     fhat = workloads.to_spectral(workloads.two_maxwellians(0).sample(cfg["N"], cfg["L"]))
     # FP32-bulk / FP64-accumulate (headline) and the plain FP64 path
@@ -424,33 +523,18 @@ def main():
 
     info = p32.info()
     npairs = info["npairs"]
-    fm = flop_model(cfg["N"], npairs)
     evals32 = 2 * args.steps
     value = evals32 / (ms32 * 1e-3)
     value64 = 2 * steps64 / (ms64 * 1e-3)
-    # dominant kernel: the plane transforms (stage 2)
+    sched32 = p32.schedule()
+    tr32 = traffic_from_profiles("medium", "fp32", sched32)
+    # dominant kernel: the plane transforms (stage 2), timed inside the timed region
     plane_ms, plane_n = st32.pop("plane_timed_region")
-    avg_plane_s = plane_ms * 1e-3 / plane_n
-    pts_per_launch = (npairs // 2) / (plane_n / evals32)
-    flop_launch = fm["plane_per_pt"] * pts_per_launch
-    bytes_launch = plane_bytes_per_pt(cfg["N"], 4) * pts_per_launch
-    tflops = flop_launch / avg_plane_s / 1e12
-    gbps = bytes_launch / avg_plane_s / 1e9
-    kern_tag = f"k_plane_reg<float, {cfg['N']}, {3 * cfg['N'] // 2}, 0>"
-    traffic = traffic_from_profiles(kern_tag)
-    # the binding roof of the roofline model: the larger of bytes / HBM peak
-    # and flops / FP32 vector peak
-    if bytes_launch / HBM_PEAK >= flop_launch / (PEAK["fp32"] * 1e12):
-        roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": round(gbps / (HBM_PEAK / 1e9), 4)}
-    else:
-        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                "frac": round(tflops / PEAK["fp32"], 4)}
-    roof.update({"traffic": traffic, "kernel": kern_tag, "avg_launch_ms": round(avg_plane_s * 1e3, 5),
-                 "alg_bytes_per_launch": bytes_launch, "alg_flop_per_launch": flop_launch,
-                 "other_roof": ({"alu_tflops": round(tflops, 3), "alu_frac": round(tflops / PEAK["fp32"], 4)}
-                                if roof["bound"] == "hbm" else
-                                {"hbm_gbps": round(gbps, 1), "hbm_frac": round(gbps / (HBM_PEAK / 1e9), 4)})})
+    roof_obj = stage_rooflines(cfg["N"], npairs, 4, {"plane": (plane_ms, plane_n)}, evals32, tr32)["plane"]
+    roof_obj["kernel"] = (tr32["plane"][3] if "plane" in tr32 else
+                          f"plane stage, schedule {sched_tag(sched32)}")
+    roof_obj["traffic_note"] = ("measured HBM bytes per launch: the z-inverse output read and the plane "
+                                "output written (pipeline intermediates; the stage has no algorithmic bytes)")
     # the paper's integrator: classical RK4 steps (4 evaluations each) with the tuned plan
     fd_rk = torch.from_numpy(fhat).to("cuda")
     p32.step(fd_rk, DT, 1, method="rk4")
@@ -464,7 +548,7 @@ def main():
     rk_ms = r0.elapsed_time(r1) / n_rk
     rk4 = {"ms_per_step": round(rk_ms, 4), "evals_per_s": round(4e3 / rk_ms, 2), "steps": n_rk}
     per_eval_ms = ms32 / evals32
-    whole = whole_path(cfg["N"], npairs, 4, ms32 / evals32)
+    whole = whole_path(cfg["N"], npairs, 4, ms32 / evals32, tr32)
     stage_ms = {k: round(v[0] / evals32, 4) for k, v in st32.items()}
 
     out = {
@@ -485,13 +569,18 @@ def main():
                    "N": cfg["N"], "L": cfg["L"], "R": cfg["R"], "N_rho": cfg["N_rho"], "M": cfg["M"],
                    "gamma": cfg["gamma"], "s": cfg["s"], "precision": "fp32 bulk, fp64 accumulate",
                    "antipodal_pairs": npairs},
-        "roofline": roof,
-        "schedule": {"fp32": p32.schedule(), "fp64": p64.schedule()},
+        "roofline": roof_obj,
+        "schedule": {"fp32": sched32, "fp64": p64.schedule()},
         "fp64": {"value": round(value64, 3), "ms_per_step": round(ms64 / steps64, 4),
-                 "stage_ms_per_eval": {k: round(v[0] / (2 * steps64), 4) for k, v in st64.items()}},
+                 "stage_ms_per_eval": {k: round(v[0] / (2 * steps64), 4) for k, v in st64.items()},
+                 "kernels": stage_rooflines(cfg["N"], npairs, 8, st64, 2 * steps64,
+                                            traffic_from_profiles("medium", "fp64", p64.schedule())),
+                 "whole_path": whole_path(cfg["N"], npairs, 8, ms64 / (2 * steps64),
+                                          traffic_from_profiles("medium", "fp64", p64.schedule()))},
         "err_fp32_vs_fp64": err32_64,
         "rk4_step": rk4,
         "stage_ms_per_eval": stage_ms,
+        "kernels": stage_rooflines(cfg["N"], npairs, 4, st32, evals32, tr32),
         "whole_path": whole,
         "wall_s": {"fp32": round(wall32, 3), "fp64": round(wall64, 3)},
     }
@@ -503,11 +592,14 @@ def main():
         for prec in ("fp32", "fp64"):
             p, ms, wall, st, q = time_steps(bzq, torch, cl, prec, fl, 2, 1)
             st.pop("plane_timed_region")
+            esz = 4 if prec == "fp32" else 8
+            npl = p.info()["npairs"]
+            tr = traffic_from_profiles("large", prec, p.schedule())
             large[prec] = {"evals_per_s": round(4 / (ms * 1e-3), 3), "ms_per_eval": round(ms / 4, 3),
                            "stage_ms_per_eval": {k: round(v[0] / 4, 3) for k, v in st.items()},
                            "schedule": p.schedule(),
-                           "whole_path": whole_path(cl["N"], p.info()["npairs"], 4 if prec == "fp32" else 8,
-                                                    ms / 4)}
+                           "kernels": stage_rooflines(cl["N"], npl, esz, st, 4, tr),
+                           "whole_path": whole_path(cl["N"], npl, esz, ms / 4, tr)}
             qs[prec] = q.cpu().numpy()
             del p
             torch.cuda.empty_cache()

@@ -67,10 +67,26 @@ typedef enum {
                               moment in FP64                                           */
 } bzq_precision;
 
+/* Angular kernel of a plan (bzq_plan_create, bzq_plan_create_otf); t = sin^2(th/2):
+ *   BZQ_KERNEL_POWER        b = c_s sin^{-(2+2s)}(th/2) = c_s t^{-1-s}, c_s = (1-s)(2-s)/(24 pi),
+ *                           0 <= s < 1: the non-cutoff kernel of eq. Bb1 (nu = 2s) with the
+ *                           constant that gives the BKW rate lambda = 1/6 of Section 5.1
+ *                           (s = 3/4 is the paper's b8 of Section 5.3);
+ *   BZQ_KERNEL_CUTOFF_CONST b = 1/(4 pi), the cutoff kernel b5 of Section 5.3 (eq. cutoff3D gives
+ *                           its weight in closed form);
+ *   BZQ_KERNEL_GENERAL      b = c t^{-1-s} (1-t)^{-r} with (c, s, r) given explicitly
+ *                           (bzq_plan_create_otf; bzq_plan_create_general takes them always). */
+typedef enum {
+    BZQ_KERNEL_POWER = 0,
+    BZQ_KERNEL_CUTOFF_CONST = 1,
+    BZQ_KERNEL_GENERAL = 2
+} bzq_kernel;
+
 /*
- * Create a plan for the operator of eq. realQ with the power-law angular
- * kernel b = c_s sin^{-(2+2s)}(th/2), c_s = (1-s)(2-s)/(24 pi) (the
- * normalisation that gives the BKW rate lambda = 1/6 of Section 5.1).
+ * Create a plan for the operator of eq. realQ (Section 4: the Gauss-Legendre
+ * rule in |q| and the sphere rule of eq. approxG, the weight F of eq. FF
+ * precomputed as in Section 4.1) with the angular kernel `kernel`
+ * (BZQ_KERNEL_POWER or BZQ_KERNEL_CUTOFF_CONST; `s` is ignored for the latter).
  *   N      grid size per axis; one of 8, 16, 24, 32, 48, 64 (EUNSUPPORTED else)
  *   L      half-width of the periodic box D_L (> 0)
  *   R      radius of the ball B_R that truncates |q| (> 0)
@@ -84,7 +100,7 @@ typedef enum {
  * are ready.  On failure *out is set to NULL and nothing stays allocated.
  */
 bzq_status bzq_plan_create(bzq_plan* out, int N, double L, double R, double gamma, double s,
-                           int N_rho, int M, int precision, void* stream);
+                           int N_rho, int M, int precision, int kernel, void* stream);
 
 /*
  * Same with a general angular kernel b = c t^{-1-s} (1-t)^{-r}
@@ -110,8 +126,8 @@ bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, dou
 bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, double theta_cut, int N_rho, int M,
                                  int precision, void* stream);
 
-/* The same plan with its weights evaluated on the fly (beyond the paper):
- * no table of J N^3 / 2 weights is stored or built.  Before the last stage of
+/* The operator of eq. realQ (Section 4) with its weights evaluated on the fly
+ * (beyond the paper): no table of J N^3 / 2 weights is stored or built.  Before the last stage of
  * each block of pairs (at most 128 MiB of weights, or $BZQ_OTF_MB), a kernel
  * evaluates that block's weights from the Funk-Hecke series of the exact
  * weight of eq. FF,
@@ -121,13 +137,17 @@ bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, doubl
  * most 64 even terms, r <= ~80).  The plan then holds N_rho x (terms rounded
  * up to 8) x (3 (N/2-1)^2 + 1) coefficients (71 MB at N = 64, N_rho = 64)
  * instead of the weight table (4.8 GB FP32, 9.7 GB FP64 at N = 64, M = 302),
- * and its workspace one block of weights.  Same arguments and limits as
- * bzq_plan_create_general (there is no n_jacobi: the series moments use their
- * own exact Gauss-Jacobi rule); every other call accepts the plan unchanged.
+ * and its workspace one block of weights.  `kernel` selects the angular kernel
+ * (bzq_kernel): BZQ_KERNEL_POWER takes s = b_s (b_c, b_r ignored),
+ * BZQ_KERNEL_CUTOFF_CONST ignores all three, BZQ_KERNEL_GENERAL takes
+ * b = b_c t^{-1-b_s} (1-t)^{-b_r} with the limits of bzq_plan_create_general
+ * (there is no n_jacobi: the series moments use their own exact Gauss-Jacobi
+ * rule).  Every other call accepts the plan unchanged.
  * BZQ_EUNSUPPORTED, before any device work, if the series would need more
  * than 64 terms. */
-bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, double b_c,
-                               double b_s, double b_r, int N_rho, int M, int precision, void* stream);
+bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, int kernel,
+                               double b_c, double b_s, double b_r, int N_rho, int M, int precision,
+                               void* stream);
 
 /* A plan for another gamma that shares the tables of `base` (weights,
  * phases, twiddles: they do not depend on gamma, which enters eq. realQ only
@@ -143,21 +163,33 @@ bzq_status bzq_plan_derive_gamma(bzq_plan* out, bzq_plan base, double gamma, voi
  * (bzq_plan_device_bytes counts them too). */
 size_t bzq_plan_shared_bytes(bzq_plan p);
 
-/* Q_hat = Q(f_hat, f_hat) (eq. realQ).  f_hat and Q_hat: device, complex128
- * N^3 (layout above); they must not overlap.  Q_hat[0] is exactly 0
- * (Remark 4.1).  A non-finite f_hat gives a non-finite Q_hat. */
+/* Q_hat = Q(f_hat, f_hat): the truncated weighted convolution of eq. sum with
+ * G replaced by its quadrature eq. approxG, evaluated in the fast form of
+ * eq. realQ (Section 4).  f_hat and Q_hat: device, complex128 N^3 (layout
+ * above); the two byte ranges must not overlap (BZQ_EINVAL).  Q_hat[0] is
+ * exactly 0 (the remark after eq. realQ: F(0, rho, sigma) = 0).
+ * Non-finite input: the first stage of the evaluation (the copy of f_hat into
+ * the padded spectrum) also reduces a NaN/Inf flag over every entry it reads
+ * (all but the Nyquist planes); the call waits for that flag (a stream
+ * synchronisation up to this stage) and returns BZQ_ENONFINITE before any
+ * launch that writes Q_hat, which is then left untouched.  Otherwise the rest
+ * of the evaluation is enqueued asynchronously. */
 bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream);
 
-/* Advance d f/dt = Q(f, f) by n_steps steps of Heun's method (explicit
- * trapezoid: f* = f + dt Q(f), f <- f + dt/2 (Q(f) + Q(f*))), in place on the
- * device array f_hat. */
+/* Advance the Galerkin system d f_k/dt = Q_k (Section 2, the ODE system that
+ * follows eq. weak) by n_steps steps of Heun's method (explicit trapezoid:
+ * f* = f + dt Q(f), f <- f + dt/2 (Q(f) + Q(f*))), in place on the device
+ * array f_hat.  dt finite, n_steps >= 0, else BZQ_EINVAL.  The input state is
+ * checked as in bzq_collision: BZQ_ENONFINITE, with f_hat untouched, if it
+ * holds NaN/Inf (the states inside the n_steps are the library's own). */
 bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream);
 
 /* The same with the classical fourth-order Runge-Kutta method, the time
  * integrator of the paper's experiments (Section 5): four evaluations per step,
  *   k1 = Q(f), k2 = Q(f + dt/2 k1), k3 = Q(f + dt/2 k2), k4 = Q(f + dt k3),
  *   f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4),
- * in place on the device array f_hat (FP64 state and stage sums). */
+ * in place on the device array f_hat (FP64 state and stage sums).  Arguments,
+ * errors and the check of the input state as for bzq_step. */
 bzq_status bzq_step_rk4(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream);
 
 /*
@@ -182,6 +214,8 @@ bzq_status bzq_check_finite(bzq_plan p, const double* f_hat, void* stream);
  * path.  bzq_workspace_destroy synchronises the device.
  */
 bzq_status bzq_workspace_create(bzq_workspace* out, bzq_plan p);
+/* bzq_collision / bzq_step (eq. realQ; Heun's method) with scratch from w, with
+ * the same argument checks and the same BZQ_ENONFINITE behaviour. */
 bzq_status bzq_collision_ws(bzq_plan p, bzq_workspace w, const double* f_hat, double* Q_hat,
                             void* stream);
 bzq_status bzq_step_ws(bzq_plan p, bzq_workspace w, double* f_hat, double dt, int n_steps,
@@ -190,15 +224,19 @@ size_t bzq_workspace_bytes(bzq_workspace w);
 bzq_status bzq_workspace_destroy(bzq_workspace w);
 
 /*
- * Independent cells, simple form: Q_hats[i] = Q(f_hats[i]) under plans[i],
+ * Independent cells, simple form: Q_hats[i] = Q(f_hats[i]) of eq. realQ under
+ * plans[i] (each cell is its own spatially homogeneous problem, Section 2),
  * enqueued cell after cell on `stream` with each plan's built-in workspace.
- * Each result is bitwise identical to bzq_collision.
+ * Each result is bitwise identical to bzq_collision.  Arrays are host arrays
+ * of `count` device pointers; BZQ_EINVAL for NULL entries, count < 1 or an
+ * f/Q pair that overlaps.  No input check for NaN/Inf (asynchronous).
  */
 bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hats,
                                double* const* Q_hats, int count, void* stream);
 
 /*
- * Independent cells, fused form.  A batch binds `count` cells (state arrays
+ * Independent cells, fused form (eq. realQ and Heun's method per cell, the
+ * cells being independent homogeneous problems, Section 2).  A batch binds `count` cells (state arrays
  * f_hats[i], device, complex128 N_i^3, owned by the caller and kept alive as
  * long as the batch) to plans (which may repeat and may differ in N, gamma,
  * kernel and precision).  Cells sharing a plan run in the same launches, up
@@ -295,9 +333,12 @@ size_t bzq_plan_device_bytes(bzq_plan p);
 /* The same figure computed before creating a plan of this geometry. */
 size_t bzq_plan_bytes_estimate(int N, int N_rho, int M, int precision);
 
-/* Per-request state a caller needs besides a plan: f_hat and Q_hat for one
- * cell of size N (complex128 N^3 each). */
-size_t bzq_request_device_bytes(int N);
+/* Device bytes one more concurrently served cell of size N needs besides its
+ * plan's tables: its state f_hat and Q_hat (complex128 N^3 each) plus the
+ * scratch of one workspace (bzq_workspace_create) of any plan of this N and
+ * precision (an upper bound over N_rho and M: the pipeline's chunk of pairs
+ * is capped).  0 for an invalid N or precision. */
+size_t bzq_request_device_bytes(int N, int precision);
 
 /*
  * Introspection for tests:

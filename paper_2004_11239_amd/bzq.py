@@ -8,7 +8,6 @@ fallback: if the library is missing the import fails.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from typing import Optional, Sequence
 
@@ -21,6 +20,10 @@ FP64 = 0
 FP32_ACC64 = 1
 _PREC = {"fp64": FP64, "f64": FP64, FP64: FP64, "fp32": FP32_ACC64, "fp32_acc64": FP32_ACC64,
          FP32_ACC64: FP32_ACC64}
+
+KERNEL_POWER = 0
+KERNEL_CUTOFF_CONST = 1
+KERNEL_GENERAL = 2
 
 STATUS = {0: "BZQ_OK", 1: "BZQ_EINVAL", 2: "BZQ_ENOMEM", 3: "BZQ_EDEVICE", 4: "BZQ_EUNSUPPORTED",
           5: "BZQ_ENONFINITE"}
@@ -46,9 +49,9 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, d, i, sz = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
     sigs = {
-        "bzq_plan_create": ([ctypes.POINTER(vp), i, d, d, d, d, i, i, i, vp], i),
+        "bzq_plan_create": ([ctypes.POINTER(vp), i, d, d, d, d, i, i, i, i, vp], i),
         "bzq_plan_create_general": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, i, vp], i),
-        "bzq_plan_create_otf": ([ctypes.POINTER(vp), i, d, d, d, d, d, d, i, i, i, vp], i),
+        "bzq_plan_create_otf": ([ctypes.POINTER(vp), i, d, d, d, i, d, d, d, i, i, i, vp], i),
         "bzq_plan_create_debye": ([ctypes.POINTER(vp), i, d, d, d, i, i, i, vp], i),
         "bzq_plan_derive_gamma": ([ctypes.POINTER(vp), vp, d, vp], i),
         "bzq_plan_shared_bytes": ([vp], sz),
@@ -62,7 +65,7 @@ def _load():
         "bzq_check_finite": ([vp, vp, vp], i),
         "bzq_collision_batch": ([ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i, vp], i),
         "bzq_plan_device_bytes": ([vp], sz),
-        "bzq_request_device_bytes": ([i], sz),
+        "bzq_request_device_bytes": ([i, i], sz),
         "bzq_plan_info": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_pairs": ([vp, ctypes.POINTER(d)], i),
         "bzq_plan_weights": ([vp, i, ctypes.POINTER(d)], i),
@@ -147,7 +150,8 @@ class Plan:
     def __init__(self, N: int, L: float, R: float, gamma: float, s: float, N_rho: int, M: int,
                  precision="fp64", kernel: Optional[Sequence[float]] = None, n_jacobi: int = 64,
                  stream=None, weights: str = "table"):
-        """kernel=None: b = c_s sin^{-(2+2s)}(th/2), c_s = (1-s)(2-s)/(24 pi).
+        """kernel=None: b = c_s sin^{-(2+2s)}(th/2), c_s = (1-s)(2-s)/(24 pi) (BZQ_KERNEL_POWER);
+        kernel="cutoff": b = 1/(4 pi) (BZQ_KERNEL_CUTOFF_CONST; `s` is ignored);
         kernel=(c, s_b, r): b = c t^{-1-s_b} (1-t)^{-r}, t = sin^2(th/2) (then `s` is ignored).
         weights="table" stores the weights at creation; "otf" evaluates them per
         chunk of pairs from their series (bzq_plan_create_otf)."""
@@ -159,17 +163,22 @@ class Plan:
         self.weights_mode = weights
         h = ctypes.c_void_p()
         st = _stream(stream)
-        if weights == "otf":
-            if kernel is None:
-                kernel = ((1 - s) * (2 - s) / (24 * math.pi), float(s), 0.0)
+        if kernel is None:
+            self.kernel, ksel, kargs = ("power", float(s)), KERNEL_POWER, (0.0, float(s), 0.0)
+        elif isinstance(kernel, str):
+            if kernel != "cutoff":
+                raise ValueError("kernel must be None, 'cutoff' or (c, s, r)")
+            self.kernel, ksel, kargs = ("cutoff",), KERNEL_CUTOFF_CONST, (0.0, 0.0, 0.0)
+        else:
             self.kernel = tuple(float(x) for x in kernel)
-            c, sb, r = self.kernel
-            code = _lib.bzq_plan_create_otf(ctypes.byref(h), self.N, self.L, self.R, self.gamma, c, sb, r,
+            ksel, kargs = KERNEL_GENERAL, self.kernel
+        if weights == "otf":
+            c, sb, r = kargs
+            code = _lib.bzq_plan_create_otf(ctypes.byref(h), self.N, self.L, self.R, self.gamma, ksel, c, sb, r,
                                             self.N_rho, self.M, self.precision, st)
-        elif kernel is None:
-            self.kernel = ((1 - s) * (2 - s) / (24 * math.pi), float(s), 0.0)
-            code = _lib.bzq_plan_create(ctypes.byref(h), self.N, self.L, self.R, self.gamma, float(s),
-                                        self.N_rho, self.M, self.precision, st)
+        elif ksel != KERNEL_GENERAL:
+            code = _lib.bzq_plan_create(ctypes.byref(h), self.N, self.L, self.R, self.gamma, kargs[1],
+                                        self.N_rho, self.M, self.precision, ksel, st)
         else:
             self.kernel = tuple(float(x) for x in kernel)
             c, sb, r = self.kernel
@@ -397,8 +406,8 @@ def collision_batch(plans: Sequence[Plan], f_hats: Sequence[torch.Tensor], outs:
     return outs
 
 
-def request_device_bytes(N: int) -> int:
-    return int(_lib.bzq_request_device_bytes(int(N)))
+def request_device_bytes(N: int, precision="fp32") -> int:
+    return int(_lib.bzq_request_device_bytes(int(N), _PREC[precision]))
 
 
 class Workspace:

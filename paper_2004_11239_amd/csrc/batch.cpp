@@ -293,8 +293,11 @@ bzq_status bzq_batch_destroy(bzq_batch b) {
 bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hats, double* const* Q_hats,
                                int count, void* stream) {
   if (count < 0 || (count > 0 && (!plans || !f_hats || !Q_hats))) return fail(BZQ_EINVAL, "bad batch arguments");
-  for (int i = 0; i < count; ++i)
+  for (int i = 0; i < count; ++i) {
     if (!plans[i] || !f_hats[i] || !Q_hats[i]) return fail(BZQ_EINVAL, "NULL entry in batch");
+    if (ranges_overlap(f_hats[i], Q_hats[i], state_bytes(plans[i]->N)))
+      return fail(BZQ_EINVAL, "f_hat and Q_hat of a cell overlap");
+  }
   for (int i = 0; i < count; ++i) {
     bzq_status s = enqueue_collision(*plans[i], plans[i]->ws, single(f_hats[i]), single(Q_hats[i]), 1,
                                      (hipStream_t)stream);

@@ -76,7 +76,7 @@ size_t Plan::workspace_bytes_per_cell() const {
   const size_t N3 = (size_t)N * N * N;
   return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * nn * 2 * esz +
          (size_t)G * P * 2 * nhp * 2 * esz + (size_t)S_cap * nh * n1 * 16 + 3 * N3 * 16 +
-         (otf ? (size_t)2 * Gw * nh * n1 * esz : 0);
+         (otf ? (size_t)2 * Gw * nh * n1 * esz : 0) + 4 * sizeof(int);
 }
 
 bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
@@ -100,6 +100,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   if ((s = w.arena.get(&w.q2, cells * N3 * 16)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.fs, cells * N3 * 16)) != BZQ_OK) return s;
   if (p.otf && (s = w.arena.get(&w.Vc, (size_t)2 * p.Gw * p.nh * p.n1 * p.esz)) != BZQ_OK) return s;
+  if ((s = w.arena.get(&w.flag, 4 * sizeof(int))) != BZQ_OK) return s;
   return BZQ_OK;
 }
 
@@ -486,19 +487,30 @@ hipError_t mark(Plan& p, int stage, bool begin, hipStream_t st) {
 
 // Enqueue one evaluation of eq. realQ for `cells` cells of plan p.
 bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrPack& Q, int cells,
-                             hipStream_t st, const FinUpdate& upd) {
+                             hipStream_t st, const FinUpdate& upd, bool check) {
   if (cells < 1 || cells > w.cells) return fail(BZQ_EINVAL, "more cells than the workspace holds");
   const Geometry g{p.N, p.P};
   CellStrides cs = w.cs;
   cs.cells = cells;
-  // the compact spectrum fc, then f(v) on the padded grid, shared by every
-  // pair (the copy and the first transform in one launch where they fit)
+  // a0: the compact spectrum fc (with the NaN/Inf flag when checked), then
+  // f(v) on the padded grid, shared by every pair (the copy and the first
+  // transform in one launch where they fit)
+  int* flag = check ? w.flag : nullptr;
+  if (check) BZQ_HIP_TRY(launch_fill_int(w.flag, 0, 1, st));
   if (zinv_ingest_fits(p.P, p.fp32)) {
-    TIMED(ST_PREP, launch_zinv_ingest(f, w.fc, w.A, g, p.fp32, cs, st));
+    TIMED(ST_PREP, launch_zinv_ingest(f, w.fc, w.A, g, p.fp32, cs, st, flag));
   } else {
-    TIMED(ST_PREP, launch_ingest(f, w.fc, cs.fc, cells, p.N, p.fp32, st));
-    TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
+    TIMED(ST_PREP, launch_ingest(f, w.fc, cs.fc, cells, p.N, p.fp32, st, flag));
   }
+  if (check) {
+    // nothing that writes an output has been enqueued yet
+    int h = 0;
+    BZQ_HIP_TRY(hipMemcpyAsync(&h, w.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    BZQ_HIP_TRY(hipStreamSynchronize(st));
+    if (h) return fail(BZQ_ENONFINITE, "f_hat holds NaN or Inf (outputs left untouched)");
+  }
+  if (!zinv_ingest_fits(p.P, p.fp32))
+    TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
   TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st));
   // the first last-stage launch writes the S partial accumulators of every
   // cell, later ones add to them
@@ -528,7 +540,7 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
 }
 
 bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
-                        hipStream_t st) {
+                        hipStream_t st, bool check) {
   const size_t n3 = (size_t)p.N * p.N * p.N;
   PtrPack q1{}, q2{}, fs{};
   for (int c = 0; c < cells; ++c) {
@@ -551,7 +563,7 @@ bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, doub
   heun.f = f;
   for (int i = 0; i < n_steps; ++i) {
     bzq_status s;
-    if ((s = enqueue_collision(p, w, f, q1, cells, st, stage)) != BZQ_OK) return s;
+    if ((s = enqueue_collision(p, w, f, q1, cells, st, stage, check && i == 0)) != BZQ_OK) return s;
     if ((s = enqueue_collision(p, w, fs, q2, cells, st, heun)) != BZQ_OK) return s;
   }
   return BZQ_OK;
@@ -561,7 +573,7 @@ bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, doub
 // k3 = Q(f + dt/2 k2), k4 = Q(f + dt k3), f <- f + dt/6 (k1 + 2 k2 + 2 k3 + k4);
 // q1 holds the current stage's Q, q2 the running sum, fs the stage argument.
 bzq_status enqueue_step_rk4(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
-                            hipStream_t st) {
+                            hipStream_t st, bool check) {
   const size_t n3 = (size_t)p.N * p.N * p.N;
   PtrPack q{}, acc{}, fs{};
   for (int c = 0; c < cells; ++c) {
@@ -571,7 +583,7 @@ bzq_status enqueue_step_rk4(Plan& p, Workspace& w, const PtrPack& f, int cells, 
   }
   for (int i = 0; i < n_steps; ++i) {
     bzq_status s;
-    if ((s = enqueue_collision(p, w, f, q, cells, st)) != BZQ_OK) return s;
+    if ((s = enqueue_collision(p, w, f, q, cells, st, FinUpdate{}, check && i == 0)) != BZQ_OK) return s;
     BZQ_HIP_TRY(launch_axpy_cells(acc, f, dt / 6.0, q, n3, cells, st));
     BZQ_HIP_TRY(launch_axpy_cells(fs, f, 0.5 * dt, q, n3, cells, st));
     if ((s = enqueue_collision(p, w, fs, q, cells, st)) != BZQ_OK) return s;
@@ -628,6 +640,36 @@ bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, d
 
 double power_kernel_constant(double s) { return (1.0 - s) * (2.0 - s) / (24.0 * (double)kPi); }
 
+// (c, s, r) of b = c t^{-1-s} (1-t)^{-r} for a bzq_kernel selector: the power
+// kernel c_s t^{-1-s} (0 <= s < 1), the constant cutoff kernel 1/(4 pi)
+// (= c t^{-1-s} with s = -1: b5 of Section 5.3), or (when `general` is
+// allowed) the explicit triple.
+bzq_status kernel_params(int kernel, double s, double c, double r, bool general, double* bc, double* bs,
+                         double* br) {
+  switch (kernel) {
+    case BZQ_KERNEL_POWER:
+      if (!(s >= 0.0 && s < 1.0)) return fail(BZQ_EINVAL, "s must lie in [0, 1)");
+      *bc = power_kernel_constant(s);
+      *bs = s;
+      *br = 0.0;
+      return BZQ_OK;
+    case BZQ_KERNEL_CUTOFF_CONST:
+      *bc = (double)(1.0L / (4.0L * kPi));
+      *bs = -1.0;
+      *br = 0.0;
+      return BZQ_OK;
+    case BZQ_KERNEL_GENERAL:
+      if (!general) break;
+      *bc = c;
+      *bs = s;
+      *br = r;
+      return BZQ_OK;
+    default:
+      break;
+  }
+  return fail(BZQ_EINVAL, "unknown angular kernel selector");
+}
+
 namespace {
 
 // f on the physical N^3 grid (FP64) into dst, layout [z][x][y]
@@ -651,12 +693,14 @@ struct bzq_workspace_s : bzq::Workspace {};
 extern "C" {
 
 bzq_status bzq_plan_create(bzq_plan* out, int N, double L, double R, double gamma, double s, int N_rho, int M,
-                           int precision, void* stream) {
-  if (!(s >= 0.0 && s < 1.0)) {
+                           int precision, int kernel, void* stream) {
+  double bc = 0, bs = 0, br = 0;
+  const bzq_status ks = kernel_params(kernel, s, 0.0, 0.0, false, &bc, &bs, &br);
+  if (ks != BZQ_OK) {
     if (out) *out = nullptr;
-    return fail(BZQ_EINVAL, "s must lie in [0, 1)");
+    return ks;
   }
-  return create_plan(out, N, L, R, gamma, power_kernel_constant(s), s, 0.0, 64, N_rho, M, precision, stream);
+  return create_plan(out, N, L, R, gamma, bc, bs, br, 64, N_rho, M, precision, stream);
 }
 
 bzq_status bzq_plan_create_general(bzq_plan* out, int N, double L, double R, double gamma, double b_c,
@@ -674,9 +718,15 @@ bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, doubl
   return create_plan(out, N, L, R, 1.0, 0.25, 0.0, 0.0, 64, N_rho, M, precision, stream, false, 1, theta_cut);
 }
 
-bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, double b_c, double b_s,
-                               double b_r, int N_rho, int M, int precision, void* stream) {
-  return create_plan(out, N, L, R, gamma, b_c, b_s, b_r, 64, N_rho, M, precision, stream, true);
+bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, int kernel, double b_c,
+                               double b_s, double b_r, int N_rho, int M, int precision, void* stream) {
+  double bc = 0, bs = 0, br = 0;
+  const bzq_status ks = kernel_params(kernel, b_s, b_c, b_r, true, &bc, &bs, &br);
+  if (ks != BZQ_OK) {
+    if (out) *out = nullptr;
+    return ks;
+  }
+  return create_plan(out, N, L, R, gamma, bc, bs, br, 64, N_rho, M, precision, stream, true);
 }
 
 bzq_status bzq_plan_derive_gamma(bzq_plan* out, bzq_plan base, double gamma, void* stream) {
@@ -691,14 +741,15 @@ size_t bzq_plan_shared_bytes(bzq_plan p) { return p ? p->shared->bytes : 0; }
 
 bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream) {
   if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
-  if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
-  return enqueue_collision(*p, p->ws, single(f_hat), single(Q_hat), 1, (hipStream_t)stream);
+  if (ranges_overlap(f_hat, Q_hat, state_bytes(p->N))) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
+  return enqueue_collision(*p, p->ws, single(f_hat), single(Q_hat), 1, (hipStream_t)stream, FinUpdate{}, true);
 }
 
 bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream) {
   if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
-  return enqueue_step(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
+  if (n_steps == 0) return BZQ_OK;
+  return enqueue_step(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream, true);
 }
 
 namespace {
@@ -821,7 +872,8 @@ bzq_status bzq_plan_autotune(bzq_plan p, const double* f_hat, int use_cache, voi
 bzq_status bzq_step_rk4(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream) {
   if (!p || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
-  return enqueue_step_rk4(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
+  if (n_steps == 0) return BZQ_OK;
+  return enqueue_step_rk4(*p, p->ws, single(f_hat), 1, dt, n_steps, (hipStream_t)stream, true);
 }
 
 bzq_status bzq_workspace_create(bzq_workspace* out, bzq_plan p) {
@@ -840,15 +892,16 @@ bzq_status bzq_workspace_create(bzq_workspace* out, bzq_plan p) {
 bzq_status bzq_collision_ws(bzq_plan p, bzq_workspace w, const double* f_hat, double* Q_hat, void* stream) {
   if (!p || !w || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (w->plan != p) return fail(BZQ_EINVAL, "workspace was made for another plan");
-  if (f_hat == Q_hat) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
-  return enqueue_collision(*p, *w, single(f_hat), single(Q_hat), 1, (hipStream_t)stream);
+  if (ranges_overlap(f_hat, Q_hat, state_bytes(p->N))) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
+  return enqueue_collision(*p, *w, single(f_hat), single(Q_hat), 1, (hipStream_t)stream, FinUpdate{}, true);
 }
 
 bzq_status bzq_step_ws(bzq_plan p, bzq_workspace w, double* f_hat, double dt, int n_steps, void* stream) {
   if (!p || !w || !f_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (w->plan != p) return fail(BZQ_EINVAL, "workspace was made for another plan");
   if (!std::isfinite(dt) || n_steps < 0) return fail(BZQ_EINVAL, "bad dt or n_steps");
-  return enqueue_step(*p, *w, single(f_hat), 1, dt, n_steps, (hipStream_t)stream);
+  if (n_steps == 0) return BZQ_OK;
+  return enqueue_step(*p, *w, single(f_hat), 1, dt, n_steps, (hipStream_t)stream, true);
 }
 
 size_t bzq_workspace_bytes(bzq_workspace w) { return w ? w->arena.bytes : 0; }
@@ -917,8 +970,21 @@ size_t bzq_plan_bytes_estimate(int N, int N_rho, int M, int precision) {
   return plan_footprint(N, N_rho, M, precision);
 }
 
-size_t bzq_request_device_bytes(int N) {
-  return N > 0 ? 2ull * N * N * N * 2 * sizeof(double) : 0;
+size_t bzq_request_device_bytes(int N, int precision) {
+  if (N < 8 || (N & 1) || (precision != BZQ_FP64 && precision != BZQ_FP32_ACC64)) return 0;
+  // a workspace of any plan of this N: the chunk of pair-twos saturates at its
+  // cap for many pairs, so a plan with very many pairs bounds every other
+  Plan p;
+  p.N = N;
+  p.P = 3 * N / 2;
+  p.n1 = N - 1;
+  p.nn = p.n1 * p.n1;
+  p.nh = (p.nn + 1) / 2;
+  p.fp32 = precision == BZQ_FP32_ACC64;
+  p.npairs = 1 << 24;
+  p.npt = p.npairs / 2;
+  set_chunking(p);
+  return 2 * state_bytes(N) + p.workspace_bytes_per_cell();
 }
 
 bzq_status bzq_plan_info(bzq_plan p, double* out) {

@@ -160,19 +160,25 @@ __device__ __forceinline__ void add_partials(double2* __restrict__ Qpart, const 
 }
 
 // ------------------------------------------------------------------ ingest
+// With flag != nullptr, flag[0] is set to 1 when any value read (every entry
+// off the Nyquist planes) is NaN or Inf: the input check of the a0 stage.
 template <typename T>
-__global__ void k_ingest(PtrPack fin, cx<T>* __restrict__ fc, size_t fc_stride, int N) {
+__global__ void k_ingest(PtrPack fin, cx<T>* __restrict__ fc, size_t fc_stride, int N, int* __restrict__ flag) {
   const int n1 = N - 1, h = N / 2;
   const int total = n1 * n1 * n1;
   const double2* __restrict__ f = (const double2*)fin.p[blockIdx.y];
   fc += blockIdx.y * fc_stride;
+  bool bad = false;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     const int i3 = e / (n1 * n1);
     const int i2 = (e / n1) % n1;
     const int i1 = e % n1;
     const int a = (i1 - h + 1 + N) % N, b = (i2 - h + 1 + N) % N, c = (i3 - h + 1 + N) % N;
-    fc[e] = to_cx<T>(f[((size_t)a * N + b) * N + c]);
+    const double2 v = f[((size_t)a * N + b) * N + c];
+    bad |= !isfinite(v.x) || !isfinite(v.y);
+    fc[e] = to_cx<T>(v);
   }
+  if (bad && flag) flag[0] = 1;
 }
 
 // -------------------------------------------------------------------- zinv
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, c
 // ZINV_PLAIN, into the slot of pair-two 0); one thread per pencil c.
 template <typename T, int N, int P, int NT>
 __global__ __launch_bounds__(NT) void k_zinv_ingest(PtrPack fin, cx<T>* __restrict__ fc, cx<T>* __restrict__ A,
-                                                    CellStrides cs) {
+                                                    CellStrides cs, int* __restrict__ flag) {
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1;
   const double2* __restrict__ f = (const double2*)fin.p[blockIdx.z];
   fc += blockIdx.z * cs.fc;
@@ -449,12 +455,16 @@ __global__ __launch_bounds__(NT) void k_zinv_ingest(PtrPack fin, cx<T>* __restri
   cx<T> v[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
+  bool bad = false;
 #pragma unroll
   for (int i3 = 0; i3 < n1; ++i3) {
-    const cx<T> x = to_cx<T>(fp[(i3 - h + 1 + N) % N]);
+    const double2 d = fp[(i3 - h + 1 + N) % N];
+    bad |= !isfinite(d.x) || !isfinite(d.y);
+    const cx<T> x = to_cx<T>(d);
     fc[(size_t)i3 * nn + c] = x;
     v[posKc<N, P>(i3)] = x;
   }
+  if (bad && flag) flag[0] = 1;
   fft_reg<P, +1>(v);
   cx<T>* Aout = A + c;
 #pragma unroll
@@ -1884,6 +1894,9 @@ __global__ void k_heun_cells(PtrPack f, PtrPack q1, PtrPack q2, double hh, size_
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     ff[i] = ff[i] + hh * (a[i] + b[i]);
 }
+__global__ void k_fill_int(int* p, int v, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
 __global__ void k_finite(const double* x, size_t n, int* flag) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     if (!isfinite(x[i])) flag[0] = 1;
@@ -1951,12 +1964,14 @@ hipError_t zinv_reg_t(const void* fc, const double* ph, void* A, int pair0, int 
 }
 
 template <typename T, int P>
-hipError_t zinv_ingest_t(const PtrPack& f, void* fc, void* A, int N, const CellStrides& cs, hipStream_t st) {
+hipError_t zinv_ingest_t(const PtrPack& f, void* fc, void* A, int N, const CellStrides& cs, int* flag,
+                         hipStream_t st) {
   if constexpr (RegFit<T, P>::value && isPad<P>()) {
     constexpr int NN = padN<P>(), nn = (NN - 1) * (NN - 1), NT = 64;
     if (N != NN) return hipErrorInvalidValue;
     dim3 grid((nn + NT - 1) / NT, 1, cs.cells);
-    hipLaunchKernelGGL((k_zinv_ingest<T, NN, P, NT>), grid, dim3(NT), 0, st, f, (cx<T>*)fc, (cx<T>*)A, cs);
+    hipLaunchKernelGGL((k_zinv_ingest<T, NN, P, NT>), grid, dim3(NT), 0, st, f, (cx<T>*)fc, (cx<T>*)A, cs,
+                       flag);
     return hipGetLastError();
   }
   return hipErrorNotSupported;
@@ -2120,13 +2135,13 @@ int zfwd_blocks_t(int variant) {
 }  // namespace
 
 hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells, int N, bool fp32,
-                         hipStream_t st) {
+                         hipStream_t st, int* flag) {
   const size_t n = (size_t)(N - 1) * (N - 1) * (N - 1);
   dim3 grid(grid_for(n, 256), cells);
   if (fp32)
-    hipLaunchKernelGGL(k_ingest<float>, grid, dim3(256), 0, st, f, (cx<float>*)fc, fc_stride, N);
+    hipLaunchKernelGGL(k_ingest<float>, grid, dim3(256), 0, st, f, (cx<float>*)fc, fc_stride, N, flag);
   else
-    hipLaunchKernelGGL(k_ingest<double>, grid, dim3(256), 0, st, f, (cx<double>*)fc, fc_stride, N);
+    hipLaunchKernelGGL(k_ingest<double>, grid, dim3(256), 0, st, f, (cx<double>*)fc, fc_stride, N, flag);
   return hipGetLastError();
 }
 
@@ -2149,10 +2164,11 @@ bool zinv_ingest_fits(int P, bool fp32) {
 }
 
 hipError_t launch_zinv_ingest(const PtrPack& f, void* fc, void* A, Geometry g, bool fp32, const CellStrides& cs,
-                              hipStream_t st) {
-#define CASE(PP) \
-  case PP:       \
-    return fp32 ? zinv_ingest_t<float, PP>(f, fc, A, g.N, cs, st) : zinv_ingest_t<double, PP>(f, fc, A, g.N, cs, st);
+                              hipStream_t st, int* flag) {
+#define CASE(PP)                                                             \
+  case PP:                                                                   \
+    return fp32 ? zinv_ingest_t<float, PP>(f, fc, A, g.N, cs, flag, st)      \
+                : zinv_ingest_t<double, PP>(f, fc, A, g.N, cs, flag, st);
   switch (g.P) { BZQ_PAD_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
@@ -2279,6 +2295,11 @@ hipError_t launch_heun(double* f, const double* q1, const double* q2, double hh,
   hipLaunchKernelGGL(k_heun, dim3(grid_for(2 * n, 256)), dim3(256), 0, st, f, q1, q2, hh, 2 * n);
   return hipGetLastError();
 }
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_int, dim3(grid_for((size_t)n, 64)), dim3(64), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_finite(const double* x, size_t n, int* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_finite, dim3(grid_for(n, 256)), dim3(256), 0, st, x, n, flag);
   return hipGetLastError();

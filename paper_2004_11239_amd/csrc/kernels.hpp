@@ -33,9 +33,11 @@ struct PtrPack {
 };
 
 // Compact spectral copy: fc[i1][i2][i3] (centred, (N-1)^3) from the FFT-order
-// complex128 array f (N^3).  fp32 selects the element type of fc.
+// complex128 array f (N^3).  fp32 selects the element type of fc.  With flag
+// != nullptr, flag[0] is set to 1 if any value read is NaN or Inf (it is
+// never cleared here).
 hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells, int N, bool fp32,
-                         hipStream_t st);
+                         hipStream_t st, int* flag = nullptr);
 
 // launch_ingest and launch_zinv(mode ZINV_PLAIN, one pair-two) in one launch,
 // for the lengths whose pencil fits the register file (zinv_ingest_fits):
@@ -49,7 +51,7 @@ bool zinv_ingest_fits(int P, bool fp32);
 hipError_t launch_collide2d_reg(const void* fc, const void* fgrid, const void* V, const double* ph, const double* cp,
                                 double* Qpart, int N, int npt, int S, bool fp32, hipStream_t st);
 hipError_t launch_zinv_ingest(const PtrPack& f, void* fc, void* A, Geometry g, bool fp32, const CellStrides& cs,
-                              hipStream_t st);
+                              hipStream_t st, int* flag = nullptr);
 
 // Step 1 of the pipeline: modulate (mode ZINV_PAIRS) and inverse-transform along
 // axis 3; writes A[pt][z][c] for pt < npt, z < P, c < (N-1)^2.
@@ -126,6 +128,7 @@ hipError_t launch_table(void* V, const double* pairdat, const double* gj, int nj
                         int npairs, bool fp32, hipStream_t st);
 
 hipError_t launch_fill(double* p, double v, size_t n, hipStream_t st);
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 // out = x + a y  (n complex128)
 hipError_t launch_axpy(double* out, const double* x, double a, const double* y, size_t n,
                        hipStream_t st);

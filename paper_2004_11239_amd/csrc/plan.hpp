@@ -55,6 +55,7 @@ struct Workspace {
   double* q2 = nullptr;
   double* fs = nullptr;
   void* Vc = nullptr;        // weights of one chunk's pairs (plans with weights on the fly)
+  int* flag = nullptr;       // NaN/Inf flag of the input check (a0)
   DeviceArena arena;
 };
 
@@ -137,18 +138,35 @@ bzq_status derive_plan(const Plan& base, double gamma, bzq_plan* out, hipStream_
 // Device bytes of the gamma-independent tables of a plan geometry.
 size_t plan_shared_bytes_estimate(int N, int N_rho, int M, int precision);
 double power_kernel_constant(double s);
+// (c, s, r) of b = c t^{-1-s} (1-t)^{-r} for a bzq_kernel selector (general:
+// whether BZQ_KERNEL_GENERAL with the explicit c, s, r is accepted)
+bzq_status kernel_params(int kernel, double s, double c, double r, bool general, double* bc, double* bs,
+                         double* br);
+// bytes of one complex128 N^3 spectral array
+inline size_t state_bytes(int N) { return (size_t)N * N * N * 16; }
 
 // Enqueue Q = Q(f) for `cells` cells sharing plan p, using workspace w.
-// With upd, the finalize launch also applies that time-step update.
+// With upd, the finalize launch also applies that time-step update.  With
+// check, the input is checked for NaN/Inf in the ingest launch and the host
+// waits for the result (a stream synchronisation) before enqueuing anything
+// else: BZQ_ENONFINITE then leaves every output untouched.
 bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrPack& Q, int cells,
-                             hipStream_t st, const FinUpdate& upd = FinUpdate{});
-// Enqueue n_steps Heun steps in place for `cells` cells.
+                             hipStream_t st, const FinUpdate& upd = FinUpdate{}, bool check = false);
+// Enqueue n_steps Heun steps in place for `cells` cells (check: of the input
+// state, as for enqueue_collision).
 bzq_status enqueue_step(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
-                        hipStream_t st);
+                        hipStream_t st, bool check = false);
 
 // Enqueue n_steps classical Runge-Kutta (RK4) steps in place for `cells` cells.
 bzq_status enqueue_step_rk4(Plan& p, Workspace& w, const PtrPack& f, int cells, double dt, int n_steps,
-                            hipStream_t st);
+                            hipStream_t st, bool check = false);
+
+// True when the byte ranges [a, a + n) and [b, b + n) overlap.
+inline bool ranges_overlap(const void* a, const void* b, size_t n) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + n && y < x + n;
+}
 
 inline PtrPack single(const double* p) {
   PtrPack pk{};

@@ -123,7 +123,7 @@ std::string table_key(const bzq_request& d) {
   return k.str();
 }
 
-size_t state_bytes(int N) { return (size_t)N * N * N * 16; }
+
 
 void release_plan(bzq_server_s* s, PlanEntry* pe) {
   for (Workspace* w : pe->all_ws) delete w;

@@ -168,6 +168,76 @@ def test_nonfinite_detection(bzq):
     assert not plan.check_finite(_dev(f))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N", [8, 64])
+def test_nonfinite_input_rejected_outputs_untouched(bzq, prec, N):
+    """The a0 stage reduces a NaN/Inf flag over the entries it reads:
+    bzq_collision, bzq_step and bzq_step_rk4 return BZQ_ENONFINITE and leave
+    Q_hat (or the state) untouched; a NaN on a Nyquist plane is not read; the
+    plan stays usable.  Both ingest kernels are covered (the plain copy at
+    N = 64 FP64, the copy fused with the first transform otherwise)."""
+    import torch
+    L = 8.0
+    plan = bzq.Plan(N, L, 4.0, 0.0, 0.5, 2, 6, precision=prec)
+    good = _input(N, L, 0)
+    bad = good.copy()
+    bad[1, 2, N - 3] = complex(np.inf, 0.0)
+    sentinel = torch.full((N, N, N), 7.0 + 3.0j, dtype=torch.complex128, device="cuda")
+    with pytest.raises(bzq.BzqError) as e:
+        plan.collision(_dev(bad), sentinel)
+    assert e.value.code == 5
+    assert bool(torch.all(sentinel == 7.0 + 3.0j))
+    bad[1, 2, N - 3] = np.nan
+    fd = _dev(bad)
+    for method in ("heun", "rk4"):
+        with pytest.raises(bzq.BzqError) as e:
+            plan.step(fd, 0.01, 2, method=method)
+        assert e.value.code == 5
+        assert np.array_equal(_host(fd), bad, equal_nan=True)
+    # a NaN at the Nyquist index is never read
+    nyq = good.copy()
+    nyq[N // 2, 0, 1] = np.nan
+    q_nyq = _host(plan.collision(_dev(nyq)))
+    q_good = _host(plan.collision(_dev(good)))
+    assert np.array_equal(q_nyq, q_good)
+
+
+def test_overlapping_buffers_rejected(bzq):
+    """f_hat and Q_hat whose byte ranges overlap (not only equal pointers) are
+    refused before any work."""
+    import ctypes
+    import torch
+    N = 8
+    plan = bzq.Plan(N, 8.0, 4.0, 0.0, 0.5, 2, 6, precision="fp64")
+    buf = torch.zeros(2 * N ** 3, dtype=torch.complex128, device="cuda")
+    f = buf[:N ** 3].view(N, N, N)
+    lib = bzq.lib()
+    base = buf.data_ptr()
+    for off in (0, 16, (N ** 3 - 1) * 16):
+        code = lib.bzq_collision(plan.handle, ctypes.c_void_p(base), ctypes.c_void_p(base + off), None)
+        assert code == 1, off
+    # adjacent, not overlapping
+    code = lib.bzq_collision(plan.handle, ctypes.c_void_p(base), ctypes.c_void_p(base + N ** 3 * 16), None)
+    assert code == 0
+    torch.cuda.synchronize()
+    del f
+
+
+def test_cutoff_selector_equals_general_b5(bzq):
+    """BZQ_KERNEL_CUTOFF_CONST builds the plan of b = 1/(4 pi) (b5 of Section 5.3),
+    bitwise the general plan with c = 1/(4 pi), s = -1, r = 0; the selected
+    power kernel equals the general plan with c_s = (1-s)(2-s)/(24 pi)."""
+    N, L, R = 8, 8.0, 4.0
+    f = _dev(_input(N, L, 3))
+    a = bzq.Plan(N, L, R, 0.0, 0.9, 8, 14, precision="fp64", kernel="cutoff")
+    b = bzq.Plan(N, L, R, 0.0, 0.0, 8, 14, precision="fp64", kernel=(1.0 / (4.0 * math.pi), -1.0, 0.0))
+    assert np.array_equal(_host(a.collision(f)), _host(b.collision(f)))
+    s = 0.25
+    c = bzq.Plan(N, L, R, 0.0, s, 8, 14, precision="fp64")
+    d = bzq.Plan(N, L, R, 0.0, 0.0, 8, 14, precision="fp64", kernel=((1 - s) * (2 - s) / (24 * math.pi), s, 0.0))
+    assert _rel(_host(c.collision(f)), _host(d.collision(f))) < 1e-15
+
+
 def test_derived_gamma_plan_shares_tables_bitwise(bzq):
     """A plan derived for another gamma (bzq_plan_derive_gamma) holds no tables
     of its own and gives bitwise the result of a plan built from scratch; it

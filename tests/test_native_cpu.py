@@ -47,7 +47,7 @@ def test_argument_validation_without_device(lib):
     f = lib.bzq_plan_create
     f.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_double, ctypes.c_double,
                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                  ctypes.c_void_p]
+                  ctypes.c_int, ctypes.c_void_p]
     f.restype = ctypes.c_int
     lib.bzq_last_error.restype = ctypes.c_char_p
     lib.bzq_status_string.restype = ctypes.c_char_p
@@ -66,14 +66,27 @@ def test_argument_validation_without_device(lib):
         ((12, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),     # valid but no FFT schedule
         ((128, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),
     ]
+    # kernel selector (BZQ_KERNEL_POWER = 0, BZQ_KERNEL_CUTOFF_CONST = 1)
+    cases = [(a + (0,), c) for a, c in cases] + [
+        ((12, 8.0, 4.0, 0.0, 2.0, 16, 38, 0, 1), 4),  # cutoff kernel: s ignored, then no FFT schedule
+        ((12, 8.0, 4.0, 0.0, 2.0, 16, 38, 0, 0), 1),  # the same s for the power kernel: invalid
+        ((16, 8.0, 4.0, 0.0, 0.5, 16, 38, 0, 2), 1),  # the general selector is not taken here
+        ((16, 8.0, 4.0, 0.0, 0.5, 16, 38, 0, 7), 1),  # unknown selector
+    ]
     for args, code in cases:
         h.value = 1234
         assert f(ctypes.byref(h), *args, None) == code, args
         assert h.value is None
         assert len(lib.bzq_last_error()) > 0
     assert lib.bzq_status_string(1) == b"invalid argument"
-    lib.bzq_request_device_bytes.restype = ctypes.c_size_t
-    assert lib.bzq_request_device_bytes(32) == 2 * 32 ** 3 * 16
+    rb = lib.bzq_request_device_bytes
+    rb.restype = ctypes.c_size_t
+    rb.argtypes = [ctypes.c_int, ctypes.c_int]
+    # state (f_hat, Q_hat) plus a workspace (whose chunk of pairs is capped in
+    # bytes, so both precisions come out near the cap), growing with N
+    assert rb(32, 1) > 2 * 32 ** 3 * 16 and rb(32, 0) > 2 * 32 ** 3 * 16
+    assert rb(64, 1) > rb(32, 1)
+    assert rb(7, 0) == 0 and rb(32, 5) == 0
     lib.bzq_collision.argtypes = [ctypes.c_void_p] * 4
     assert lib.bzq_collision(None, None, None, None) == 1
     lib.bzq_plan_destroy.argtypes = [ctypes.c_void_p]
@@ -146,16 +159,21 @@ def test_otf_plan_limits_without_device(lib):
     even terms of the weight series."""
     f = lib.bzq_plan_create_otf
     d, i = ctypes.c_double, ctypes.c_int
-    f.argtypes = [ctypes.POINTER(ctypes.c_void_p), i, d, d, d, d, d, d, i, i, i, ctypes.c_void_p]
+    f.argtypes = [ctypes.POINTER(ctypes.c_void_p), i, d, d, d, i, d, d, d, i, i, i, ctypes.c_void_p]
     f.restype = ctypes.c_int
-    c = (1 - 0.5) * (2 - 0.5) / (24 * 3.141592653589793)
+    c = 0.02
     h = ctypes.c_void_p()
+    # selector 0: the power kernel of order b_s (b_c, b_r ignored); 2: (b_c, b_s, b_r)
     cases = [
-        ((15, 8.0, 4.0, 0.0, c, 0.5, 0.0, 16, 38, 0), 1),      # odd N
-        ((16, 8.0, 4.0, 0.0, c, 1.0, 0.0, 16, 38, 0), 1),      # s = 1
-        ((16, 8.0, 4.0, 0.0, c, 0.5, 0.0, 16, 37, 0), 1),      # no Lebedev rule of size 37
-        ((12, 8.0, 4.0, 0.0, c, 0.5, 0.0, 16, 38, 0), 4),      # no FFT schedule
-        ((64, 2.0, 40.0, 0.0, c, 0.5, 0.0, 8, 38, 0), 4),      # a|k| ~ 840: series too long
+        ((15, 8.0, 4.0, 0.0, 0, 0.0, 0.5, 0.0, 16, 38, 0), 1),     # odd N
+        ((16, 8.0, 4.0, 0.0, 0, 0.0, 1.0, 0.0, 16, 38, 0), 1),     # s = 1
+        ((16, 8.0, 4.0, 0.0, 2, -1.0, 0.5, 0.0, 16, 38, 0), 1),    # general kernel with c <= 0
+        ((16, 8.0, 4.0, 0.0, 5, c, 0.5, 0.0, 16, 38, 0), 1),       # unknown selector
+        ((16, 8.0, 4.0, 0.0, 0, 0.0, 0.5, 0.0, 16, 37, 0), 1),     # no Lebedev rule of size 37
+        ((12, 8.0, 4.0, 0.0, 0, -5.0, 0.5, 9.0, 16, 38, 0), 4),    # b_c, b_r ignored; no FFT schedule
+        ((12, 8.0, 4.0, 0.0, 1, 0.0, 7.0, 0.0, 16, 38, 0), 4),     # cutoff: all ignored
+        ((12, 8.0, 4.0, 0.0, 2, c, 0.5, 0.0, 16, 38, 0), 4),       # no FFT schedule
+        ((64, 2.0, 40.0, 0.0, 0, 0.0, 0.5, 0.0, 8, 38, 0), 4),     # a|k| ~ 840: series too long
     ]
     for args, code in cases:
         h.value = 1234
