@@ -176,6 +176,21 @@ size_t bzq_plan_shared_bytes(bzq_plan p);
  * of the evaluation is enqueued asynchronously. */
 bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* stream);
 
+/* bzq_collision for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same operator and arguments; it calls no allocating routine of any kind.
+ * Its pipeline scratch (compact spectrum, f on the padded grid, the two
+ * intermediates of a chunk of pairs and the partial sums) is a static device
+ * array of 128 MiB that each GPU running the library holds until the process
+ * ends; the chunk of pairs is shrunk to fit it (results then differ from
+ * bzq_collision in summation order only).  Plans whose scratch cannot fit even
+ * with one pair-two per chunk give BZQ_EUNSUPPORTED; every plan of the sizes
+ * above fits.  All calls on one GPU share that array: calls that overlap in
+ * time on one GPU (other streams, other threads) race and must not be issued.
+ * No NaN/Inf check (nothing synchronises): a non-finite f_hat gives a
+ * non-finite Q_hat.  Asynchronous on `stream`. */
+bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat, void* stream);
+
 /* Advance the Galerkin system d f_k/dt = Q_k (Section 2, the ODE system that
  * follows eq. weak) by n_steps steps of Heun's method (explicit trapezoid:
  * f* = f + dt Q(f), f <- f + dt/2 (Q(f) + Q(f*))), in place on the device

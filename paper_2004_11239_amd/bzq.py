@@ -56,6 +56,7 @@ def _load():
         "bzq_plan_derive_gamma": ([ctypes.POINTER(vp), vp, d, vp], i),
         "bzq_plan_shared_bytes": ([vp], sz),
         "bzq_collision": ([vp, vp, vp, vp], i),
+        "bzq_collision_noalloc": ([vp, vp, vp, vp], i),
         "bzq_step": ([vp, vp, d, i, vp], i),
         "bzq_step_rk4": ([vp, vp, d, i, vp], i),
         "bzq_plan_set_schedule": ([vp, vp], i),
@@ -231,6 +232,14 @@ class Plan:
             out = torch.empty_like(f_hat)
         qp = _spectral(out, self.N, "out")
         _check(_lib.bzq_collision(self.handle, fp, qp, _stream(stream)))
+        return out
+
+    def collision_noalloc(self, f_hat: torch.Tensor, out: torch.Tensor, stream=None):
+        """Q(f, f) with the library's static device scratch (bzq_collision_noalloc):
+        no allocation in the call; `out` must be given."""
+        fp = _spectral(f_hat, self.N, "f_hat")
+        qp = _spectral(out, self.N, "out")
+        _check(_lib.bzq_collision_noalloc(self.handle, fp, qp, _stream(stream)))
         return out
 
     def step(self, f_hat: torch.Tensor, dt: float, n_steps: int = 1, stream=None, method: str = "heun"):

@@ -83,6 +83,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   if (cells < 1 || cells > kMaxCells) return fail(BZQ_EINVAL, "cells per launch must lie in [1, 64]");
   w.plan = &p;
   w.cells = cells;
+  w.G = w.S = w.Gw = 0;   // the plan's geometry, whatever its schedule
   w.cs.fc = (size_t)p.n1 * p.nn;
   w.cs.fg = (size_t)p.P * p.P * p.P;
   w.cs.a = (size_t)p.G * p.P * p.nn;
@@ -150,17 +151,18 @@ constexpr int kSTargets[3] = {512, 1024, 2048};
 // resident workgroups and S down to what fits it, so that no launch ends with
 // a nearly empty round (64^3 FP32: 1008 workgroups on 512 slots instead of
 // 1071).  S never exceeds its value without the rounding.
-int zfwd_splits(const Plan& p, int zv, int s_target) {
+int zfwd_splits_for(const Plan& p, int G, int zv, int s_target) {
   const bool pipe = zv == 2 && (p.P == 48 || p.P == 72 || p.P == 96);
   const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
   const int tq = pipe ? 32 : reg_zfwd ? (p.fp32 ? 32 : 16) : 8;
   const int pt_group = pipe ? 1 : reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
-  const int groups = (p.G + pt_group - 1) / pt_group;
+  const int groups = (G + pt_group - 1) / pt_group;
   const int tiles = (p.nh + tq - 1) / tq;
   const int slots = p.cus * (zv >= 1 && zv <= 2 ? p.zfwd_bpc[zv] : 0);
   if (slots > 0 && slots <= s_target) return std::max(1, std::min(groups, s_target / slots * slots / tiles));
   return std::max(1, std::min(groups, (s_target + tiles - 1) / tiles));
 }
+int zfwd_splits(const Plan& p, int zv, int s_target) { return zfwd_splits_for(p, p.G, zv, s_target); }
 
 // Chunking of the pair loop: the two pipeline intermediates stay below 1 GiB
 // per cell (one chunk per evaluation up to N = 32); the splits S of the last
@@ -463,9 +465,10 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
 
 enum Stage { ST_PREP = 0, ST_ZINV = 1, ST_PLANE = 2, ST_ZFWD = 3, ST_FINAL = 4, ST_COUNT = 5 };
 
-// Record an event before (begin=true) or after a launch of a timed stage.
-hipError_t mark(Plan& p, int stage, bool begin, hipStream_t st) {
-  if (!(p.timing >> stage & 1)) return hipSuccess;
+// Record an event before (begin=true) or after a launch of a timed stage
+// (never for a workspace marked untimed, whose calls create nothing).
+hipError_t mark(Plan& p, const Workspace& w, int stage, bool begin, hipStream_t st) {
+  if (w.untimed || !(p.timing >> stage & 1)) return hipSuccess;
   if (p.ev_used == p.ev_pool.size()) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
@@ -478,9 +481,9 @@ hipError_t mark(Plan& p, int stage, bool begin, hipStream_t st) {
 
 #define TIMED(stage, expr)                                \
   do {                                                    \
-    BZQ_HIP_TRY(mark(p, (stage), true, st));              \
+    BZQ_HIP_TRY(mark(p, w, (stage), true, st));           \
     BZQ_HIP_TRY(expr);                                    \
-    BZQ_HIP_TRY(mark(p, (stage), false, st));             \
+    BZQ_HIP_TRY(mark(p, w, (stage), false, st));          \
   } while (0)
 
 }  // namespace
@@ -514,28 +517,31 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
   TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st));
   // the first last-stage launch writes the S partial accumulators of every
   // cell, later ones add to them
-  for (int c0 = 0; c0 < p.npt; c0 += p.G) {
-    const int n = std::min(p.G, p.npt - c0);
+  // the chunk geometry: the plan's, or the workspace's own for scratch of
+  // another size
+  const int G = w.G ? w.G : p.G, S = w.S ? w.S : p.S, Gw = w.Gw ? w.Gw : p.Gw;
+  for (int c0 = 0; c0 < p.npt; c0 += G) {
+    const int n = std::min(G, p.npt - c0);
     TIMED(ST_ZINV, launch_zinv(w.fc, p.ph, w.A, p.tw_pad, g, 2 * c0, n, ZINV_PAIRS, p.fp32, cs, st, p.var[0]));
     TIMED(ST_PLANE, launch_plane(w.A, w.B, w.fgrid, nullptr, p.tw_pad, g, n, PLANE_PRODUCT, p.fp32, cs, st,
                                  p.var[1]));
     if (p.otf) {
       // weights of Gw pair-twos at a time, then the last stage over those pair-twos
-      for (int w0 = 0; w0 < n; w0 += p.Gw) {
-        const int m = std::min(p.Gw, n - w0);
+      for (int w0 = 0; w0 < n; w0 += Gw) {
+        const int m = std::min(Gw, n - w0);
         const int pair0 = 2 * (c0 + w0);
         const void* Bw = (const char*)w.B + (size_t)w0 * p.P * 2 * p.nhp * 2 * p.esz;
         TIMED(ST_ZFWD, launch_wgen(w.Vc, p.coef, p.pdv, p.terms, p.mt, p.N, p.Mh, p.nreal, pair0, 2 * m,
                                    p.ncoef, p.fp32, st));
-        TIMED(ST_ZFWD, launch_zfwd(Bw, w.Vc, p.ph, p.cp, w.Qpart, p.tw_pad, g, pair0, m, p.S, p.fp32, cs, st,
+        TIMED(ST_ZFWD, launch_zfwd(Bw, w.Vc, p.ph, p.cp, w.Qpart, p.tw_pad, g, pair0, m, S, p.fp32, cs, st,
                                    p.var[2], pair0, c0 == 0 && w0 == 0));
       }
     } else {
-      TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, p.S, p.fp32, cs, st,
+      TIMED(ST_ZFWD, launch_zfwd(w.B, p.V, p.ph, p.cp, w.Qpart, p.tw_pad, g, 2 * c0, n, S, p.fp32, cs, st,
                                  p.var[2], 0, c0 == 0));
     }
   }
-  TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, p.S, st, upd));
+  TIMED(ST_FINAL, launch_finalize(w.Qpart, Q, cs.qp, cells, p.N, S, st, upd));
   return BZQ_OK;
 }
 
@@ -743,6 +749,56 @@ bzq_status bzq_collision(bzq_plan p, const double* f_hat, double* Q_hat, void* s
   if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
   if (ranges_overlap(f_hat, Q_hat, state_bytes(p->N))) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
   return enqueue_collision(*p, p->ws, single(f_hat), single(Q_hat), 1, (hipStream_t)stream, FinUpdate{}, true);
+}
+
+bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat, void* stream) {
+  if (!p || !f_hat || !Q_hat) return fail(BZQ_EINVAL, "NULL argument");
+  if (ranges_overlap(f_hat, Q_hat, state_bytes(p->N))) return fail(BZQ_EINVAL, "f_hat and Q_hat must not overlap");
+  // the largest chunk of pair-twos (at most the plan's) whose scratch fits
+  const size_t esz = p->esz;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_fc = al((size_t)p->n1 * p->nn * 2 * esz), b_fg = al((size_t)p->P * p->P * p->P * esz);
+  const int zv = effective_variant(*p, 2);
+  int G = p->G, S = 0, Gw = 0;
+  size_t b_a = 0, b_b = 0, b_q = 0, b_w = 0;
+  auto need = [&](int g) {
+    S = zfwd_splits_for(*p, g, zv, p->s_target);
+    Gw = p->otf ? std::min(p->Gw, g) : 0;
+    b_a = al((size_t)g * p->P * p->nn * 2 * esz);
+    b_b = al((size_t)g * p->P * 2 * p->nhp * 2 * esz);
+    b_q = al((size_t)S * p->nh * p->n1 * 16);
+    b_w = al((size_t)2 * Gw * p->nh * p->n1 * esz);
+    return b_fc + b_fg + b_a + b_b + b_q + b_w;
+  };
+  while (G > 1 && need(G) > kNoAllocScratchBytes) --G;
+  if (need(G) > kNoAllocScratchBytes)
+    return fail(BZQ_EUNSUPPORTED, "plan too large for the no-allocation scratch (" +
+                                      std::to_string(need(G)) + " bytes needed, " +
+                                      std::to_string(kNoAllocScratchBytes) + " available)");
+  void* base = nullptr;
+  BZQ_HIP_TRY(noalloc_scratch(&base));
+  // a workspace that owns nothing: its buffers are slices of the scratch
+  Workspace w;
+  w.plan = p;
+  w.cells = 1;
+  w.G = G;
+  w.S = S;
+  w.Gw = Gw;
+  w.untimed = true;
+  char* at = (char*)base;
+  w.fc = at; at += b_fc;
+  w.fgrid = at; at += b_fg;
+  w.A = at; at += b_a;
+  w.B = at; at += b_b;
+  w.Qpart = (double*)at; at += b_q;
+  w.Vc = p->otf ? at : nullptr;
+  w.cs.fc = (size_t)p->n1 * p->nn;
+  w.cs.fg = (size_t)p->P * p->P * p->P;
+  w.cs.a = (size_t)G * p->P * p->nn;
+  w.cs.b = (size_t)G * p->P * 2 * p->nhp;
+  w.cs.qp = (size_t)S * p->nh * p->n1;
+  w.cs.cells = 1;
+  return enqueue_collision(*p, w, single(f_hat), single(Q_hat), 1, (hipStream_t)stream);
 }
 
 bzq_status bzq_step(bzq_plan p, double* f_hat, double dt, int n_steps, void* stream) {

@@ -25,6 +25,7 @@
 // zero padding folds away) used wherever a pencil fits the register file, and
 // an LDS Stockham one used otherwise (FP64 at P >= 72) and by the last stage.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "fft.hpp"
@@ -2133,6 +2134,35 @@ int zfwd_blocks_t(int variant) {
 #define BZQ_PAD_P(X) X(12) X(24) X(36) X(48) X(72) X(96)
 
 }  // namespace
+
+// ------------------------------------------------ no-allocation scratch
+// The scratch of bzq_collision_noalloc: a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends.  In host code
+// the array's name is only a host-side stand-in; the device address comes
+// from hipGetSymbolAddress, once per device with that device current, and is
+// the only handle host code passes on (kernel arguments, copies).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptrs[kMaxDevices] = {};
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = p;
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
+}
+
 
 hipError_t launch_ingest(const PtrPack& f, void* fc, size_t fc_stride, int cells, int N, bool fp32,
                          hipStream_t st, int* flag) {

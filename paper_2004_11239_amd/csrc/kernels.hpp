@@ -127,6 +127,11 @@ hipError_t launch_heun_cells(const PtrPack& f, const PtrPack& q1, const PtrPack&
 hipError_t launch_table(void* V, const double* pairdat, const double* gj, int nj, int N,
                         int npairs, bool fp32, hipStream_t st);
 
+// Size of the static device scratch of bzq_collision_noalloc, and its device
+// address on the current device (looked up once per device, then cached).
+constexpr size_t kNoAllocScratchBytes = 128ull << 20;
+hipError_t noalloc_scratch(void** out);
+
 hipError_t launch_fill(double* p, double v, size_t n, hipStream_t st);
 hipError_t launch_fill_int(int* p, int v, int n, hipStream_t st);
 // out = x + a y  (n complex128)

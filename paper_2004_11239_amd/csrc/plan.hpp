@@ -45,6 +45,11 @@ struct Plan;
 struct Workspace {
   const Plan* plan = nullptr;
   int cells = 0;
+  // chunk geometry of the pipeline on this scratch: pair-twos per chunk, the
+  // last stage's splits, pair-twos per block of generated weights; 0 = the
+  // plan's G, S, Gw (workspaces made by workspace_init)
+  int G = 0, S = 0, Gw = 0;
+  bool untimed = false;      // never record timing events (no allocation at all)
   CellStrides cs{};
   void* fc = nullptr;        // cells x (N-1)^3 complex, compute precision
   void* fgrid = nullptr;     // cells x P^3 real
@@ -128,6 +133,9 @@ int effective_variant(const Plan& p, int stage);
 std::map<std::string, int> tune_cache_read();
 void tune_cache_write(const std::map<std::string, int>& m);
 void set_chunking(Plan& p);
+// Splits of the last stage for a chunk of G pair-twos under kernel variant zv
+// and workgroup target s_target.
+int zfwd_splits_for(const Plan& p, int G, int zv, int s_target);
 size_t plan_footprint(int N, int N_rho, int M, int precision);
 bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, double bc, double bs,
                        double br, int nj, int N_rho, int M, int precision, void* stream, bool otf = false,

@@ -41,6 +41,13 @@ def test_header_symbols_exported(lib):
     assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
+    # every internal symbol resolves inside the library (a lazily bound one
+    # would only fail at its first call)
+    nm = shutil.which("nm")
+    if nm:
+        r = subprocess.run([nm, "-D", "--undefined-only", LIB], capture_output=True, text=True)
+        assert r.returncode == 0
+        assert "bzq" not in r.stdout, r.stdout
 
 
 def test_argument_validation_without_device(lib):
