@@ -63,27 +63,44 @@ def test_bessel_route_matches_sphere_route(name):
         assert abs(got - ref) <= 2e-12 * max(1.0, abs(ref)), (name, kv, a, got, ref)
 
 
-def test_against_mpmath_reference():
-    mp = pytest.importorskip("mpmath")
-    mp.mp.dps = 30
-    k = power_kernel(0.5)
+def _psi_mp(x, y, kern, npts=33):
+    """eq. FF with the azimuth done (J0) in t = sin^2(th/2), by 30-digit mpmath
+    quadrature: 4 pi c \int_0^1 t^{-s} (1-t)^{-r} [e^{2ixt} J0(Y) - 1] / t dt,
+    Y = 2 y sqrt(t(1-t)).  The bracket over t is formed without cancellation:
+    (J0(Y) - 1)/t = -y^2 (1-t) 1F2(1; 2, 2; -y^2 t(1-t)) and expm1(2ixt)/t; the
+    two end panels take t = a u^4 and 1 - t = (1-b) u^4, which makes the
+    algebraic end singularities smooth in u."""
+    import mpmath as mp
+    with mp.workdps(30):
+        x, y = mp.mpf(x), mp.mpf(y)
+        s, r = mp.mpf(kern.s), mp.mpf(kern.r)
 
-    def psi_mp(x, y):
-        x = mp.mpf(x)
-        y = mp.mpf(y)
+        def f(t, omt):
+            j0m1_t = -(y * y) * omt * mp.hyp1f2(1, 2, 2, -(y * y) * t * omt)
+            j0 = 1 + t * j0m1_t
+            return t ** (-s) * omt ** (-r) * (mp.expm1(2j * x * t) / t * j0 + j0m1_t)
 
-        def f(t):
-            Y = 2 * y * mp.sqrt(t * (1 - t))
-            return t ** (-k.s) * (mp.expj(2 * x * t) * mp.besselj(0, Y) - 1) / t
+        pts = mp.linspace(0, 1, npts)
+        a, b = pts[1], pts[-2]
+        tot = (mp.quad(lambda u: f(a * u ** 4, 1 - a * u ** 4) * 4 * a * u ** 3, [0, 1])
+               + mp.quad(lambda u: f(1 - (1 - b) * u ** 4, (1 - b) * u ** 4) * 4 * (1 - b) * u ** 3, [0, 1])
+               + mp.quad(lambda t: f(t, 1 - t), pts[1:-1]))
+        return complex(4 * mp.pi * mp.mpf(kern.c) * tot)
 
-        pts = mp.linspace(0, 1, 9)
-        re = mp.quad(lambda t: mp.re(f(t)), pts)
-        im = mp.quad(lambda t: mp.im(f(t)), pts)
-        return complex(4 * mp.pi * k.c * mp.mpc(re, im))
 
-    for x, y in [(0.3, 0.1), (5.0, 2.0), (9.5, 9.5)]:
-        ref = psi_mp(x, y)
-        assert abs(psi(x, y, k) - ref) <= 1e-14 * abs(ref) + 1e-16, (x, y)
+@pytest.mark.parametrize("name", ["s025", "s050", "s075", "b6", "b7"])
+def test_against_mpmath_reference(name):
+    """Psi of the 64-node Gauss-Jacobi rule against a 30-digit quadrature, over
+    the whole range of (x, y) = (a k.sigma, a |k x sigma|) the workloads reach:
+    a |k| <= pi R/(2L) sqrt(3) (N/2 - 1) = 42.2 at N = 64, L = 10, R = 5."""
+    pytest.importorskip("mpmath")
+    kern = {"s025": power_kernel(0.25), "s050": power_kernel(0.5), "s075": power_kernel(0.75),
+            "b6": PAPER_KERNELS["b6"], "b7": PAPER_KERNELS["b7"]}[name]
+    for x, y in [(0.3, 0.1), (5.0, 2.0), (9.5, 9.5), (42.2, 0.0), (0.0, 42.2), (-29.8, 29.8),
+                 (17.0, 38.0), (-40.0, 11.0)]:
+        ref = _psi_mp(x, y, kern)
+        got = complex(psi(x, y, kern))
+        assert abs(got - ref) <= 1e-14 * abs(ref) + 1e-16, (name, x, y, got, ref)
 
 
 @pytest.mark.parametrize("name", ["b5", "b6", "b7", "b8"])
