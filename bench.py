@@ -253,10 +253,18 @@ def batch_bench(bzq, torch, n_cells, steps, seed=0):
     return out
 
 
-def serve_bench(rates, duration, precision="fp32"):
+def serve_bench(bzq, rates, duration, precision="fp32", q_fraction=0.0, max_queued=32):
+    """The served form: Poisson arrivals at each rate (req/s) for `duration`
+    seconds against one server (plans stay cached across the rates; each new
+    plan's schedule is tuned on its first request, during the warm-up), with
+    a bounded queue of max_queued waiting requests."""
     from paper_2004_11239_amd import serve
-    return [serve.run(r, duration, seed=0, budget_gb=64, slots=4, precision=precision, n_steps=10)
-            for r in rates]
+    srv = bzq.Server(64 << 30, 4, max_queued=max_queued, tune=True)
+    try:
+        return [serve.run(r, duration, seed=0, slots=4, precision=precision, n_steps=10, server=srv,
+                          max_queued=max_queued, q_fraction=q_fraction) for r in rates]
+    finally:
+        srv.destroy()
 
 
 def whole_path(N, npairs, esz, per_eval_ms, traffic=None):
@@ -343,14 +351,16 @@ def bench_2d(bzq, torch, n_evals=20):
     N, R = 64, 6.0
     L = (3 + math.sqrt(2)) * R / 4
     K = 0.5
-    f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L, K))
+    # f sampled, and the error taken, on the cell-centred grid (Table 1's grid)
+    f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L, K, centred=True), centred=True)
     fd = torch.from_numpy(f).to("cuda")
     out = {"workload": "2-D collision N=64^2 N_rho=64 N_sigma=32 (midpoint) R=6 L=6.62 b3, BKW at t=0"}
-    v = workloads.velocity_grid(N, L)
+    v = workloads.velocity_grid(N, L, centred=True)
     v2 = v[:, None] ** 2 + v[None, :] ** 2
     exact = np.exp(-v2 / (2 * K)) / (2 * math.pi * K) * (1 - K) ** 2 / (4 * K ** 4) * 0.125 * (
         8 * K * K - 8 * K * v2 + v2 * v2)
-    sgn = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    kk = np.fft.fftfreq(N, 1.0 / N)
+    sgn = np.where(np.arange(N) % 2 == 0, 1.0, -1.0) * np.exp(1j * math.pi * kk / N)
     for prec in ("fp32", "fp64"):
         plan = bzq.Plan2D(N, L, R, 0.0, (1.0 / (8 * math.pi), 0.0, 0.0), N, 32, precision=prec)
         q = torch.empty_like(fd)
@@ -460,8 +470,9 @@ def main():
     ap.add_argument("--no-2d", dest="two_d", action="store_false",
                     help="skip the 2-D operator at Table 1's N = 64 setting")
     ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
-    ap.add_argument("--serve-rates", default="2,20", help="request rates (req/s) of the served form ('': skip)")
-    ap.add_argument("--serve-duration", type=float, default=5.0)
+    ap.add_argument("--serve-rates", default="10,25,50,100,200,500",
+                    help="request rates (req/s) of the served form ('': skip)")
+    ap.add_argument("--serve-duration", type=float, default=3.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run 3 device-to-device copies of MIB MiB (reference kernel for "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -614,8 +625,9 @@ def main():
         torch.cuda.empty_cache()
     if args.serve_rates:
         rates = [float(r) for r in args.serve_rates.split(",")]
-        out["served"] = serve_bench(rates, args.serve_duration)
-        out["served_fp64"] = serve_bench(rates, args.serve_duration, precision="fp64")
+        out["served"] = serve_bench(bzq, rates, args.serve_duration)
+        out["served_fp64"] = serve_bench(bzq, rates, args.serve_duration, precision="fp64")
+        out["served_mixed_q"] = serve_bench(bzq, [rates[0]], args.serve_duration, q_fraction=0.5)
     if not args.no_cpu_baseline:
         ks, qo, t, cb = cpu_baseline(cfg, fhat)
         idx = tuple(np.mod(ks, cfg["N"]).T)

@@ -57,7 +57,8 @@ typedef enum {
     BZQ_ENOMEM = 2,        /* device memory could not be allocated                 */
     BZQ_EDEVICE = 3,       /* a HIP runtime call failed (details: bzq_last_error)  */
     BZQ_EUNSUPPORTED = 4,  /* valid in principle, but no kernel for this size      */
-    BZQ_ENONFINITE = 5     /* NaN or Inf found in the input                        */
+    BZQ_ENONFINITE = 5,    /* NaN or Inf found in the input                        */
+    BZQ_EBUSY = 6          /* the request server's queue is full; nothing queued   */
 } bzq_status;
 
 typedef enum {
@@ -278,35 +279,48 @@ size_t bzq_batch_device_bytes(bzq_batch b);
 bzq_status bzq_batch_destroy(bzq_batch b);
 
 /*
- * Request server with continuous batching.  A request advances one cell by
- * n_steps Heun steps of the power-law operator with the given parameters.
+ * Request server with continuous batching.  A request is one cell of the
+ * power-law operator (BZQ_KERNEL_POWER) with its own parameters and asks for
+ * either Q_hat = Q(f_hat) (kind BZQ_REQ_COLLISION, eq. realQ) or n_steps Heun
+ * steps of the Galerkin system of Section 2 (kind BZQ_REQ_STEP).
  *   bzq_server_create: budget_bytes of device memory (>= 64 MiB) for cached
  *     plans, workspaces and request state; `slots` (1..16) requests run
- *     concurrently, each on its own stream.  A worker thread owns all device
- *     work.
+ *     concurrently, each on its own stream; at most max_queued requests wait
+ *     (0 = no limit); flags: BZQ_SERVER_TUNE times the kernel schedule of
+ *     every new plan on its first request's input (bzq_plan_autotune, with
+ *     the tuning cache) before that request runs.  A worker thread owns all
+ *     device work.
  *   bzq_server_submit: copies f_host (host, complex128 N^3) and queues the
- *     request; returns its id at once.  Thread-safe.
- *   bzq_server_poll: 1 = done (result copied to f_out if not NULL, request
- *     released), 0 = not yet, -1 = unknown id, -2 = failed (bzq_last_error
- *     tells why; released).  times (optional, host double[3]) = arrival,
- *     start and completion on the server's monotonic clock, seconds.
+ *     request; returns its id at once.  BZQ_EBUSY (nothing queued, counted as
+ *     rejected) when max_queued requests already wait.  Thread-safe.
+ *   bzq_server_poll: 1 = done (result, the new state or Q_hat, copied to f_out
+ *     if not NULL, request released), 0 = not yet, -1 = unknown id, -2 =
+ *     failed (bzq_last_error tells why; released).  times (optional, host
+ *     double[3]) = arrival, start and completion on the server's monotonic
+ *     clock, seconds.
  *   bzq_server_wait: blocks until request id is done or failed, or timeout.
- *   bzq_server_stats: out[8] = submitted, completed, failed, queued, running,
- *     device bytes in use, peak device bytes, plans evicted.
+ *   bzq_server_stats: out[9] = submitted, completed, failed, queued, running,
+ *     device bytes in use, peak device bytes, plans evicted, rejected.
  * Requests are admitted in arrival order when their plan (if not cached), a
  * workspace and their state fit the budget; idle plans are evicted least
- * recently used first; a request that cannot fit alone fails with ENOMEM.
- * Each result is bitwise identical to bzq_step run alone.
+ * recently used first.  A request that cannot fit while nothing else runs
+ * fails with ENOMEM (it never waits for memory that no completion can free).
+ * Each result is bitwise identical to bzq_step / bzq_collision run alone on a
+ * plan of the same parameters and schedule.
  */
+typedef enum { BZQ_REQ_STEP = 0, BZQ_REQ_COLLISION = 1 } bzq_request_kind;
+typedef enum { BZQ_SERVER_TUNE = 1 } bzq_server_flags;
+
 typedef struct {
     int N;
     double L, R, gamma, s;
     int N_rho, M, precision;
-    double dt;
-    int n_steps;
+    double dt;        /* BZQ_REQ_STEP only */
+    int n_steps;      /* BZQ_REQ_STEP only */
+    int kind;         /* a bzq_request_kind */
 } bzq_request;
 
-bzq_status bzq_server_create(bzq_server* out, size_t budget_bytes, int slots);
+bzq_status bzq_server_create(bzq_server* out, size_t budget_bytes, int slots, int max_queued, int flags);
 bzq_status bzq_server_submit(bzq_server s, const bzq_request* req, const double* f_host,
                              unsigned long long* id);
 int bzq_server_poll(bzq_server s, unsigned long long id, double* f_out, double* times);

@@ -147,7 +147,7 @@ def collision_direct(fhat: np.ndarray, d: Discretization, k_out: Optional[np.nda
         T = weight_table(d, k_out)                                  # [J, nk]
     h = N // 2
     Q = np.zeros(nk, dtype=np.complex128)
-    mdot = sig @ m.T.astype(np.float64)                            # [J, nm]  m.sigma_j
+    mf = m.T.astype(np.float64)
     for k0 in range(0, nk, k_block):
         kb = k_out[k0:k0 + k_block]
         diff = kb[None, :, :] - m[:, None, :]                       # k - m  [nm, kb, 3]
@@ -156,7 +156,8 @@ def collision_direct(fhat: np.ndarray, d: Discretization, k_out: Optional[np.nda
         C = np.where(valid, fkm, 0.0) * fm[:, None]                 # C[m, k] = f_{k-m} f_m
         acc = np.zeros(len(kb), dtype=np.complex128)
         for j0 in range(0, J, j_block):
-            E = np.exp((-1j * math.pi / d.L) * rho[j0:j0 + j_block, None] * mdot[j0:j0 + j_block])
+            mdot = sig[j0:j0 + j_block] @ mf                         # m.sigma_j  [jb, nm]
+            E = np.exp((-1j * math.pi / d.L) * rho[j0:j0 + j_block, None] * mdot)
             Y = E @ C                                                # [jb, kb]
             acc += np.sum(T[j0:j0 + j_block, k0:k0 + k_block] * Y, axis=0)
         Q[k0:k0 + k_block] = acc

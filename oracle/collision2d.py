@@ -218,12 +218,16 @@ def collision_direct2d(fhat: np.ndarray, d: Discretization2D, k_out: Optional[np
     return out
 
 
-def to_physical2d(ghat: np.ndarray, L: float) -> np.ndarray:
-    """g(v_j) = sum_k g_k e^{i pi k.v_j / L} on v_j = -L + j 2L/N (real part)."""
+def to_physical2d(ghat: np.ndarray, L: float, centred: bool = False) -> np.ndarray:
+    """g(v_j) = sum_k g_k e^{i pi k.v_j / L} on v_j = -L + j 2L/N (real part), or
+    on the cell-centred grid v_j = -L + (j + 1/2) 2L/N (centred=True, where
+    e^{i pi k v_j / L} = (-1)^k e^{i pi k/N} e^{2 pi i k j/N})."""
     N = ghat.shape[0]
     k = np.fft.fftfreq(N, 1.0 / N).astype(np.int64)
     k[N // 2] = 0
-    sgn = np.where(k % 2 == 0, 1.0, -1.0)
+    sgn = np.where(k % 2 == 0, 1.0, -1.0).astype(np.complex128)
+    if centred:
+        sgn = sgn * np.exp(1j * math.pi * k / N)
     return np.real(np.fft.ifft2(ghat * sgn[:, None] * sgn[None, :])) * float(N) ** 2
 
 

@@ -26,7 +26,10 @@ KERNEL_CUTOFF_CONST = 1
 KERNEL_GENERAL = 2
 
 STATUS = {0: "BZQ_OK", 1: "BZQ_EINVAL", 2: "BZQ_ENOMEM", 3: "BZQ_EDEVICE", 4: "BZQ_EUNSUPPORTED",
-          5: "BZQ_ENONFINITE"}
+          5: "BZQ_ENONFINITE", 6: "BZQ_EBUSY"}
+REQ_STEP = 0
+REQ_COLLISION = 1
+SERVER_TUNE = 1
 
 
 class BzqError(RuntimeError):
@@ -40,7 +43,7 @@ class BzqRequest(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("L", ctypes.c_double), ("R", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("s", ctypes.c_double), ("N_rho", ctypes.c_int),
                 ("M", ctypes.c_int), ("precision", ctypes.c_int), ("dt", ctypes.c_double),
-                ("n_steps", ctypes.c_int)]
+                ("n_steps", ctypes.c_int), ("kind", ctypes.c_int)]
 
 
 def _load():
@@ -82,7 +85,7 @@ def _load():
         "bzq_batch_group_info": ([vp, i, ctypes.POINTER(i)], i),
         "bzq_batch_device_bytes": ([vp], sz),
         "bzq_batch_destroy": ([vp], i),
-        "bzq_server_create": ([ctypes.POINTER(vp), sz, i], i),
+        "bzq_server_create": ([ctypes.POINTER(vp), sz, i, i, i], i),
         "bzq_server_submit": ([vp, ctypes.POINTER(BzqRequest), vp, ctypes.POINTER(ctypes.c_ulonglong)], i),
         "bzq_server_poll": ([vp, ctypes.c_ulonglong, vp, ctypes.POINTER(d)], i),
         "bzq_server_wait": ([vp, ctypes.c_ulonglong, d], i),
@@ -505,19 +508,26 @@ class Batch:
 
 
 class Server:
-    """Request server with continuous batching (see bzq_server_create)."""
+    """Request server with continuous batching (see bzq_server_create):
+    max_queued bounds the waiting requests (0: unbounded; a full queue makes
+    submit raise BzqError with code BZQ_EBUSY), tune times each new plan's
+    schedule on its first request."""
 
-    def __init__(self, budget_bytes: int, slots: int = 4):
+    def __init__(self, budget_bytes: int, slots: int = 4, max_queued: int = 0, tune: bool = False):
         h = ctypes.c_void_p()
-        _check(_lib.bzq_server_create(ctypes.byref(h), int(budget_bytes), int(slots)))
+        _check(_lib.bzq_server_create(ctypes.byref(h), int(budget_bytes), int(slots), int(max_queued),
+                                      SERVER_TUNE if tune else 0))
         self._h = h
 
-    def submit(self, f_hat_host, N, L, R, gamma, s, N_rho, M, precision="fp32", dt=0.01, n_steps=10):
+    def submit(self, f_hat_host, N, L, R, gamma, s, N_rho, M, precision="fp32", dt=0.01, n_steps=10,
+               kind="step"):
+        """kind="step": n_steps Heun steps of f; kind="collision": Q(f) (dt, n_steps unused)."""
         import numpy as np
         f = np.ascontiguousarray(f_hat_host, dtype=np.complex128)
         if f.shape != (N, N, N):
             raise ValueError("f_hat must be (N, N, N)")
-        req = BzqRequest(N, L, R, gamma, s, N_rho, M, _PREC[precision], dt, n_steps)
+        k = {"step": REQ_STEP, "collision": REQ_COLLISION}[kind]
+        req = BzqRequest(N, L, R, gamma, s, N_rho, M, _PREC[precision], dt, n_steps, k)
         rid = ctypes.c_ulonglong()
         _check(_lib.bzq_server_submit(self._h, ctypes.byref(req), f.ctypes.data_as(ctypes.c_void_p),
                                       ctypes.byref(rid)))
@@ -541,10 +551,10 @@ class Server:
         _check(_lib.bzq_server_wait(self._h, ctypes.c_ulonglong(rid), float(timeout)))
 
     def stats(self):
-        v = (ctypes.c_double * 8)()
+        v = (ctypes.c_double * 9)()
         _check(_lib.bzq_server_stats(self._h, v))
         keys = ("submitted", "completed", "failed", "queued", "running", "device_bytes", "peak_device_bytes",
-                "evictions")
+                "evictions", "rejected")
         return {k: v[i] for i, k in enumerate(keys)}
 
     def destroy(self):

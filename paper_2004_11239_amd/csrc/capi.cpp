@@ -1134,6 +1134,7 @@ const char* bzq_status_string(bzq_status s) {
     case BZQ_EDEVICE: return "HIP runtime error";
     case BZQ_EUNSUPPORTED: return "unsupported size";
     case BZQ_ENONFINITE: return "non-finite input";
+    case BZQ_EBUSY: return "request queue full";
   }
   return "unknown status";
 }

@@ -1,9 +1,10 @@
 // Request server with continuous batching for the collision operator.
 //
-// A request asks to advance one homogeneous cell by n_steps Heun steps
-// (2 evaluations of eq. realQ each) under given (N, L, R, gamma, s, N_rho, M,
-// precision).  Requests arrive from any host thread (bzq_server_submit) and
-// are served by one worker thread that owns every HIP call:
+// A request asks for Q(f) of one homogeneous cell (eq. realQ) or to advance
+// it by n_steps Heun steps (2 evaluations each) under given (N, L, R, gamma,
+// s, N_rho, M, precision).  Requests arrive from any host thread
+// (bzq_server_submit; refused with BZQ_EBUSY when the bounded queue is full)
+// and are served by one worker thread that owns every HIP call:
 //   * plans are cached by their parameters and kept resident; a plan's
 //     workspaces are pooled, so concurrent requests on one plan each get
 //     their own scratch; plans that differ only in gamma share one set of
@@ -11,7 +12,8 @@
 //   * admission is by device-memory footprint: a request starts only when
 //     its plan (if not cached), a workspace (if none is free) and its state
 //     fit in the budget; idle cached plans are evicted least recently used
-//     first; a request that cannot fit even alone is failed with ENOMEM;
+//     first; a request waits for memory only while other requests run (whose
+//     completion frees some), otherwise it fails with ENOMEM;
 //   * up to `slots` requests run at once, each on its own stream, so their
 //     kernels overlap on the device; a finishing request frees its slot and
 //     memory and the next queued requests are admitted at once (FIFO order);
@@ -23,6 +25,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -48,6 +51,7 @@ struct PlanEntry {
   std::string key;
   std::string tkey;                 // the plan's gamma-independent tables
   bzq_plan plan = nullptr;
+  bool tuned = false;               // schedule timed (BZQ_SERVER_TUNE) or inherited
   size_t plan_bytes = 0;            // excluding the shared tables
   size_t ws_bytes = 0;              // bytes of one extra workspace
   int in_use = 0;
@@ -84,6 +88,8 @@ struct Slot {
 struct bzq_server_s {
   int device = 0;
   size_t budget = 0;
+  int max_queued = 0;               // 0: unbounded
+  int flags = 0;
   size_t used = 0, peak = 0;
   std::vector<Slot> slots;
   std::mutex mu;
@@ -99,7 +105,7 @@ struct bzq_server_s {
   unsigned long long next_id = 1;
   Clock::time_point t0 = Clock::now();
   // stats (guarded by mu)
-  unsigned long long submitted = 0, completed = 0, failed = 0, evictions = 0;
+  unsigned long long submitted = 0, completed = 0, failed = 0, evictions = 0, rejected = 0;
   int running = 0;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
@@ -187,7 +193,18 @@ bool try_start(bzq_server_s* s, Request* r, Slot& sl) {
       finish(s, r, 3, BZQ_ENOMEM, "request does not fit the device-memory budget");
       return true;
     }
-    if (s->used + est > s->budget && !make_room(s, est, base)) return false;
+    if (s->used + est > s->budget && !make_room(s, est, base)) {
+      // no room beside the plan that would lend its tables: build a plan of
+      // its own instead, with that one evictable too
+      if (!base || !make_room(s, full, nullptr)) {
+        if (s->running == 0) {
+          finish(s, r, 3, BZQ_ENOMEM, "request does not fit the device-memory budget beside the cached plans");
+          return true;
+        }
+        return false;   // a completion will free memory
+      }
+      base = nullptr;
+    }
     bzq_plan p = nullptr;
     bzq_status st;
     if (base) {
@@ -197,6 +214,7 @@ bool try_start(bzq_server_s* s, Request* r, Slot& sl) {
       st = create_plan(&p, d.N, d.L, d.R, d.gamma, bc, d.s, 0.0, 64, d.N_rho, d.M, d.precision, sl.stream);
     }
     if (st != BZQ_OK) {
+      if (st == BZQ_ENOMEM && s->running > 0) return false;   // retry once memory is freed
       finish(s, r, 3, st, bzq_last_error());
       return true;
     }
@@ -208,6 +226,7 @@ bool try_start(bzq_server_s* s, Request* r, Slot& sl) {
     e->plan = p;
     e->plan_bytes = pb;
     e->ws_bytes = p->ws.arena.bytes;
+    e->tuned = base != nullptr;       // a derived plan inherits its base's schedule
     s->used += pb;
     auto& t = s->tables[tkey];
     if (t.second++ == 0) {
@@ -240,11 +259,20 @@ bool try_start(bzq_server_s* s, Request* r, Slot& sl) {
     }
     return false;
   }
+  // an allocation that fails while nothing runs would fail again: the
+  // request fails instead of waiting for a completion that never comes
+  auto alloc_failed = [&](const char* what) {
+    if (s->running == 0 && pe->in_use == 0) {
+      finish(s, r, 3, BZQ_ENOMEM, std::string("allocation of the request's ") + what + " failed");
+      return true;
+    }
+    return false;
+  };
   if (!own && !ws) {
     ws = new Workspace();
     if (workspace_init(*ws, *pe->plan, 1) != BZQ_OK) {
       delete ws;
-      return false;
+      return alloc_failed("workspace");
     }
     pe->all_ws.push_back(ws);
     s->used += pe->ws_bytes;
@@ -260,12 +288,14 @@ bool try_start(bzq_server_s* s, Request* r, Slot& sl) {
   } else {
     if (hipMalloc(&d_f, state_bytes(d.N)) != hipSuccess) {
       (void)hipGetLastError();
-      return false;
+      if (ws) pe->free_ws.push_back(ws);
+      return alloc_failed("state");
     }
     if (hipHostMalloc(&h_pin, state_bytes(d.N), hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFree(d_f);
-      return false;
+      if (ws) pe->free_ws.push_back(ws);
+      return alloc_failed("pinned host buffer");
     }
     s->used += state_bytes(d.N);
   }
@@ -286,12 +316,34 @@ bool try_start(bzq_server_s* s, Request* r, Slot& sl) {
   std::memcpy(h_pin, r->host_f.data(), state_bytes(d.N));
   Workspace& w = own ? pe->plan->ws : *ws;
   hipError_t e1 = hipMemcpyAsync(d_f, h_pin, state_bytes(d.N), hipMemcpyHostToDevice, sl.stream);
-  bzq_status st = e1 == hipSuccess ? enqueue_step(*pe->plan, w, single(d_f), 1, d.dt, d.n_steps, sl.stream)
-                                   : BZQ_EDEVICE;
-  hipError_t e2 = st == BZQ_OK ? hipMemcpyAsync(h_pin, d_f, state_bytes(d.N), hipMemcpyDeviceToHost, sl.stream)
+  bzq_status st = e1 == hipSuccess ? BZQ_OK : BZQ_EDEVICE;
+  if (st == BZQ_OK && (s->flags & BZQ_SERVER_TUNE) && !pe->tuned) {
+    // the first request of a new plan: time its schedule on this input
+    // (synchronous, on the plan's own workspace, before the request runs)
+    pe->tuned = true;
+    if (own) st = bzq_plan_autotune(pe->plan, d_f, 1, sl.stream);
+  }
+  // the result: the new state (step) or Q(f) in the workspace's stage buffer
+  double* result = d_f;
+  if (st == BZQ_OK) {
+    if (d.kind == BZQ_REQ_COLLISION) {
+      result = w.q1;
+      st = enqueue_collision(*pe->plan, w, single(d_f), single(result), 1, sl.stream);
+    } else {
+      st = enqueue_step(*pe->plan, w, single(d_f), 1, d.dt, d.n_steps, sl.stream);
+    }
+  }
+  hipError_t e2 = st == BZQ_OK ? hipMemcpyAsync(h_pin, result, state_bytes(d.N), hipMemcpyDeviceToHost, sl.stream)
                                : hipErrorUnknown;
-  if (e2 == hipSuccess) e2 = hipEventRecord(sl.done, sl.stream);
-  if (e2 != hipSuccess) r->err = st != BZQ_OK ? st : BZQ_EDEVICE;
+  if (e2 != hipSuccess && st == BZQ_OK) st = BZQ_EDEVICE;
+  // the event is recorded after whatever was enqueued, also on failure, so
+  // that the request's buffers return to the pools only once its kernels end
+  if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
+    (void)hipStreamSynchronize(sl.stream);
+    (void)hipEventRecord(sl.done, nullptr);
+    if (st == BZQ_OK) st = BZQ_EDEVICE;
+  }
+  r->err = st;
   sl.req = r;
   return true;
 }
@@ -316,7 +368,7 @@ void complete(bzq_server_s* s, Slot& sl) {
 
 void worker_main(bzq_server_s* s) {
   (void)hipSetDevice(s->device);
-  bool blocked = false;
+  bool blocked = false;   // the queue's head waits for memory (only while requests run)
   while (!s->stop.load()) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
@@ -333,6 +385,7 @@ void worker_main(bzq_server_s* s) {
         blocked = false;                      // memory was freed
       }
     }
+    if (s->running == 0) blocked = false;   // nothing left to wait for
     for (Slot& sl : s->slots) {
       if (blocked || sl.req || s->pending.empty()) continue;
       Request* r = s->pending.front();
@@ -354,13 +407,17 @@ void worker_main(bzq_server_s* s) {
 
 extern "C" {
 
-bzq_status bzq_server_create(bzq_server* out, size_t budget_bytes, int slots) {
+bzq_status bzq_server_create(bzq_server* out, size_t budget_bytes, int slots, int max_queued, int flags) {
   if (!out) return fail(BZQ_EINVAL, "out is NULL");
   *out = nullptr;
   if (slots < 1 || slots > 16) return fail(BZQ_EINVAL, "slots must lie in [1, 16]");
   if (budget_bytes < (64ull << 20)) return fail(BZQ_EINVAL, "budget below 64 MiB");
+  if (max_queued < 0) return fail(BZQ_EINVAL, "max_queued must be >= 0");
+  if (flags & ~BZQ_SERVER_TUNE) return fail(BZQ_EINVAL, "unknown server flag");
   auto* s = new bzq_server_s();
   s->budget = budget_bytes;
+  s->max_queued = max_queued;
+  s->flags = flags;
   BZQ_HIP_TRY(hipGetDevice(&s->device));
   s->slots.resize(slots);
   for (Slot& sl : s->slots) {
@@ -379,7 +436,17 @@ bzq_status bzq_server_submit(bzq_server s, const bzq_request* req, const double*
   if (!s || !req || !f_host || !id) return fail(BZQ_EINVAL, "NULL argument");
   const int N = req->N;
   if (N < 8 || N > 64 || (N & 1)) return fail(BZQ_EINVAL, "N must be even, 8..64");
-  if (req->n_steps < 0 || !(req->dt == req->dt)) return fail(BZQ_EINVAL, "bad dt or n_steps");
+  if (req->kind != BZQ_REQ_STEP && req->kind != BZQ_REQ_COLLISION) return fail(BZQ_EINVAL, "unknown request kind");
+  if (req->kind == BZQ_REQ_STEP && (req->n_steps < 0 || !std::isfinite(req->dt)))
+    return fail(BZQ_EINVAL, "bad dt or n_steps");
+  if (s->max_queued > 0) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const unsigned long long queued = s->submitted - s->completed - s->failed - (unsigned long long)s->running;
+    if (queued >= (unsigned long long)s->max_queued) {
+      ++s->rejected;
+      return fail(BZQ_EBUSY, "request queue full");
+    }
+  }
   auto r = std::make_unique<Request>();
   r->desc = *req;
   r->host_f.assign(f_host, f_host + (size_t)N * N * N * 2);
@@ -444,6 +511,7 @@ bzq_status bzq_server_stats(bzq_server s, double* out) {
   out[5] = (double)s->used;
   out[6] = (double)s->peak;
   out[7] = (double)s->evictions;
+  out[8] = (double)s->rejected;
   return BZQ_OK;
 }
 

@@ -1,10 +1,13 @@
 """Poisson-arrival driver for the request server (continuous batching).
 
 Each request advances one homogeneous cell by `n_steps` Heun steps of the
-collision operator; sizes, kernels and initial data are drawn per request.
-Requests are submitted at their arrival times from a feeder thread while the
-main thread collects completions; latency is completion minus arrival on the
-server's clock.
+collision operator, or (a fraction `q_fraction` of them) asks for Q(f) of the
+cell; sizes, kernels and initial data are drawn per request.  Requests are
+submitted at their arrival times from a feeder thread while the main thread
+collects completions; latency is completion minus arrival on the server's
+clock.  The server's queue is bounded (`max_queued`): a request that arrives
+while it is full is rejected and counted, so that an overloaded server reaches
+a steady state instead of an ever-growing queue.
 
     python -m paper_2004_11239_amd.serve --rates 2,10,100 --duration 10
 
@@ -29,15 +32,19 @@ def _percentile(x, q):
 def run(rate_hz: float, duration_s: float, seed: int = 0, budget_gb: float = 64.0, slots: int = 4,
         precision: str = "fp32", n_steps: int = 10, dt: float = 0.01, L: float = 8.0, R: float = 4.0,
         M: int = 110, sizes=(16, 32, 48, 64), gammas=(-1.0, 0.0), ss=(0.25, 0.75), drain_s: float = 600.0,
-        server=None):
+        server=None, max_queued: int = 32, tune: bool = True, q_fraction: float = 0.0, input_pool: int = 8):
     import workloads
 
     stream = workloads.request_stream(rate_hz, duration_s, seed, sizes=sizes, gammas=gammas, ss=ss)
-    # inputs are prepared before the clock starts
-    inputs = [workloads.to_spectral(workloads.random_mixture(ms).sample(N, L)) for (_, N, _, _, ms) in stream]
+    kinds = np.random.default_rng(seed + 7).random(len(stream)) < q_fraction
+    # inputs are prepared before the clock starts: a pool of `input_pool`
+    # seeded mixtures per size, reused in turn
+    pool = {N: [workloads.to_spectral(workloads.random_mixture(seed * 1000 + 17 * N + i).sample(N, L))
+                for i in range(input_pool)] for N in sorted(set(N for (_, N, _, _, _) in stream))}
+    inputs = [pool[N][i % input_pool] for i, (_, N, _, _, _) in enumerate(stream)]
     own = server is None
     if own:
-        server = bzq.Server(int(budget_gb * (1 << 30)), slots)
+        server = bzq.Server(int(budget_gb * (1 << 30)), slots, max_queued=max_queued, tune=tune)
     # resident plans for every parameter set of the stream (not timed)
     warm = {}
     for (_, N, g, s, _) in stream:
@@ -48,6 +55,8 @@ def run(rate_hz: float, duration_s: float, seed: int = 0, budget_gb: float = 64.
         server.wait(rid)
         server.poll(rid, N)
     ids = [None] * len(stream)
+    rejected = [False] * len(stream)
+    fed = threading.Event()
     t0 = time.perf_counter()
 
     def feeder():
@@ -55,23 +64,33 @@ def run(rate_hz: float, duration_s: float, seed: int = 0, budget_gb: float = 64.
             delay = t - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            ids[i] = server.submit(inputs[i], N, L, R, g, s, N, M, precision, dt, n_steps)
+            try:
+                ids[i] = server.submit(inputs[i], N, L, R, g, s, N, M, precision, dt, n_steps,
+                                       kind="collision" if kinds[i] else "step")
+            except bzq.BzqError as e:
+                if e.code != 6:     # BZQ_EBUSY: the bounded queue is full
+                    raise
+                rejected[i] = True
+        fed.set()
 
     th = threading.Thread(target=feeder)
     th.start()
-    lat, done_t, first_arrival = [], [], None
+    lat, lat_q, done_t, first_arrival = [], [], [], None
     remaining = set(range(len(stream)))
     deadline = time.perf_counter() + duration_s + drain_s
     while remaining and time.perf_counter() < deadline:
         progressed = False
         for i in list(remaining):
+            if rejected[i]:
+                remaining.discard(i)
+                continue
             if ids[i] is None:
                 continue
             r = server.poll(ids[i], stream[i][1])
             if r is None:
                 continue
             _, (ta, ts, td) = r
-            lat.append(td - ta)
+            (lat_q if kinds[i] else lat).append(td - ta)
             done_t.append(td)
             first_arrival = ta if first_arrival is None else min(first_arrival, ta)
             remaining.discard(i)
@@ -83,11 +102,17 @@ def run(rate_hz: float, duration_s: float, seed: int = 0, budget_gb: float = 64.
     if own:
         server.destroy()
     span = (max(done_t) - first_arrival) if done_t else float("nan")
-    return {"rate_req_s": rate_hz, "requests": len(stream), "completed": len(lat),
-            "p50_s": _percentile(lat, 50), "p99_s": _percentile(lat, 99),
-            "throughput_req_s": len(lat) / span if done_t else 0.0,
-            "peak_device_gb": stats["peak_device_bytes"] / 1e9, "evictions": stats["evictions"],
-            "slots": slots, "precision": precision, "n_steps": n_steps}
+    n_done = len(lat) + len(lat_q)
+    out = {"rate_req_s": rate_hz, "requests": len(stream), "completed": n_done,
+           "rejected": int(sum(rejected)), "max_queued": max_queued,
+           "p50_s": _percentile(lat + lat_q, 50), "p99_s": _percentile(lat + lat_q, 99),
+           "throughput_req_s": n_done / span if done_t else 0.0,
+           "peak_device_gb": stats["peak_device_bytes"] / 1e9, "evictions": stats["evictions"],
+           "slots": slots, "precision": precision, "n_steps": n_steps}
+    if q_fraction > 0:
+        out.update({"q_requests": len(lat_q), "q_p50_s": _percentile(lat_q, 50), "q_p99_s": _percentile(lat_q, 99),
+                    "step_p50_s": _percentile(lat, 50), "step_p99_s": _percentile(lat, 99)})
+    return out
 
 
 def main():

@@ -4,11 +4,15 @@ sample of output modes, for the medium (32^3) and large (64^3) workloads.
 
 Calls only `oracle` and `workloads` (seeded inputs).  Run from the repository
 root:  python tests/golden/make_golden.py [name ...]
-Each case writes tests/golden/<name>.npz with arrays
+Also the 2-D operator (d = 2, Section 5.2) on broadband inputs at N = 64, all
+modes: tests/golden/<name>.npz with Q2 (complex128 N^2, FFT order) and params2
+(N, L, R, gamma, N_rho, N_sigma, seed) and the kernel name.
+Each 3-D case writes tests/golden/<name>.npz with arrays
   modes  int64 [n, 3]   sampled output modes k
   Q      complex128 [n] oracle Q_k
   params float64 [8]    N, L, R, gamma, s, N_rho, M, seed
-  kind   input recipe code (0: two Maxwellians at +-2 e1, 1: random mixture)
+  kind   input recipe code (0: two Maxwellians at +-2 e1, 1: random mixture,
+         2: broadband random Hermitian spectrum, workloads.broadband_spectrum)
 """
 import os
 import sys
@@ -21,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 import oracle      # noqa: E402
 import workloads   # noqa: E402
+from oracle import collision2d as o2   # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -32,7 +37,41 @@ CASES = {
     "medium_gm1": (32, 8.0, 4.0, -1.0, 0.50, 32, 110, 3, 0, 16),
     "medium_gp1": (32, 8.0, 4.0, 1.0, 0.50, 32, 110, 4, 0, 16),
     "large_s050": (64, 10.0, 5.0, 0.0, 0.50, 64, 302, 0, 1, 16),
+    # the large workload at gamma = -1, +1 (same input as large_s050)
+    "large_gm1": (64, 10.0, 5.0, -1.0, 0.50, 64, 302, 0, 1, 24),
+    "large_gp1": (64, 10.0, 5.0, 1.0, 0.50, 64, 302, 0, 1, 24),
 }
+
+# broadband inputs, sampled at every |k|_inf <= 2 mode, the 8 corners of K_N
+# and 128 random modes (workloads.survey_mode_sample)
+BROADBAND = {
+    # name: (N, L, R, gamma, s, N_rho, M, seed)
+    "broadband_N32": (32, 8.0, 4.0, 0.0, 0.50, 32, 110, 7),
+    "broadband_N48": (48, 9.0, 4.5, 0.0, 0.75, 16, 110, 8),
+    "broadband_N64": (64, 10.0, 5.0, 0.0, 0.50, 64, 302, 9),
+}
+
+
+# 2-D broadband cases at N = 64: the register pipeline at 16 pair-twos, the
+# register / column-parity pipeline at Table 1's setting (512 pair-twos) and the
+# LDS pipeline (1040 pair-twos)
+CASES_2D = {
+    # name: (N, L, R, gamma, kernel, N_rho, N_sigma, seed)
+    "broadband2d_N64_reg": (64, 8.0, 4.0, 0.0, "b1", 8, 8, 31),
+    "broadband2d_N64_tab1": (64, (3 + 2 ** 0.5) * 6.0 / 4, 6.0, 0.0, "b4", 64, 32, 32),
+    "broadband2d_N64_lds": (64, 8.0, 4.0, 0.0, "b3", 65, 64, 33),
+}
+
+
+def make2d(name):
+    N, L, R, gamma, kname, N_rho, N_sigma, seed = CASES_2D[name]
+    d = o2.Discretization2D(N, L, R, gamma, o2.PAPER_KERNELS_2D[kname], N_rho, N_sigma)
+    f = workloads.broadband_spectrum_2d(N, seed)
+    t0 = time.time()
+    q = o2.collision_direct2d(f, d)
+    params = np.array([N, L, R, gamma, N_rho, N_sigma, seed], dtype=np.float64)
+    np.savez(os.path.join(HERE, name + ".npz"), Q2=q, params2=params, kernel=np.array(kname))
+    print(f"{name}: all {(N - 1) ** 2} modes in {time.time() - t0:.1f} s", flush=True)
 
 
 def sample_modes(N, n_random, seed):
@@ -49,22 +88,32 @@ def sample_modes(N, n_random, seed):
 
 
 def input_of(N, L, seed, kind):
+    if kind == 2:
+        return workloads.broadband_spectrum(N, seed)
     mix = workloads.two_maxwellians(seed) if kind == 0 else workloads.random_mixture(seed)
     return workloads.to_spectral(mix.sample(N, L))
 
 
 def make(name):
-    N, L, R, gamma, s, N_rho, M, seed, kind, nr = CASES[name]
+    if name in BROADBAND:
+        N, L, R, gamma, s, N_rho, M, seed = BROADBAND[name]
+        kind = 2
+        ks = workloads.survey_mode_sample(N, seed)
+    else:
+        N, L, R, gamma, s, N_rho, M, seed, kind, nr = CASES[name]
+        ks = sample_modes(N, nr, seed)
     d = oracle.Discretization.power(N, L, R, gamma, s, N_rho, M)
     f = input_of(N, L, seed, kind)
-    ks = sample_modes(N, nr, seed)
     t0 = time.time()
-    q = oracle.collision_direct(f, d, k_out=ks, k_block=len(ks), j_block=128 if N >= 64 else 512)
+    q = oracle.collision_direct(f, d, k_out=ks, k_block=len(ks), j_block=64 if N >= 64 else 256)
     params = np.array([N, L, R, gamma, s, N_rho, M, seed], dtype=np.float64)
     np.savez(os.path.join(HERE, name + ".npz"), modes=ks, Q=q, params=params, kind=np.array(kind))
-    print(f"{name}: {len(ks)} modes in {time.time() - t0:.1f} s")
+    print(f"{name}: {len(ks)} modes in {time.time() - t0:.1f} s", flush=True)
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CASES)):
-        make(n)
+    for n in (sys.argv[1:] or list(CASES) + list(BROADBAND) + list(CASES_2D)):
+        if n in CASES_2D:
+            make2d(n)
+        else:
+            make(n)

@@ -176,36 +176,32 @@ def _table1():
 
 
 def test_table1_bkw(bzq):
-    """Table 1: L_inf error of Q on the grid against eq. QQ (d = 2) at t = 0,
-    N_rho = N, N_sigma = 32, R = 6, L = (3 + sqrt 2) R / 4.  At N = 64 the
-    truncation of the profile is far below the quadrature error, the error is
-    that of the radial and circle rules, and it reproduces the printed row to
-    within 10% (measured: 0.5-4%).  At N <= 32 the error is the truncation of the
-    narrow profile (K = 1/2) to N - 1 modes per axis; the paper does not state
-    its mode set and prints smaller values there, so those rows are pinned to
-    their order of magnitude (N = 8) and to the ordering in N only."""
+    """Table 1: L_inf error of Q against eq. QQ (d = 2) at t = 0, N_rho = N,
+    N_sigma = 32, R = 6, L = (3 + sqrt 2) R / 4, with f sampled and the error
+    taken on the cell-centred grid v_j = -L + (j + 1/2) h.  Measured against the
+    printed values: N = 8, 16 all kernels 0.87-1.05; N = 32 b1, b2 0.95-0.97
+    (truncation-dominated), b3, b4 1.55-1.59 (where the weight's quadrature
+    enters, computed exactly here and by the paper's eps-split there);
+    N = 64 0.99-1.00."""
     ref = _table1()
     K = o2.bkw2d_K(0.0)
     errs = {}
     for N in (8, 16, 32, 64):
-        f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L_BKW, K))
-        v = workloads.velocity_grid(N, L_BKW)
+        f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L_BKW, K, centred=True), centred=True)
+        v = workloads.velocity_grid(N, L_BKW, centred=True)
         exact = o2.bkw2d_Q(v[:, None] ** 2 + v[None, :] ** 2, K)
         fd = _dev(f)
         for name in KERNELS:
             plan = bzq.Plan2D(N, L_BKW, R_BKW, 0.0, _kernel(name), N, 32, precision="fp64")
             Q = _host(plan.collision(fd))
             plan.destroy()
-            errs[N, name] = float(np.max(np.abs(o2.to_physical2d(Q, L_BKW) - exact)))
+            errs[N, name] = float(np.max(np.abs(o2.to_physical2d(Q, L_BKW, centred=True) - exact)))
             print(f"Table 1 N={N} {name}: {errs[N, name]:.4e}  paper {ref[N][name]:.4e}", flush=True)
-    for N in (8, 16, 32, 64):
-        e = [errs[N, n] for n in KERNELS]
-        assert max(e) < 3 * min(e), N
     for name in KERNELS:
-        assert errs[64, name] < errs[32, name] < errs[16, name] < errs[8, name]
-        assert ref[8][name] / 20 < errs[8, name] < 20 * ref[8][name]
-        # N = 64: the quadrature error alone, which reproduces the printed row
-        assert abs(errs[64, name] / ref[64][name] - 1) < 0.1, (name, errs[64, name], ref[64][name])
+        r = {N: errs[N, name] / ref[N][name] for N in (8, 16, 32, 64)}
+        assert 0.8 < r[8] < 1.2 and 0.8 < r[16] < 1.2, (name, r)
+        assert (0.85 < r[32] < 1.15) if name in ("b1", "b2") else (0.5 < r[32] < 2.0), (name, r)
+        assert abs(r[64] - 1) < 0.03, (name, r)
 
 
 # ------------------------------------------------------------------ time steps
@@ -260,3 +256,30 @@ def test_bkw_evolution_rk4(bzq):
         print(f"2-D BKW, RK4 to t = 2, N = {N}: L_inf error {errs[N]:.3e}, change of f {moved:.3e}", flush=True)
         assert errs[N] < 1e-3 * moved
     assert errs[64] < 1e-7
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["broadband2d_N64_reg", "broadband2d_N64_tab1", "broadband2d_N64_lds"])
+def test_n64_broadband_every_mode(bzq, name, prec):
+    """Broadband input (flat random Hermitian spectrum, workloads.broadband_spectrum_2d)
+    at N = 64, every mode against the stored oracle values: each mode within
+    tol * max|Q| and the relative L2 within tol.  Smooth inputs leave the modes
+    near |k| = N/2 - 1 at ~1e-17 of the peak, so only such an input exercises
+    the pruning of the kept modes and the recombination of the two column
+    parities at the edges (the FP64 column-parity kernel at 512 pair-twos, the
+    register kernel at 16, the LDS pipeline at 1040)."""
+    data = np.load(os.path.join(HERE, "golden", name + ".npz"), allow_pickle=False)
+    N, L, R, gamma, N_rho, N_sigma, seed = data["params2"]
+    N, N_rho, N_sigma, seed = int(N), int(N_rho), int(N_sigma), int(seed)
+    kern = o2.PAPER_KERNELS_2D[str(data["kernel"])]
+    f = workloads.broadband_spectrum_2d(N, seed)
+    print(f"case {name} prec={prec}", flush=True)
+    plan = bzq.Plan2D(N, L, R, gamma, (kern.c, kern.s, kern.r), N_rho, N_sigma, precision=prec)
+    Q = _host(plan.collision(_dev(f)))
+    plan.destroy()
+    ref = data["Q2"]
+    err = _rel(Q, ref)
+    worst = float(np.max(np.abs(Q - ref)) / np.max(np.abs(ref)))
+    print(f"{name} {prec}: rel L2 {err:.3e}, worst mode / max|Q| {worst:.3e}", flush=True)
+    assert err < TOL[prec] and worst < TOL[prec]
+    assert Q[0, 0] == 0.0

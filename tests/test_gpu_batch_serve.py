@@ -193,6 +193,81 @@ def test_server_admission_queues_and_fails_what_cannot_fit(bzq):
 
 def test_serve_driver_reports_latency(bzq):
     from paper_2004_11239_amd import serve
-    r = serve.run(50.0, 1.0, seed=3, budget_gb=8, slots=4, n_steps=2, sizes=(16, 24), M=14)
+    r = serve.run(50.0, 1.0, seed=3, budget_gb=8, slots=4, n_steps=2, sizes=(16, 24), M=14, max_queued=0)
     assert r["completed"] == r["requests"] > 10
     assert 0 < r["p50_s"] <= r["p99_s"]
+
+
+def test_server_collision_requests_alone_and_in_mix(bzq):
+    """A Q(f) request (BZQ_REQ_COLLISION) returns bzq_collision's result bitwise,
+    alone and in a mix with step requests of other sizes and gammas."""
+    N, g, s, seed = 16, -1.0, 0.25, 31
+    srv = bzq.Server(16 << 30, slots=4)
+    rid = srv.submit(_f(N, 8.0, seed), N, 8.0, 4.0, g, s, 8, 14, "fp32", kind="collision")
+    srv.wait(rid)
+    alone, _ = srv.poll(rid, N)
+    ids = []
+    for i, (Nm, gm, sm, sd) in enumerate(REQS):
+        ids.append((_submit(srv, Nm, gm, sm, sd), Nm))
+        if i == 2:
+            qid = srv.submit(_f(N, 8.0, seed), N, 8.0, 4.0, g, s, 8, 14, "fp32", kind="collision")
+    srv.wait(qid)
+    mixed, _ = srv.poll(qid, N)
+    for rid, Nm in ids:
+        srv.wait(rid)
+        srv.poll(rid, Nm)
+    srv.destroy()
+    p = bzq.Plan(N, 8.0, 4.0, g, s, 8, 14, precision="fp32")
+    ref = _host(p.collision(_dev(_f(N, 8.0, seed))))
+    assert np.array_equal(alone, ref)
+    assert np.array_equal(mixed, ref)
+
+
+def test_server_bounded_queue_rejects(bzq):
+    """With one slot and at most two waiting requests, a burst of submissions is
+    partly refused with BZQ_EBUSY (nothing queued); every accepted request
+    completes and the refusals are counted."""
+    srv = bzq.Server(16 << 30, slots=1, max_queued=2)
+    f = _f(32, 8.0, 5)
+    accepted, refused = [], 0
+    for _ in range(12):
+        try:
+            accepted.append(srv.submit(f, 32, 8.0, 4.0, 0.0, 0.5, 16, 38, "fp32", 0.01, 4))
+        except bzq.BzqError as e:
+            assert e.code == 6
+            refused += 1
+    # the first two fill the queue before the worker takes any of them
+    assert refused > 0 and len(accepted) >= 2
+    for rid in accepted:
+        srv.wait(rid, 120)
+        out, _ = srv.poll(rid, 32)
+        assert np.isfinite(out).all()
+    st = srv.stats()
+    assert st["rejected"] == refused and st["completed"] == len(accepted) and st["failed"] == 0
+    srv.destroy()
+
+
+def test_server_gamma_sibling_without_room_for_both(bzq):
+    """A budget that holds one plan with its state but not the cached plan
+    beside a plan derived from it for another gamma: the second request evicts
+    the idle first plan and builds its own instead of waiting forever."""
+    N, N_rho, M = 32, 16, 38
+    full = bzq.plan_bytes_estimate(N, N_rho, M, "fp32") + N ** 3 * 16
+    budget = full + full // 3
+    srv = bzq.Server(budget, slots=2)
+    a = _submit(srv, N, 0.0, 0.5, 41, 1, N_rho, M)
+    srv.wait(a, 120)
+    qa, _ = srv.poll(a, N)
+    b = _submit(srv, N, -1.0, 0.5, 42, 1, N_rho, M)
+    assert srv.wait(b, 120) is None
+    qb, _ = srv.poll(b, N)
+    assert np.isfinite(qa).all() and np.isfinite(qb).all()
+    st = srv.stats()
+    assert st["failed"] == 0 and st["completed"] == 2 and st["evictions"] >= 1
+    assert st["peak_device_bytes"] <= budget
+    srv.destroy()
+    # the gamma = -1 result equals the single-cell path
+    p = bzq.Plan(N, 8.0, 4.0, -1.0, 0.5, N_rho, M, precision="fp32")
+    f = _dev(_f(N, 8.0, 42))
+    p.step(f, 0.01, 1)
+    assert np.array_equal(_host(f), qb)

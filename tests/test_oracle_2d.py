@@ -260,27 +260,54 @@ def table1():
     return rows
 
 
-def bkw_table1_error(Q, N):
-    """L_inf over the N^2 grid of Q_num(v_j) - Q_exact(v_j) at t = 0 (K = 1/2)."""
-    v = workloads.velocity_grid(N, L_BKW)
+def bkw_table1_error(Q, N, centred=True):
+    """L_inf over the N^2 grid of Q_num(v_j) - Q_exact(v_j) at t = 0 (K = 1/2);
+    the cell-centred grid v_j = -L + (j + 1/2) h by default."""
+    v = workloads.velocity_grid(N, L_BKW, centred)
     v2 = v[:, None] ** 2 + v[None, :] ** 2
-    return float(np.max(np.abs(o2.to_physical2d(Q, L_BKW) - o2.bkw2d_Q(v2, o2.bkw2d_K(0.0)))))
+    return float(np.max(np.abs(o2.to_physical2d(Q, L_BKW, centred) - o2.bkw2d_Q(v2, o2.bkw2d_K(0.0)))))
+
+
+def test_centred_grid_transforms():
+    """On the cell-centred grid v_j = -L + (j + 1/2) h: to_physical2d against the
+    literal sum of g_k e^{i pi k.v_j / L}, and the projection of the inputs
+    module as its inverse for a band-limited g."""
+    rng = np.random.default_rng(3)
+    N, L = 8, 3.0
+    ks = np.arange(-N // 2 + 1, N // 2)
+    g = np.zeros((N, N), np.complex128)
+    for k1 in ks:
+        for k2 in ks:
+            if (k1, k2) <= (0, 0):
+                continue
+            c = complex(rng.normal(), rng.normal())
+            g[k1 % N, k2 % N] = c
+            g[-k1 % N, -k2 % N] = np.conj(c)
+    g[0, 0] = 0.4
+    v = workloads.velocity_grid(N, L, centred=True)
+    assert abs(v[0] + L - L / N) < 1e-15 and abs(v.sum()) < 1e-13
+    lit = np.array([[sum(g[k1 % N, k2 % N] * np.exp(1j * math.pi * (k1 * a + k2 * b) / L)
+                         for k1 in ks for k2 in ks).real for b in v] for a in v])
+    phys = o2.to_physical2d(g, L, centred=True)
+    assert np.max(np.abs(phys - lit)) < 1e-13
+    assert np.max(np.abs(workloads.to_spectral_2d(phys, centred=True) - g)) < 1e-14
 
 
 @pytest.mark.parametrize("N", [8, 16])
 def test_table1_small_grids(N):
-    """Table 1 at N = 8, 16 (all four kernels).  The error here is the truncation
-    of the narrow initial profile (K = 1/2) to N - 1 modes per axis, which the
-    paper's mode convention does not state; the pin is the order of magnitude
-    of the printed error, and the point of the table: the four kernels, cutoff
-    and non-cutoff, err alike (within a factor 3 of each other)."""
+    """Table 1 at N = 8, 16 (all four kernels), where the error is the truncation
+    of the narrow initial profile (K = 1/2).  With f sampled, and the error
+    taken, on the cell-centred grid v_j = -L + (j + 1/2) h, the printed values
+    are reproduced to within 15% (measured 0.87-1.05 of the printed value);
+    on the grid v_j = -L + j h they come out 3.4-12x larger, because that grid
+    holds the point v = 0 where the truncated profile errs most."""
     ref = table1()[N]
-    f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L_BKW, o2.bkw2d_K(0.0)))
+    f = workloads.to_spectral_2d(workloads.bkw2d_profile_on_grid(N, L_BKW, o2.bkw2d_K(0.0), centred=True),
+                                 centred=True)
     errs = {}
     for name in KERNELS:
         d = o2.Discretization2D(N, L_BKW, R_BKW, 0.0, o2.PAPER_KERNELS_2D[name], N, 32)
         errs[name] = bkw_table1_error(o2.collision_direct2d(f, d), N)
         print(N, name, f"{errs[name]:.4e}", "paper", f"{ref[name]:.4e}")
     for name in KERNELS:
-        assert ref[name] / 20 < errs[name] < ref[name] * 20, (name, errs[name], ref[name])
-    assert max(errs.values()) < 3 * min(errs.values())
+        assert 0.8 < errs[name] / ref[name] < 1.2, (name, errs[name], ref[name])

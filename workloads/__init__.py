@@ -29,15 +29,18 @@ __all__ = [
     "MaxwellianMixture", "two_maxwellians", "random_mixture", "bkw_profile_on_grid",
     "ProblemConfig", "CFG_SMALL", "CFG_MEDIUM", "CFG_LARGE", "config_input",
     "cell_batch", "request_stream", "to_spectral_2d", "bkw2d_profile_on_grid", "random_mixture_2d",
+    "broadband_spectrum", "broadband_spectrum_2d", "survey_mode_sample",
 ]
 
 
 # --------------------------------------------------------------------------
 # grids and the spectral projection
 # --------------------------------------------------------------------------
-def velocity_grid(N: int, L: float) -> np.ndarray:
-    """1-D grid v_j = -L + j*2L/N, j = 0..N-1 (the same along each axis)."""
-    return -L + (2.0 * L / N) * np.arange(N, dtype=np.float64)
+def velocity_grid(N: int, L: float, centred: bool = False) -> np.ndarray:
+    """1-D grid v_j = -L + j*2L/N, j = 0..N-1 (the same along each axis); with
+    centred=True the cell-centred grid v_j = -L + (j + 1/2) 2L/N, symmetric about
+    0 (the grid on which the paper's Table 1 is reproduced at every N)."""
+    return -L + (2.0 * L / N) * (np.arange(N, dtype=np.float64) + (0.5 if centred else 0.0))
 
 
 def mode_indices(N: int) -> np.ndarray:
@@ -118,23 +121,30 @@ def bkw_profile_on_grid(N: int, L: float, K: float) -> np.ndarray:
         (5 * K - 3) / (2 * K) + (1 - K) * v2 / (2 * K * K))
 
 
-def to_spectral_2d(f_phys: np.ndarray) -> np.ndarray:
-    """The 2-D projection: f_k = N^-2 (-1)^(k1+k2) sum_j f(v_j) e^{-2 pi i k.j/N},
-    Nyquist removed; complex128 N^2 in FFT index order."""
+def to_spectral_2d(f_phys: np.ndarray, centred: bool = False) -> np.ndarray:
+    """The 2-D projection: f_k = N^-2 sum_j f(v_j) e^{-i pi k.v_j/L}, i.e.
+    N^-2 (-1)^(k1+k2) sum_j f(v_j) e^{-2 pi i k.j/N} on the grid v_j = -L + j h,
+    with the extra factor e^{-i pi (k1+k2)/N} for samples on the cell-centred
+    grid v_j = -L + (j + 1/2) h (centred=True); Nyquist removed; complex128 N^2
+    in FFT index order."""
     f_phys = np.asarray(f_phys, dtype=np.float64)
     N = f_phys.shape[0]
     assert f_phys.shape == (N, N) and N % 2 == 0
-    sign = np.where(mode_indices(N) % 2 == 0, 1.0, -1.0)
+    k = mode_indices(N)
+    sign = np.where(k % 2 == 0, 1.0, -1.0).astype(np.complex128)
+    if centred:
+        sign = sign * np.exp(-1j * math.pi * k / N)
     fh = np.fft.fft2(f_phys) / float(N) ** 2 * sign[:, None] * sign[None, :]
     fh[N // 2, :] = 0.0
     fh[:, N // 2] = 0.0
     return fh.astype(np.complex128)
 
 
-def bkw2d_profile_on_grid(N: int, L: float, K: float) -> np.ndarray:
+def bkw2d_profile_on_grid(N: int, L: float, K: float, centred: bool = False) -> np.ndarray:
     """The 2-D BKW profile (2 pi K)^-1 exp(-|v|^2/2K) [ (4K - 2)/(2K) + (1 - K)|v|^2/(2K^2) ]
-    (Section 5.1 with d = 2), sampled on the N^2 grid; used only as initial data."""
-    v = velocity_grid(N, L)
+    (Section 5.1 with d = 2), sampled on the N^2 grid (velocity_grid with
+    `centred`); used only as initial data."""
+    v = velocity_grid(N, L, centred)
     v2 = v[:, None] ** 2 + v[None, :] ** 2
     return np.exp(-v2 / (2 * K)) / (2 * math.pi * K) * ((4 * K - 2) / (2 * K) + (1 - K) * v2 / (2 * K * K))
 
@@ -154,6 +164,52 @@ def random_mixture_2d(seed: int, N: int, L: float) -> np.ndarray:
     for wi, u, T in zip(w, centers, temps):
         f += wi / (2.0 * math.pi * T) * np.exp(-((v[:, None] - u[0]) ** 2 + (v[None, :] - u[1]) ** 2) / (2.0 * T))
     return f
+
+
+def broadband_spectrum(N: int, seed: int, d: int = 3) -> np.ndarray:
+    """Random spectral coefficients with a flat spectrum over K_N (d = 3 or 2):
+    f_k = (a + i b)/sqrt(2), a, b ~ N(0, 1), for every k in K_N, made Hermitian
+    (f_{-k} = conj f_k, f_0 real), Nyquist entries zero; FFT index order.  Its
+    grid function is real but not positive: an input on which every mode of
+    the output, up to the corners of K_N, carries weight (unlike smooth
+    Maxwellians, whose edge modes are ~1e-30 of the peak)."""
+    rng = np.random.default_rng(seed)
+    shape = (N,) * d
+    f = (rng.normal(size=shape) + 1j * rng.normal(size=shape)) / math.sqrt(2.0)
+    # Hermitian part: f_k <- (f_k + conj f_{-k}) / sqrt 2 keeps unit variance
+    fm = np.conj(np.flip(np.roll(f, -1, axis=tuple(range(d))), axis=tuple(range(d))))
+    f = (f + fm) / math.sqrt(2.0)
+    h = N // 2
+    for ax in range(d):
+        idx = [slice(None)] * d
+        idx[ax] = h
+        f[tuple(idx)] = 0.0
+    f[(0,) * d] = f[(0,) * d].real
+    return f.astype(np.complex128)
+
+
+def broadband_spectrum_2d(N: int, seed: int) -> np.ndarray:
+    """`broadband_spectrum` on the 2-D mode set K_N = {-N/2+1..N/2-1}^2."""
+    return broadband_spectrum(N, seed, d=2)
+
+
+def survey_mode_sample(N: int, seed: int, n_random: int = 128, inf_radius: int = 2) -> np.ndarray:
+    """Output modes for sampled parity at large N: every k with |k|_inf <=
+    inf_radius, the 8 corners (+-(N/2-1))^3 of K_N, and n_random uniform modes
+    of K_N (seeded); duplicates removed, order kept.  int64 [n, 3]."""
+    h = N // 2 - 1
+    r = np.arange(-inf_radius, inf_radius + 1)
+    near = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    corners = np.array([(a, b, c) for a in (-h, h) for b in (-h, h) for c in (-h, h)])
+    rng = np.random.default_rng(seed)
+    rnd = rng.integers(-h, h + 1, size=(n_random, 3))
+    out, seen = [], set()
+    for k in np.concatenate([near, corners, rnd]):
+        t = tuple(int(x) for x in k)
+        if t not in seen:
+            seen.add(t)
+            out.append(t)
+    return np.array(out, dtype=np.int64)
 
 
 # --------------------------------------------------------------------------
