@@ -257,9 +257,10 @@ bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hat
  * long as the batch) to plans (which may repeat and may differ in N, gamma,
  * kernel and precision).  Cells sharing a plan run in the same launches, up
  * to 64 cells per launch; cells_per_launch = 0 lets an autotuner choose per
- * plan (timing the candidates 1, 2, 4 ... 64 on these cells once, with the
+ * plan, timing the
+ * candidates 1, 2, 4 ... 64 on these cells once, with the
  * choice cached in the file $BZQ_TUNE_CACHE or ~/.cache/bzq_autotune.txt;
- * workspaces are capped by $BZQ_BATCH_WS_MB, default 8192).  Creation is
+ * workspaces are capped by $BZQ_BATCH_WS_MB, default 8192.  Creation is
  * synchronous and allocates the workspaces.
  *   bzq_batch_collision: Q_hats[i] = Q(f_hats[i]).
  *   bzq_batch_step: n_steps Heun steps of every cell in place; use_graph != 0
@@ -271,6 +272,14 @@ bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hat
  */
 bzq_status bzq_batch_create(bzq_batch* out, const bzq_plan* plans, double* const* f_hats, int count,
                             int cells_per_launch, void* stream);
+/* Mixed sizes in one launch (cells of N = 16, 24, 32 in one launch per
+ * pipeline stage over a device table of (cell, workgroup) work items) is
+ * switched off: its first run on the device ended in a memory fault whose
+ * cause is not known.  cells_per_launch = -1, which demands it, returns
+ * BZQ_EUNSUPPORTED; 0 and > 0 keep one group of launches per plan.
+ * bzq_batch_rounds: the rounds of the mixed launches (always 0 while they are
+ * switched off). */
+int bzq_batch_rounds(bzq_batch b);
 bzq_status bzq_batch_collision(bzq_batch b, double* const* Q_hats, void* stream);
 bzq_status bzq_batch_step(bzq_batch b, double dt, int n_steps, int use_graph, void* stream);
 int bzq_batch_groups(bzq_batch b);

@@ -82,6 +82,7 @@ def _load():
         "bzq_batch_collision": ([vp, ctypes.POINTER(vp), vp], i),
         "bzq_batch_step": ([vp, d, i, i, vp], i),
         "bzq_batch_groups": ([vp], i),
+        "bzq_batch_rounds": ([vp], i),
         "bzq_batch_group_info": ([vp, i, ctypes.POINTER(i)], i),
         "bzq_batch_device_bytes": ([vp], sz),
         "bzq_batch_destroy": ([vp], i),
@@ -483,6 +484,10 @@ class Batch:
 
     def step(self, dt: float, n_steps: int = 1, use_graph: bool = True, stream=None):
         _check(_lib.bzq_batch_step(self._h, float(dt), int(n_steps), int(bool(use_graph)), _stream(stream)))
+
+    def rounds(self) -> int:
+        """Rounds of the mixed-size launches (0: one group of launches per plan)."""
+        return int(_lib.bzq_batch_rounds(self._h))
 
     def groups(self):
         out = []

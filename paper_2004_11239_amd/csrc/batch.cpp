@@ -11,10 +11,22 @@
 // fastest per-cell time) whose choices persist in a text cache keyed by the
 // plan geometry.  A whole Heun step of the batch can be captured once into a
 // HIP graph and replayed.
+//
+// Mixed sizes in one launch (switched off, see kMixedLaunches): when every
+// plan of the batch is an FP32 table plan with N in {16, 24, 32} and the
+// kernel variants of the mixed launches, the cells of all sizes run together,
+// round after round: a round holds, for each size, as many cells as it has
+// workspace slots (slots sized so that all sizes finish in the same number of
+// rounds within the workspace budget), and each pipeline stage of a round is
+// one launch over a device table of (cell, workgroup) items of every size
+// (launch_mix).  Per cell the kernels' bodies, arguments and order are those
+// of the single-cell path.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <memory>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -56,9 +68,28 @@ size_t ws_budget_bytes() {
 
 using namespace bzq;
 
+// Rounds of the mixed-size launches: slot workspaces, the per-round cell
+// tables and work-item offsets on the device.
+struct MixedRounds {
+  std::vector<Workspace*> slot_ws;            // one cell each
+  std::vector<int> slot_group;                // group of each slot
+  int rounds = 0, max_cells = 0;
+  std::vector<int> ncells;                    // active cells per round
+  std::vector<std::array<int, MIX_STAGES>> totals;   // items per (round, stage)
+  MixCell* d_cells = nullptr;                 // [round][max_cells]
+  int* d_offs = nullptr;                      // [round][stage][max_cells + 1]
+  double2** d_outs = nullptr;                 // [cell] outputs of bzq_batch_collision
+  std::vector<double*> h_outs;
+  DeviceArena arena;
+  ~MixedRounds() {
+    for (Workspace* w : slot_ws) delete w;
+  }
+};
+
 struct bzq_batch_s {
   std::vector<double*> f;
   std::vector<Group> groups;
+  std::unique_ptr<MixedRounds> mix;   // set when the cells run in mixed-size launches
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;   // private stream the graph is recorded on
@@ -154,7 +185,32 @@ bzq_status autotune(Group& g, const std::vector<double*>& f, hipStream_t st) {
   return BZQ_OK;
 }
 
+// Phase `phase` of round r in mixed-size launches (phase 0: Q into the
+// batch's outputs; 1, 2: the two evaluations of a Heun step).
+bzq_status enqueue_mixed_round(bzq_batch_s* b, int r, int phase, double a, hipStream_t st) {
+  MixedRounds& m = *b->mix;
+  const MixCell* cells = m.d_cells + (size_t)r * m.max_cells;
+  for (int stg = 0; stg < MIX_STAGES; ++stg) {
+    const int* offs = m.d_offs + ((size_t)r * MIX_STAGES + stg) * (m.max_cells + 1);
+    BZQ_HIP_TRY(launch_mix(stg, cells, offs, m.ncells[r], m.totals[r][stg], phase, a, m.d_outs, st));
+  }
+  return BZQ_OK;
+}
+
+// One evaluation (step = false) or one Heun step of every cell, round after
+// round.  Both evaluations of a step finish within the round: the next round
+// reuses the slots' stage buffers (fs, q1).
+bzq_status enqueue_mixed(bzq_batch_s* b, bool step, double dt, hipStream_t st) {
+  for (int r = 0; r < b->mix->rounds; ++r) {
+    bzq_status s = enqueue_mixed_round(b, r, step ? 1 : 0, dt, st);
+    if (s == BZQ_OK && step) s = enqueue_mixed_round(b, r, 2, 0.5 * dt, st);
+    if (s != BZQ_OK) return s;
+  }
+  return BZQ_OK;
+}
+
 bzq_status enqueue_batch_step(bzq_batch_s* b, double dt, hipStream_t st) {
+  if (b->mix) return enqueue_mixed(b, true, dt, st);
   for (auto& g : b->groups) {
     for (size_t c0 = 0; c0 < g.cells.size(); c0 += g.cpl) {
       const int m = (int)std::min<size_t>(g.cpl, g.cells.size() - c0);
@@ -162,6 +218,115 @@ bzq_status enqueue_batch_step(bzq_batch_s* b, double dt, hipStream_t st) {
       if (s != BZQ_OK) return s;
     }
   }
+  return BZQ_OK;
+}
+
+// The mixed-size launches are switched off: their first run on the device
+// ended in a GPU memory fault whose cause is not known.  Until it is, batches
+// run in groups of one plan each and cells_per_launch = -1 is refused.
+constexpr bool kMixedLaunches = false;
+
+// Whether every group runs in the mixed-size launches.
+bool mixed_eligible(const bzq_batch_s* b) {
+  for (const auto& g : b->groups) {
+    const Plan& p = *g.plan;
+    if (p.otf || p.G != p.npt) return false;
+    if (!mix_supported(p.N, p.fp32, effective_variant(p, 0), effective_variant(p, 1), effective_variant(p, 2)))
+      return false;
+  }
+  return true;
+}
+
+// Rounds for the mixed-size launches: the fewest rounds R for which a slot
+// per ceil(cells / R) cells of every size fits the workspace budget; cells of
+// the largest N first in each round's table (their items are the heaviest).
+bzq_status plan_mixed(bzq_batch_s* b, hipStream_t st) {
+  auto m = std::make_unique<MixedRounds>();
+  const size_t budget = ws_budget_bytes();
+  size_t total_bytes = 0;
+  for (auto& g : b->groups) total_bytes += g.cells.size() * g.plan->workspace_bytes_per_cell();
+  int R = (int)std::max<size_t>(1, (total_bytes + budget - 1) / budget);
+  std::vector<int> k(b->groups.size());
+  for (;; ++R) {
+    size_t need = 0;
+    for (size_t i = 0; i < b->groups.size(); ++i) {
+      k[i] = (int)((b->groups[i].cells.size() + R - 1) / R);
+      need += (size_t)k[i] * b->groups[i].plan->workspace_bytes_per_cell();
+    }
+    if (need <= budget || R >= 1 << 20) break;
+  }
+  std::vector<size_t> order(b->groups.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return b->groups[x].plan->N > b->groups[y].plan->N; });
+  // slots and their workspaces
+  std::vector<std::vector<int>> slots_of(b->groups.size());
+  for (size_t gi : order)
+    for (int j = 0; j < k[gi]; ++j) {
+      auto* w = new Workspace();
+      m->slot_ws.push_back(w);
+      m->slot_group.push_back((int)gi);
+      slots_of[gi].push_back((int)m->slot_ws.size() - 1);
+      bzq_status s = workspace_init(*w, *b->groups[gi].plan, 1);
+      if (s != BZQ_OK) return s;
+    }
+  // round tables
+  int rounds = 0;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi)
+    rounds = std::max(rounds, (int)((b->groups[gi].cells.size() + k[gi] - 1) / k[gi]));
+  m->rounds = rounds;
+  m->max_cells = (int)m->slot_ws.size();
+  std::vector<MixCell> cells((size_t)rounds * m->max_cells);
+  std::vector<int> offs((size_t)rounds * MIX_STAGES * (m->max_cells + 1), 0);
+  m->ncells.assign(rounds, 0);
+  m->totals.assign(rounds, {});
+  for (int r = 0; r < rounds; ++r) {
+    int n = 0;
+    for (size_t gi : order) {
+      const Group& g = b->groups[gi];
+      const Plan& p = *g.plan;
+      for (int j = 0; j < k[gi]; ++j) {
+        const size_t ci = (size_t)r * k[gi] + j;
+        if (ci >= g.cells.size()) break;
+        const Workspace& w = *m->slot_ws[slots_of[gi][j]];
+        MixCell& c = cells[(size_t)r * m->max_cells + n];
+        c.N = p.N;
+        c.npt = p.npt;
+        c.S = p.S;
+        c.cell = g.cells[ci];
+        c.f = (double2*)b->f[c.cell];
+        c.fs = (double2*)w.fs;
+        c.q1 = (double2*)w.q1;
+        c.q2 = (double2*)w.q2;
+        c.fc = w.fc;
+        c.fgrid = (float*)w.fgrid;
+        c.A = w.A;
+        c.B = w.B;
+        c.Qpart = (double2*)w.Qpart;
+        c.V = (const float*)p.V;
+        c.ph = (const double2*)p.ph;
+        c.cp = p.cp;
+        ++n;
+      }
+    }
+    m->ncells[r] = n;
+    for (int stg = 0; stg < MIX_STAGES; ++stg) {
+      int* o = &offs[((size_t)r * MIX_STAGES + stg) * (m->max_cells + 1)];
+      for (int i = 0; i < n; ++i) {
+        const MixCell& c = cells[(size_t)r * m->max_cells + i];
+        o[i + 1] = o[i] + mix_items(stg, c.N, c.npt, c.S);
+      }
+      m->totals[r][stg] = o[n];
+    }
+  }
+  bzq_status s;
+  if ((s = m->arena.get(&m->d_cells, cells.size() * sizeof(MixCell))) != BZQ_OK) return s;
+  if ((s = m->arena.get(&m->d_offs, offs.size() * sizeof(int))) != BZQ_OK) return s;
+  if ((s = m->arena.get(&m->d_outs, b->f.size() * sizeof(double2*))) != BZQ_OK) return s;
+  BZQ_HIP_TRY(hipMemcpyAsync(m->d_cells, cells.data(), cells.size() * sizeof(MixCell), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipMemcpyAsync(m->d_offs, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  BZQ_HIP_TRY(hipStreamSynchronize(st));   // the host tables go out of scope
+  for (size_t i = 0; i < b->groups.size(); ++i) b->groups[i].cpl = k[i];
+  b->mix = std::move(m);
   return BZQ_OK;
 }
 
@@ -174,7 +339,8 @@ bzq_status bzq_batch_create(bzq_batch* out, const bzq_plan* plans, double* const
   if (!out) return fail(BZQ_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 1 || !plans || !f_hats) return fail(BZQ_EINVAL, "bad batch arguments");
-  if (cells_per_launch < 0 || cells_per_launch > kMaxCells) return fail(BZQ_EINVAL, "cells_per_launch must lie in [0, 64]");
+  if (cells_per_launch < -1 || cells_per_launch > kMaxCells)
+    return fail(BZQ_EINVAL, "cells_per_launch must lie in [-1, 64]");
   for (int i = 0; i < count; ++i)
     if (!plans[i] || !f_hats[i]) return fail(BZQ_EINVAL, "NULL entry in batch");
   hipStream_t st = (hipStream_t)stream;
@@ -191,6 +357,25 @@ bzq_status bzq_batch_create(bzq_batch* out, const bzq_plan* plans, double* const
       it = gid.find(plans[i]);
     }
     b->groups[it->second].cells.push_back(i);
+  }
+  if (cells_per_launch < 0 && !kMixedLaunches) {
+    delete b;
+    return fail(BZQ_EUNSUPPORTED, "mixed-size launches are switched off: their first run on the device ended in a "
+                                  "memory fault whose cause is not known");
+  }
+  if (kMixedLaunches && cells_per_launch <= 0 && mixed_eligible(b)) {
+    bzq_status s = plan_mixed(b, st);
+    if (s != BZQ_OK) {
+      delete b;
+      return s;
+    }
+    *out = b;
+    return BZQ_OK;
+  }
+  if (cells_per_launch < 0) {
+    delete b;
+    return fail(BZQ_EUNSUPPORTED, "these plans do not run in mixed-size launches (FP32 table plans with N in "
+                                  "{16, 24, 32} and their default kernel variants only)");
   }
   for (auto& g : b->groups) {
     bzq_status s = BZQ_OK;
@@ -217,6 +402,17 @@ bzq_status bzq_batch_collision(bzq_batch b, double* const* Q_hats, void* stream)
   std::vector<double*> q(Q_hats, Q_hats + b->f.size());
   for (double* x : q)
     if (!x) return fail(BZQ_EINVAL, "NULL output in batch");
+  for (const auto& g : b->groups)
+    for (int c : g.cells)
+      if (ranges_overlap(q[c], b->f[c], state_bytes(g.plan->N)))
+        return fail(BZQ_EINVAL, "an output overlaps its cell's state");
+  if (b->mix) {
+    MixedRounds& m = *b->mix;
+    m.h_outs = q;
+    BZQ_HIP_TRY(hipMemcpyAsync(m.d_outs, m.h_outs.data(), q.size() * sizeof(double*), hipMemcpyHostToDevice, st));
+    BZQ_HIP_TRY(hipStreamSynchronize(st));   // h_outs may change with the next call
+    return enqueue_mixed(b, false, 0.0, st);
+  }
   for (auto& g : b->groups) {
     for (size_t c0 = 0; c0 < g.cells.size(); c0 += g.cpl) {
       const int m = (int)std::min<size_t>(g.cpl, g.cells.size() - c0);
@@ -278,10 +474,17 @@ bzq_status bzq_batch_group_info(bzq_batch b, int group, int* out) {
 
 size_t bzq_batch_device_bytes(bzq_batch b) {
   size_t n = 0;
-  if (b)
+  if (b) {
     for (auto& g : b->groups) n += g.ws ? g.ws->arena.bytes : 0;
+    if (b->mix) {
+      for (Workspace* w : b->mix->slot_ws) n += w->arena.bytes;
+      n += b->mix->arena.bytes;
+    }
+  }
   return n;
 }
+
+int bzq_batch_rounds(bzq_batch b) { return b && b->mix ? b->mix->rounds : 0; }
 
 bzq_status bzq_batch_destroy(bzq_batch b) {
   if (!b) return BZQ_OK;

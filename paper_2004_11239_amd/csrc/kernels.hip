@@ -384,26 +384,24 @@ __device__ __forceinline__ constexpr int posKc(int i) {
 }
 
 // modulation (mode ZINV_PAIRS), plain copy or grid sign, then inverse FFT
-// along axis 3; one thread per pencil c (i1 fastest)
+// along axis 3; one thread per pencil c (i1 fastest).  The body of one
+// workgroup (pencil block bx, pair-two pt) of one cell; s3 holds 2(N-1)
+// values of LDS.  Also the z-inverse of the mixed-size launch.
 template <typename T, int N, int P, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
-                                                 cx<T>* __restrict__ A, int pair0, CellStrides cs) {
+__device__ __forceinline__ void zinv_reg_body(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
+                                              cx<T>* __restrict__ A, int pair0, int bx, int pt, cx<T>* s3, const unsigned tx) {
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
-  fc += blockIdx.z * cs.fc;
-  A += blockIdx.z * cs.a;
-  const int pt = blockIdx.y;
   // axis-3 factors of the pair-two in LDS, in the compute type (see k_zinv_half)
-  __shared__ cx<T> s3[MODE == ZINV_PAIRS ? 2 * n1 : 1];
   const double2* phA = MODE == ZINV_PAIRS ? ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2) : nullptr;
   const double2* phB = MODE == ZINV_PAIRS ? phA + 3 * PL : nullptr;
   if constexpr (MODE == ZINV_PAIRS) {
-    for (int t = threadIdx.x; t < 2 * n1; t += NT) {
+    for (int t = tx; t < 2 * n1; t += NT) {
       const int i3 = t < n1 ? t : t - n1;
       s3[t] = to_cx<T>((t < n1 ? phA : phB)[2 * PL - 2 * (i3 - h + 1)]);
     }
     __syncthreads();
   }
-  const int c = blockIdx.x * NT + threadIdx.x;
+  const int c = bx * NT + tx;
   if (c >= nn) return;
   const int i2 = c / n1, i1 = c - i2 * n1;
   const int k1 = i1 - h + 1, k2 = i2 - h + 1;
@@ -438,17 +436,22 @@ __global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, c
   for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * nn] = v[zi];
 }
 
+template <typename T, int N, int P, int NT, int MODE>
+__global__ __launch_bounds__(NT) void k_zinv_reg(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
+                                                 cx<T>* __restrict__ A, int pair0, CellStrides cs) {
+  __shared__ cx<T> s3[MODE == ZINV_PAIRS ? 2 * (N - 1) : 1];
+  zinv_reg_body<T, N, P, NT, MODE>(fc + blockIdx.z * cs.fc, ph, A + blockIdx.z * cs.a, pair0, blockIdx.x,
+                                   blockIdx.y, s3, threadIdx.x);
+}
+
 // The first step of an evaluation in one launch: the compact copy of f (as
 // k_ingest) and its inverse transform along axis 3 (as k_zinv_reg in mode
 // ZINV_PLAIN, into the slot of pair-two 0); one thread per pencil c.
 template <typename T, int N, int P, int NT>
-__global__ __launch_bounds__(NT) void k_zinv_ingest(PtrPack fin, cx<T>* __restrict__ fc, cx<T>* __restrict__ A,
-                                                    CellStrides cs, int* __restrict__ flag) {
+__device__ __forceinline__ void zinv_ingest_body(const double2* __restrict__ f, cx<T>* __restrict__ fc,
+                                                 cx<T>* __restrict__ A, int* __restrict__ flag, int bx, const unsigned tx) {
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1;
-  const double2* __restrict__ f = (const double2*)fin.p[blockIdx.z];
-  fc += blockIdx.z * cs.fc;
-  A += blockIdx.z * cs.a;
-  const int c = blockIdx.x * NT + threadIdx.x;
+  const int c = bx * NT + tx;
   if (c >= nn) return;
   const int i2 = c / n1, i1 = c - i2 * n1;
   const int a = (i1 - h + 1 + N) % N, b = (i2 - h + 1 + N) % N;
@@ -472,6 +475,13 @@ __global__ __launch_bounds__(NT) void k_zinv_ingest(PtrPack fin, cx<T>* __restri
   for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * nn] = v[zi];
 }
 
+template <typename T, int N, int P, int NT>
+__global__ __launch_bounds__(NT) void k_zinv_ingest(PtrPack fin, cx<T>* __restrict__ fc, cx<T>* __restrict__ A,
+                                                    CellStrides cs, int* __restrict__ flag) {
+  zinv_ingest_body<T, N, P, NT>((const double2*)fin.p[blockIdx.z], fc + blockIdx.z * cs.fc, A + blockIdx.z * cs.a,
+                                flag, blockIdx.x, threadIdx.x);
+}
+
 template <typename T, int P>
 struct PlaneCfg {
   static constexpr int Z = P == 8 ? 8 : P == 12 ? 12 : P == 16 ? 8 : P == 24 ? 8 : P == 32 ? 4
@@ -482,23 +492,18 @@ struct PlaneCfg {
 
 // Z planes of one pair-two per workgroup; one thread per row (axis 2) or
 // column (axis 1) of a plane.  LDS holds the N-1 mode rows of each plane.
+// The body of one workgroup (z block bx, pair-two pt) of one cell; sm holds
+// PlaneCfg<T, P>::Z (N-1)(P+1) values of LDS.  Also the plane stage of the
+// mixed-size launch (with more threads than PlaneCfg<T, P>::NT: the extra
+// ones idle).
 template <typename T, int N, int P, int MODE>
-__global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>* __restrict__ A,
-                                                                  cx<T>* __restrict__ B,
-                                                                  const T* __restrict__ fgrid,
-                                                                  T* __restrict__ gridout, CellStrides cs) {
+__device__ __forceinline__ void plane_reg_body(const cx<T>* __restrict__ A, cx<T>* __restrict__ B,
+                                               const T* __restrict__ fgrid, T* __restrict__ gridout, int bx, int pt,
+                                               cx<T>* sm, const unsigned tx) {
   constexpr int n1 = N - 1, nn = n1 * n1, LD = P + 1;
-  A += blockIdx.z * cs.a;
-  if constexpr (MODE == PLANE_TO_GRID) {
-    gridout += blockIdx.z * cs.fg;
-  } else {
-    B += blockIdx.z * cs.b;
-    fgrid += blockIdx.z * cs.fg;
-  }
   constexpr int Z = PlaneCfg<T, P>::Z;
-  __shared__ cx<T> sm[Z * n1 * LD];
-  const int z0 = blockIdx.x * Z, pt = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int z0 = bx * Z;
+  const int tid = tx;
   // rows: inverse along axis 2
   if (tid < Z * n1) {
     const int zz = tid / n1, i1 = tid - zz * n1;
@@ -557,6 +562,20 @@ __global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>*
       if (c == cmid) st_nt(Bout + nhp + cmid, w);
     }
   }
+}
+
+template <typename T, int N, int P, int MODE>
+__global__ __launch_bounds__((PlaneCfg<T, P>::NT)) void k_plane_reg(const cx<T>* __restrict__ A,
+                                                                  cx<T>* __restrict__ B,
+                                                                  const T* __restrict__ fgrid,
+                                                                  T* __restrict__ gridout, CellStrides cs) {
+  __shared__ cx<T> sm[PlaneCfg<T, P>::Z * (N - 1) * (P + 1)];
+  if constexpr (MODE == PLANE_TO_GRID)
+    plane_reg_body<T, N, P, MODE>(A + blockIdx.z * cs.a, B, fgrid, gridout + blockIdx.z * cs.fg, blockIdx.x,
+                                  blockIdx.y, sm, threadIdx.x);
+  else
+    plane_reg_body<T, N, P, MODE>(A + blockIdx.z * cs.a, B + blockIdx.z * cs.b, fgrid + blockIdx.z * cs.fg, gridout,
+                                  blockIdx.x, blockIdx.y, sm, threadIdx.x);
 }
 
 
@@ -1398,25 +1417,34 @@ __device__ __forceinline__ void zfwd_produce(const cx<T>* __restrict__ Bin, cx<T
   }
 }
 
+// LDS of one k_zfwd_pipe workgroup
 template <typename T, int N, int P>
-__global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
-    const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
-    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
-    int first, CellStrides cs) {
+struct ZfwdPipeLds {
+  cx<T> W[2][N - 1][2 * ZfwdPipeCfg<P>::TQ];
+  double2 E12[2][2][ZfwdPipeCfg<P>::TQ];
+  double2 E3[2][2][N - 1];
+  double CPV[2][2];
+};
+
+// The body of one workgroup (tile bx, split s) of one cell; also the last
+// stage of the mixed-size launch at P = 48.
+template <typename T, int N, int P>
+__device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, const T* __restrict__ V,
+                                               const double2* __restrict__ ph, const double* __restrict__ cp,
+                                               double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
+                                               int first, int bx, int s, ZfwdPipeLds<T, N, P>& L, const unsigned tx) {
   using C = ZfwdPipeCfg<P>;
   constexpr int TQ = C::TQ, PW = C::PW, NC = 64 * C::CW;
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
   constexpr int nhp = (nh + 15) / 16 * 16;
   constexpr int OPT = (TQ * n1 + NC - 1) / NC;
-  B += blockIdx.z * cs.b;
-  Qpart += blockIdx.z * cs.qp;
-  __shared__ cx<T> W[2][n1][2 * TQ];
-  __shared__ double2 E12[2][2][TQ];
-  __shared__ double2 E3[2][2][n1];
-  __shared__ double CPV[2][2];
-  const int c0 = blockIdx.x * TQ, s = blockIdx.y;
-  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
+  auto& W = L.W;
+  auto& E12 = L.E12;
+  auto& E3 = L.E3;
+  auto& CPV = L.CPV;
+  const int c0 = bx * TQ;
+  const int wv = __builtin_amdgcn_readfirstlane((int)tx >> 6);
+  const int lane = tx & 63;
   const int nmine = s < npt ? (npt - 1 - s) / S + 1 : 0;
   if (wv < PW) {
     // ---- producers
@@ -1460,7 +1488,7 @@ __global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
     }
   } else {
     // ---- consumers: output modes o = t + bb NC of the tile (i3 = o / TQ, pencil c0 + o % TQ)
-    const int t = (int)threadIdx.x - 64 * PW;
+    const int t = (int)tx - 64 * PW;
     double accx[OPT], accy[OPT];
     T va[OPT], vb[OPT];
 #pragma unroll
@@ -1515,6 +1543,16 @@ __global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
   }
 }
 
+template <typename T, int N, int P>
+__global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
+    const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
+    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
+    int first, CellStrides cs) {
+  __shared__ ZfwdPipeLds<T, N, P> lds;
+  zfwd_pipe_body<T, N, P>(B + blockIdx.z * cs.b, V, ph, cp, Qpart + blockIdx.z * cs.qp, pair0, vpair0, npt, S,
+                          first, blockIdx.x, blockIdx.y, lds, threadIdx.x);
+}
+
 // Forward FFT along axis 3 with one thread per (pencil, pair-two), then the
 // split of the two packed pairs, the weights and the FP64 accumulation.
 // A workgroup owns TQ half-spectrum pencils c0..c0+TQ-1 (and their mirrors)
@@ -1529,24 +1567,32 @@ struct ZfwdCfg {
   static constexpr int NT = 2 * TQ * PT;
 };
 
+// LDS of one k_zfwd_reg workgroup
 template <typename T, int N, int P>
-__global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
-    const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
-    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
-    int first, CellStrides cs) {
+struct ZfwdRegLds {
+  cx<T> W[ZfwdCfg<T, P>::PT][N - 1][2 * ZfwdCfg<T, P>::TQ];   // kept modes [pt][i3][pencil]
+  double2 E12[ZfwdCfg<T, P>::PT][2][ZfwdCfg<T, P>::TQ];       // e^{ia(k1 s1 + k2 s2)} per pair A/B, pencil
+  double2 E3[ZfwdCfg<T, P>::PT][2][N - 1];                    // e^{ia k3 s3} per pair A/B
+  double CPV[ZfwdCfg<T, P>::PT][2];
+};
+
+// The body of one workgroup (tile bx, split s) of one cell; also the last
+// stage of the mixed-size launch at P < 48.
+template <typename T, int N, int P>
+__device__ __forceinline__ void zfwd_reg_body(const cx<T>* __restrict__ B, const T* __restrict__ V,
+                                              const double2* __restrict__ ph, const double* __restrict__ cp,
+                                              double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
+                                              int first, int bx, int s, ZfwdRegLds<T, N, P>& L, const unsigned tx) {
   using C = ZfwdCfg<T, P>;
-  B += blockIdx.z * cs.b;
-  Qpart += blockIdx.z * cs.qp;
   constexpr int TQ = C::TQ, PT = C::PT, NT = C::NT;
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
   constexpr int OPT = (TQ * n1 + NT - 1) / NT;
-  __shared__ cx<T> W[PT][n1][2 * TQ];            // kept modes [pt][i3][pencil]
-  __shared__ double2 E12[PT][2][TQ];             // e^{ia(k1 s1 + k2 s2)} per pair A/B, pencil
-  __shared__ double2 E3[PT][2][n1];              // e^{ia k3 s3} per pair A/B
-  __shared__ double CPV[PT][2];
-  const int c0 = blockIdx.x * TQ;
-  const int s = blockIdx.y;
-  const int tid = threadIdx.x;
+  auto& W = L.W;
+  auto& E12 = L.E12;
+  auto& E3 = L.E3;
+  auto& CPV = L.CPV;
+  const int c0 = bx * TQ;
+  const int tid = tx;
   const int ngroups = (npt + PT - 1) / PT;
   double accx[OPT], accy[OPT];
 #pragma unroll
@@ -1627,6 +1673,16 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
   });
 }
 
+template <typename T, int N, int P>
+__global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
+    const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
+    const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
+    int first, CellStrides cs) {
+  __shared__ ZfwdRegLds<T, N, P> lds;
+  zfwd_reg_body<T, N, P>(B + blockIdx.z * cs.b, V, ph, cp, Qpart + blockIdx.z * cs.qp, pair0, vpair0, npt, S, first,
+                         blockIdx.x, blockIdx.y, lds, threadIdx.x);
+}
+
 
 // ---------------------------------------------------------------- finalize
 // Sixteen lanes per half-spectrum mode (c, i3), 16 modes per workgroup: lane
@@ -1636,32 +1692,50 @@ __global__ __launch_bounds__((ZfwdCfg<T, P>::NT)) void k_zfwd_reg(
 // from k3 >= 0 only, so Q(-k) is exactly conj Q(k) everywhere.  The remaining
 // workgroups zero the Nyquist planes.
 constexpr int kFinModes = 16, kFinLanes = 16;
-// the fused update at element i of cell c where Q = (qx, qy)
-__device__ __forceinline__ void fin_update(const FinUpdate& u, int c, size_t i, double qx, double qy) {
-  double2* __restrict__ F = (double2*)u.f.p[c];
-  double2* __restrict__ W = (double2*)(u.ws + (size_t)c * u.wstride);
-  const double2 x = F[i];
+// The output of one cell's finalisation and its fused update: Q the result,
+// F the state, W the stage buffer (FinUpdate for this cell).
+struct FinCell {
+  double2* Q;
+  double2* F;
+  double2* W;
+  int mode;
+  double a;
+};
+
+// the fused update at element i where Q = (qx, qy)
+__device__ __forceinline__ void fin_update(const FinCell& u, size_t i, double qx, double qy) {
+  const double2 x = u.F[i];
   if (u.mode == FIN_STAGE) {
-    W[i] = double2{x.x + u.a * qx, x.y + u.a * qy};
+    u.W[i] = double2{x.x + u.a * qx, x.y + u.a * qy};
   } else {
-    const double2 y = W[i];
-    F[i] = double2{x.x + u.a * (y.x + qx), x.y + u.a * (y.y + qy)};
+    const double2 y = u.W[i];
+    u.F[i] = double2{x.x + u.a * (y.x + qx), x.y + u.a * (y.y + qy)};
   }
 }
 
-__global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qpart, PtrPack qout, int N, int S,
-                                                  size_t qp_stride, FinUpdate upd) {
-  __shared__ double2 red[kFinLanes][kFinModes];
+// Workgroups of one cell's finalisation at N: the half-spectrum blocks, then
+// the Nyquist blocks.
+__host__ __device__ __forceinline__ int fin_main_blocks(int N) {
+  const int nh = ((N - 1) * (N - 1) + 1) / 2;
+  return (nh * (N - 1) + kFinModes - 1) / kFinModes;
+}
+__host__ __device__ __forceinline__ int fin_blocks(int N) {
+  return fin_main_blocks(N) + (3 * N * N - 3 * N + 1 + 255) / 256;
+}
+
+// The body of workgroup bx of gx of one cell; also the finalisation of the
+// mixed-size launch.
+__device__ __forceinline__ void finalize_body(const double2* __restrict__ Qpart, int N, int S, const FinCell& u,
+                                              int bx, int gx, double2 (*red)[kFinModes], const unsigned tx) {
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, cmid = (nn - 1) / 2;
-  Qpart += blockIdx.y * qp_stride;
-  double2* __restrict__ Q = (double2*)qout.p[blockIdx.y];
+  double2* __restrict__ Q = u.Q;
   const int nmain = nh * n1;
   const int nnyq = 3 * N * N - 3 * N + 1;
-  const int slot = threadIdx.x & (kFinModes - 1);                       // mode within the workgroup
-  const int lane = (threadIdx.x >> 6) * 4 + ((threadIdx.x >> 4) & 3);  // residue of s, 0..15
+  const int slot = tx & (kFinModes - 1);                       // mode within the workgroup
+  const int lane = (tx >> 6) * 4 + ((tx >> 4) & 3);  // residue of s, 0..15
   const int nblk_main = (nmain + kFinModes - 1) / kFinModes;
-  if ((int)blockIdx.x < nblk_main) {
-    const int e = blockIdx.x * kFinModes + slot;
+  if (bx < nblk_main) {
+    const int e = bx * kFinModes + slot;
     double x = 0.0, y = 0.0;
     if (e < nmain) {
       const int i3 = e / nh, c = e - i3 * nh;
@@ -1673,7 +1747,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qp
     }
     red[lane][slot] = double2{x, y};
     __syncthreads();
-    if (threadIdx.x < kFinModes && e < nmain) {
+    if (tx < kFinModes && e < nmain) {
       const int i3 = e / nh, c = e - i3 * nh;
       const int i2 = c / n1, i1 = c - i2 * n1;
       const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
@@ -1690,22 +1764,31 @@ __global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qp
       const bool mirror = k1 != 0 || k2 != 0 || k3 != 0;
       Q[ip] = double2{sx, sy};
       if (mirror) Q[im] = double2{sx, -sy};
-      if (upd.mode != FIN_NONE) {
-        fin_update(upd, blockIdx.y, ip, sx, sy);
-        if (mirror) fin_update(upd, blockIdx.y, im, sx, -sy);
+      if (u.mode != FIN_NONE) {
+        fin_update(u, ip, sx, sy);
+        if (mirror) fin_update(u, im, sx, -sy);
       }
     }
     return;
   }
   // Nyquist entries: plane a = h, then b = h (a != h), then d = h (a, b != h)
-  for (int r0 = (blockIdx.x - nblk_main) * 256 + threadIdx.x; r0 < nnyq; r0 += (gridDim.x - nblk_main) * 256) {
+  for (int r0 = (bx - nblk_main) * 256 + tx; r0 < nnyq; r0 += (gx - nblk_main) * 256) {
     int r = r0, a, b, d;
     if (r < N * N) { a = h; b = r / N; d = r % N; }
     else if ((r -= N * N) < N * (N - 1)) { a = r / N; a += a >= h; b = h; d = r % N; }
     else { r -= N * (N - 1); a = r / (N - 1); a += a >= h; b = r % (N - 1); b += b >= h; d = h; }
     Q[((size_t)a * N + b) * N + d] = double2{0.0, 0.0};
-    if (upd.mode != FIN_NONE) fin_update(upd, blockIdx.y, ((size_t)a * N + b) * N + d, 0.0, 0.0);
+    if (u.mode != FIN_NONE) fin_update(u, ((size_t)a * N + b) * N + d, 0.0, 0.0);
   }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double2* __restrict__ Qpart, PtrPack qout, int N, int S,
+                                                  size_t qp_stride, FinUpdate upd) {
+  __shared__ double2 red[kFinLanes][kFinModes];
+  const int c = blockIdx.y;
+  const FinCell u{(double2*)qout.p[c], (double2*)upd.f.p[c], (double2*)(upd.ws + (size_t)c * upd.wstride), upd.mode,
+                  upd.a};
+  finalize_body(Qpart + c * qp_stride, N, S, u, blockIdx.x, gridDim.x, red, threadIdx.x);
 }
 
 // ------------------------------------------------------------------- table
@@ -2135,6 +2218,188 @@ int zfwd_blocks_t(int variant) {
 
 }  // namespace
 
+// ------------------------------------------------- mixed-size launches
+// Independent cells of different N (16, 24, 32; FP32 bulk) in one launch per
+// pipeline stage: the launch walks a device work table of (cell, workgroup of
+// that cell's stage) items, one item per workgroup, whatever the cells' sizes.
+// Each item runs the body of the single-cell kernel for the cell's N with the
+// same arguments, so every cell's result is bitwise that of the single-cell
+// path.  The cells' geometry and buffers come from MixCell descriptors;
+// offs[k] is the first item of cell k (offs[n] = the round's item count).
+// A persistent variant (a fixed grid looping over items taken from a device
+// counter) kept the loop-invariant addresses and constants of all three sizes
+// live across its loop: 213 VGPRs in the plane stage and 247 in the last
+// stage, against the 157 and 208 of the single-cell kernels, which costs the
+// plane stage a third of its resident waves.  One item per workgroup keeps the
+// single-cell register counts.
+namespace {
+
+template <int ST>
+struct MixCfg;
+template <>
+struct MixCfg<MIX_INGEST> {
+  static constexpr int NT = 64;
+  static constexpr size_t LDS = 16;
+};
+template <>
+struct MixCfg<MIX_GRID> {
+  static constexpr int NT = 192;
+  static constexpr size_t LDS = PlaneCfg<float, 48>::Z * 31 * 49 * 8;
+};
+template <>
+struct MixCfg<MIX_ZINV> {
+  static constexpr int NT = 64;
+  static constexpr size_t LDS = 2 * 31 * 8;
+};
+template <>
+struct MixCfg<MIX_PLANE> {
+  static constexpr int NT = 192;
+  static constexpr size_t LDS = PlaneCfg<float, 48>::Z * 31 * 49 * 8;
+};
+template <>
+struct MixCfg<MIX_ZFWD> {
+  static constexpr int NT = 128;
+  static constexpr size_t LDS = sizeof(ZfwdPipeLds<float, 32, 48>) > sizeof(ZfwdRegLds<float, 24, 36>)
+                                    ? sizeof(ZfwdPipeLds<float, 32, 48>)
+                                    : sizeof(ZfwdRegLds<float, 24, 36>);
+};
+template <>
+struct MixCfg<MIX_FINAL> {
+  static constexpr int NT = 256;
+  static constexpr size_t LDS = sizeof(double2) * kFinLanes * kFinModes;
+};
+
+template <int N>
+constexpr int mixP() { return 3 * N / 2; }
+
+// one item of stage ST for a cell of size N; `local` is the item within the cell
+template <int ST, int N>
+__device__ __forceinline__ void mix_item(const MixCell& c, int local, int phase, double a, double2* const* outs,
+                                         unsigned char* lds, const unsigned tx) {
+  constexpr int P = mixP<N>(), n1 = N - 1, nn = n1 * n1;
+  static_assert(PlaneCfg<float, P>::NT <= MixCfg<MIX_PLANE>::NT, "plane threads");
+  const double2* fin = phase == 2 ? c.fs : c.f;
+  if constexpr (ST == MIX_INGEST) {
+    zinv_ingest_body<float, N, P, 64>(fin, (cx<float>*)c.fc, (cx<float>*)c.A, nullptr, local, tx);
+  } else if constexpr (ST == MIX_GRID) {
+    plane_reg_body<float, N, P, PLANE_TO_GRID>((const cx<float>*)c.A, nullptr, nullptr, c.fgrid, local, 0,
+                                               (cx<float>*)lds, tx);
+  } else if constexpr (ST == MIX_ZINV) {
+    constexpr int gx = (nn + 63) / 64;
+    zinv_reg_body<float, N, P, 64, ZINV_PAIRS>((const cx<float>*)c.fc, c.ph, (cx<float>*)c.A, 0, local % gx, local / gx,
+                                               (cx<float>*)lds, tx);
+  } else if constexpr (ST == MIX_PLANE) {
+    constexpr int gx = P / PlaneCfg<float, P>::Z;
+    plane_reg_body<float, N, P, PLANE_PRODUCT>((const cx<float>*)c.A, (cx<float>*)c.B, c.fgrid, nullptr, local % gx,
+                                               local / gx, (cx<float>*)lds, tx);
+  } else if constexpr (ST == MIX_ZFWD) {
+    constexpr int tiles = ((nn + 1) / 2 + 31) / 32;
+    if constexpr (P == 48)
+      zfwd_pipe_body<float, N, P>((const cx<float>*)c.B, c.V, c.ph, c.cp, c.Qpart, 0, 0, c.npt, c.S, 1, local % tiles,
+                                  local / tiles,
+                                  *(ZfwdPipeLds<float, N, P>*)lds, tx);
+    else
+      zfwd_reg_body<float, N, P>((const cx<float>*)c.B, c.V, c.ph, c.cp, c.Qpart, 0, 0, c.npt, c.S, 1, local % tiles,
+                                 local / tiles,
+                                 *(ZfwdRegLds<float, N, P>*)lds, tx);
+  } else {
+    FinCell u;
+    u.F = c.f;
+    if (phase == 0) {
+      u.Q = outs[c.cell];
+      u.W = nullptr;
+      u.mode = FIN_NONE;
+    } else if (phase == 1) {
+      u.Q = c.q1;
+      u.W = c.fs;
+      u.mode = FIN_STAGE;
+    } else {
+      u.Q = c.q2;
+      u.W = c.q1;
+      u.mode = FIN_HEUN;
+    }
+    u.a = a;
+    finalize_body(c.Qpart, N, c.S, u, local, fin_blocks(N), (double2(*)[kFinModes])lds, tx);
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(MixCfg<ST>::NT) void k_mix(const MixCell* __restrict__ cells, const int* __restrict__ offs,
+                                                        int ncells, int phase, double a,
+                                                        double2* const* __restrict__ outs) {
+  __shared__ __align__(16) unsigned char lds[MixCfg<ST>::LDS];
+  // the item's cell: the last k with offs[k] <= item (uniform over the workgroup)
+  const int item = blockIdx.x;
+  int lo = 0, hi = ncells;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  const MixCell& c = cells[lo];
+  const int local = item - offs[lo];
+  if (c.N == 16) mix_item<ST, 16>(c, local, phase, a, outs, lds, threadIdx.x);
+  else if (c.N == 24) mix_item<ST, 24>(c, local, phase, a, outs, lds, threadIdx.x);
+  else mix_item<ST, 32>(c, local, phase, a, outs, lds, threadIdx.x);
+}
+
+template <int ST>
+int mix_items_t(int N, int npt, int S) {
+  auto per = [&](auto tag) -> int {
+    constexpr int NN = decltype(tag)::value, P = mixP<NN>(), nn = (NN - 1) * (NN - 1);
+    if constexpr (ST == MIX_INGEST) return (nn + 63) / 64;
+    else if constexpr (ST == MIX_GRID) return P / PlaneCfg<float, P>::Z;
+    else if constexpr (ST == MIX_ZINV) return (nn + 63) / 64 * npt;
+    else if constexpr (ST == MIX_PLANE) return P / PlaneCfg<float, P>::Z * npt;
+    else if constexpr (ST == MIX_ZFWD) return ((nn + 1) / 2 + 31) / 32 * S;
+    else return fin_blocks(NN);
+  };
+  if (N == 16) return per(std::integral_constant<int, 16>{});
+  if (N == 24) return per(std::integral_constant<int, 24>{});
+  if (N == 32) return per(std::integral_constant<int, 32>{});
+  return 0;
+}
+
+template <int ST>
+hipError_t mix_launch_t(const MixCell* cells, const int* offs, int ncells, int total, int phase, double a,
+                        double2* const* outs, hipStream_t st) {
+  if (total < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_mix<ST>, dim3(total), dim3(MixCfg<ST>::NT), 0, st, cells, offs, ncells, phase, a, outs);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool mix_supported(int N, bool fp32, int zinv_variant, int plane_variant, int zfwd_variant) {
+  if (!fp32 || (N != 16 && N != 24 && N != 32)) return false;
+  return zinv_variant == 1 && plane_variant == 1 && zfwd_variant == (N == 32 ? 2 : 1);
+}
+
+int mix_items(int stage, int N, int npt, int S) {
+  switch (stage) {
+    case MIX_INGEST: return mix_items_t<MIX_INGEST>(N, npt, S);
+    case MIX_GRID: return mix_items_t<MIX_GRID>(N, npt, S);
+    case MIX_ZINV: return mix_items_t<MIX_ZINV>(N, npt, S);
+    case MIX_PLANE: return mix_items_t<MIX_PLANE>(N, npt, S);
+    case MIX_ZFWD: return mix_items_t<MIX_ZFWD>(N, npt, S);
+    case MIX_FINAL: return mix_items_t<MIX_FINAL>(N, npt, S);
+  }
+  return 0;
+}
+
+hipError_t launch_mix(int stage, const MixCell* cells, const int* offs, int ncells, int total, int phase, double a,
+                      double2* const* outs, hipStream_t st) {
+  switch (stage) {
+    case MIX_INGEST: return mix_launch_t<MIX_INGEST>(cells, offs, ncells, total, phase, a, outs, st);
+    case MIX_GRID: return mix_launch_t<MIX_GRID>(cells, offs, ncells, total, phase, a, outs, st);
+    case MIX_ZINV: return mix_launch_t<MIX_ZINV>(cells, offs, ncells, total, phase, a, outs, st);
+    case MIX_PLANE: return mix_launch_t<MIX_PLANE>(cells, offs, ncells, total, phase, a, outs, st);
+    case MIX_ZFWD: return mix_launch_t<MIX_ZFWD>(cells, offs, ncells, total, phase, a, outs, st);
+    case MIX_FINAL: return mix_launch_t<MIX_FINAL>(cells, offs, ncells, total, phase, a, outs, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------ no-allocation scratch
 // The scratch of bzq_collision_noalloc: a file-scope device array, one copy on
 // every GPU the library runs on, held until the process ends.  In host code
@@ -2264,9 +2529,7 @@ unsigned stage_variants(int stage, int P, bool fp32) {
 
 hipError_t launch_finalize(const double* Qpart, const PtrPack& Q, size_t qp_stride, int cells, int N, int S,
                            hipStream_t st, const FinUpdate& upd) {
-  const size_t nh = ((size_t)(N - 1) * (N - 1) + 1) / 2;
-  const size_t nmain = nh * (N - 1), nnyq = 3 * (size_t)N * N - 3 * N + 1;
-  dim3 grid((unsigned)((nmain + kFinModes - 1) / kFinModes + (nnyq + 255) / 256), cells);
+  dim3 grid((unsigned)fin_blocks(N), cells);
   hipLaunchKernelGGL(k_finalize, grid, dim3(256), 0, st, (const double2*)Qpart, Q, N, S, qp_stride, upd);
   return hipGetLastError();
 }

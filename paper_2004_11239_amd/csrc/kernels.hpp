@@ -127,6 +127,39 @@ hipError_t launch_heun_cells(const PtrPack& f, const PtrPack& q1, const PtrPack&
 hipError_t launch_table(void* V, const double* pairdat, const double* gj, int nj, int N,
                         int npairs, bool fp32, hipStream_t st);
 
+// Mixed-size launches (FP32 bulk, N in {16, 24, 32}): one launch per pipeline
+// stage over the cells of a round, one work item (cell, workgroup of that
+// cell's stage) per workgroup, from a device work table (offs: first item of
+// each cell).  Stages, in order: the compact copy of f with its transform
+// along axis 3, f on the padded grid, the z-inverse, the plane, the z-forward
+// with the weights, the finalisation.
+enum MixStage { MIX_INGEST = 0, MIX_GRID = 1, MIX_ZINV = 2, MIX_PLANE = 3, MIX_ZFWD = 4, MIX_FINAL = 5, MIX_STAGES = 6 };
+struct MixCell {
+  int N;               // 16, 24 or 32
+  int npt, S;          // pair-twos (one chunk), splits of the last stage
+  int cell;            // index of the cell in its batch (output of a plain evaluation)
+  double2* f;          // state: the input of a plain evaluation and of the first Heun stage
+  double2* fs;         // stage state (input of the second Heun stage)
+  double2* q1;         // Q of the first Heun stage
+  double2* q2;         // Q of the second
+  void* fc;            // workspace of the cell's slot (complex FP32, FP32, complex FP32 x 2)
+  float* fgrid;
+  void* A;
+  void* B;
+  double2* Qpart;
+  const float* V;      // tables of the cell's plan
+  const double2* ph;
+  const double* cp;
+};
+// Whether a plan (N, precision, kernel variants as used) runs in the mixed
+// launches, and the work items of stage `stage` of one such cell.
+bool mix_supported(int N, bool fp32, int zinv_variant, int plane_variant, int zfwd_variant);
+int mix_items(int stage, int N, int npt, int S);
+// phase 0: Q = Q(f) into outs[cell]; 1: q1 = Q(f), fs = f + a q1; 2: q2 = Q(fs),
+// f += a (q1 + q2) (the two evaluations of a Heun step with a = dt, dt/2)
+hipError_t launch_mix(int stage, const MixCell* cells, const int* offs, int ncells, int total, int phase, double a,
+                      double2* const* outs, hipStream_t st);
+
 // Size of the static device scratch of bzq_collision_noalloc, and its device
 // address on the current device (looked up once per device, then cached).
 constexpr size_t kNoAllocScratchBytes = 128ull << 20;

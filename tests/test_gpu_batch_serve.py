@@ -271,3 +271,66 @@ def test_server_gamma_sibling_without_room_for_both(bzq):
     f = _dev(_f(N, 8.0, 42))
     p.step(f, 0.01, 1)
     assert np.array_equal(_host(f), qb)
+
+
+def test_mixed_size_launches_are_refused(bzq):
+    """While the mixed-size launches are switched off, a batch that demands
+    them (cells_per_launch = -1) is refused with BZQ_EUNSUPPORTED before any
+    of their kernels runs, and the default (0) takes grouped launches."""
+    p16 = bzq.Plan(16, 8.0, 4.0, 0.0, 0.5, 8, 14, precision="fp32")
+    p24 = bzq.Plan(24, 8.0, 4.0, -1.0, 0.25, 6, 14, precision="fp32")
+    fd = [_dev(_f(16, 8.0, 1)), _dev(_f(24, 8.0, 2))]
+    with pytest.raises(bzq.BzqError) as e:
+        bzq.Batch([p16, p24], fd, cells_per_launch=-1)
+    assert e.value.code == 4
+    b = bzq.Batch([p16, p24], fd, cells_per_launch=1)
+    assert b.rounds() == 0 and len(b.groups()) == 2
+    b.destroy()
+
+
+@pytest.mark.skip(reason="mixed-size launches are switched off: their first device run ended in a GPU memory "
+                         "fault whose cause is not known (a CPU build of the kernel bodies finds every access "
+                         "in bounds and every result bitwise equal)")
+@pytest.mark.parametrize("budget_mb", [8192, 48])
+def test_mixed_size_launches_bitwise_equal_solo(bzq, budget_mb, monkeypatch):
+    """Cells of N = 16, 24 and 32 (FP32 bulk, different gammas and s) in the
+    mixed-size launches: one launch per pipeline stage over a device table of
+    work items of every size, in one round (8 GB of workspace) or in several
+    (48 MB).  Q of every cell, and two Heun steps (eager and graph-replayed),
+    equal the single-cell path bit for bit."""
+    import torch
+    monkeypatch.setenv("BZQ_BATCH_WS_MB", str(budget_mb))
+    p16 = bzq.Plan(16, 8.0, 4.0, 0.0, 0.5, 8, 14, precision="fp32")
+    p24 = bzq.Plan(24, 8.0, 4.0, -1.0, 0.25, 6, 14, precision="fp32")
+    p32 = bzq.Plan(32, 8.0, 4.0, 0.0, 0.75, 4, 14, precision="fp32")
+    plans = [p16, p24, p32, p16, p16, p24, p32, p16, p24]
+    fs = [_f(p.N, 8.0, 300 + i) for i, p in enumerate(plans)]
+    solo_q = [_host(p.collision(_dev(f))) for p, f in zip(plans, fs)]
+    fd = [_dev(f) for f in fs]
+    batch = bzq.Batch(plans, fd, cells_per_launch=-1)
+    rounds = batch.rounds()
+    assert rounds >= 1 and (rounds > 1) == (budget_mb < 100), rounds
+    outs = [torch.empty_like(f) for f in fd]
+    batch.collision(outs)
+    for a, b in zip(solo_q, outs):
+        assert np.array_equal(a, _host(b))
+    # two Heun steps: solo, batched eager, batched graph
+    ref = [_dev(f) for f in fs]
+    for p, r in zip(plans, ref):
+        p.step(r, 0.01, 2)
+    batch.step(0.01, 2, use_graph=False)
+    for a, b in zip(ref, fd):
+        assert np.array_equal(_host(a), _host(b))
+    fg = [_dev(f) for f in fs]
+    bg = bzq.Batch(plans, fg, cells_per_launch=-1)
+    for rep in range(2):
+        bg.step(0.01, 1, use_graph=True)
+        torch.cuda.synchronize()
+    for a, b in zip(ref, fg):
+        assert np.array_equal(_host(a), _host(b))
+    batch.destroy()
+    bg.destroy()
+    # a plan the mixed launches do not take is refused when they are demanded
+    p8 = bzq.Plan(8, 8.0, 4.0, 0.0, 0.5, 4, 14, precision="fp32")
+    with pytest.raises(bzq.BzqError):
+        bzq.Batch([p16, p8], [_dev(_f(16, 8.0, 1)), _dev(_f(8, 8.0, 2))], cells_per_launch=-1)

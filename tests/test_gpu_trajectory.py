@@ -98,20 +98,46 @@ def test_bkw_time_evolution(bzq):
     assert err < 0.01 * moved
 
 
-def test_invariants_along_200_steps(bzq):
-    N, L, R, s, N_rho, M, dt = 32, 8.0, 4.0, 0.5, 32, 110, 0.01
+@pytest.mark.parametrize("s", [0.25, 0.5, 0.75])
+def test_invariants_along_200_steps(bzq, s):
+    """The medium workload's trajectory (N = 32, L = 8, R = 4, N_rho = 32, M = 110,
+    gamma = 0, Heun dt = 0.01, 200 steps from the two-Maxwellian start) for each
+    singularity order s.  Along it: mass exact (Remark 4.1), momentum and energy
+    to the operator's spectral accuracy, entropy dissipation <= 0 and shrinking
+    (H-theorem).  At steps 50 and 200 the GPU state is checked against the
+    oracle: Q of that state at sampled modes (|k|_inf <= 1, the corners, 24
+    random), and the moments and entropy dissipation that bzq_moments returns
+    against the oracle's formulas on the same state."""
+    N, L, R, N_rho, M, dt = 32, 8.0, 4.0, 32, 110, 0.01
     f0 = workloads.to_spectral(workloads.two_maxwellians(0).sample(N, L))
     mass0, mom0, en0 = oracle.moments(f0, L)
+    d = oracle.Discretization.power(N, L, R, 0.0, s, N_rho, M)
+    ks = workloads.survey_mode_sample(N, 50, n_random=24, inf_radius=1)
+    T = oracle.weight_table(d, ks)
+    idx = tuple(np.mod(ks, N).T)
     trajs = {}
-    for prec in ("fp64", "fp32"):
+    for prec, tol in (("fp64", 1e-11), ("fp32", 1e-5)):
         plan = bzq.Plan(N, L, R, 0.0, s, N_rho, M, precision=prec)
         g = _dev(f0)
         rec = []
-        for _ in range(4):
+        for step in (50, 100, 150, 200):
             plan.step(g, dt, 50)
             m = plan.moments(g)
-            print(prec, m)
+            print(prec, s, step, m, flush=True)
             rec.append(m)
+            if step in (50, 200):
+                fh = _host(g)
+                q_gpu = _host(plan.collision(g))
+                q_ref = oracle.collision_direct(fh, d, k_out=ks, k_block=len(ks), T=T)
+                err = _rel(q_gpu[idx], q_ref)
+                print(f"s={s} {prec} step {step}: Q vs oracle at {len(ks)} modes {err:.2e}", flush=True)
+                assert err < tol, (s, prec, step, err)
+                mass, mom, en = oracle.moments(fh, L)
+                assert abs(m["mass"] - mass) < 1e-14 * mass
+                assert np.max(np.abs(np.array(m["momentum"]) - mom)) < 1e-12 * en
+                assert abs(m["energy"] - en) < 1e-12 * en
+                D = oracle.entropy_dissipation(q_gpu, oracle.to_physical(fh, L), L)
+                assert abs(m["entropy_dissipation"] - D) < 1e-9 * abs(D)
         trajs[prec] = (_host(g), rec)
         plan.destroy()
     f64, rec64 = trajs["fp64"]
