@@ -88,7 +88,9 @@ typedef enum {
  * rule in |q| and the sphere rule of eq. approxG, the weight F of eq. FF
  * precomputed as in Section 4.1) with the angular kernel `kernel`
  * (BZQ_KERNEL_POWER or BZQ_KERNEL_CUTOFF_CONST; `s` is ignored for the latter).
- *   N      grid size per axis; one of 8, 16, 24, 32, 48, 64 (EUNSUPPORTED else)
+ *   N      grid size per axis; one of 8, 16, 24, 32, 48, 64, 128 (EUNSUPPORTED
+ *          else; at 128 the plane stage runs in three passes through a row
+ *          buffer, since a padded plane of 192^2 values does not fit LDS)
  *   L      half-width of the periodic box D_L (> 0)
  *   R      radius of the ball B_R that truncates |q| (> 0)
  *   gamma  exponent of Phi(|q|) = |q|^gamma, -3 < gamma <= 1 (eq. Bb)
@@ -135,7 +137,7 @@ bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, doubl
  *   Re(e^{-ix} F) = sum_{l even} (2l+1) (-1)^{l/2} mu_l j_l(a|k|) P_l(k.sigma/|k|),
  *   mu_l = 2 pi \int b(u) (P_l(u) - 1) du  (finite for every s < 1),
  * truncated at l <= r + 8 r^{1/3} + 12, r = a|k| (below 1e-13 of the sum; at
- * most 64 even terms, r <= ~80).  The plan then holds N_rho x (terms rounded
+ * most 80 even terms, r <= ~100).  The plan then holds N_rho x (terms rounded
  * up to 8) x (3 (N/2-1)^2 + 1) coefficients (71 MB at N = 64, N_rho = 64)
  * instead of the weight table (4.8 GB FP32, 9.7 GB FP64 at N = 64, M = 302),
  * and its workspace one block of weights.  `kernel` selects the angular kernel
@@ -145,7 +147,7 @@ bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, doubl
  * (there is no n_jacobi: the series moments use their own exact Gauss-Jacobi
  * rule).  Every other call accepts the plan unchanged.
  * BZQ_EUNSUPPORTED, before any device work, if the series would need more
- * than 64 terms. */
+ * than 80 terms. */
 bzq_status bzq_plan_create_otf(bzq_plan* out, int N, double L, double R, double gamma, int kernel,
                                double b_c, double b_s, double b_r, int N_rho, int M, int precision,
                                void* stream);

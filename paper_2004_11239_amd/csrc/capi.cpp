@@ -42,7 +42,7 @@ thread_local std::string g_last_error;
 const long double kPi = 3.141592653589793238462643383279502884L;
 constexpr int kMomentBlocks = 256;
 
-bool supported_N(int N) { return N == 8 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64; }
+bool supported_N(int N) { return N == 8 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64 || N == 128; }
 }  // namespace
 
 bzq_status fail(bzq_status s, const std::string& msg) {
@@ -75,7 +75,8 @@ Plan::~Plan() {
 size_t Plan::workspace_bytes_per_cell() const {
   const size_t N3 = (size_t)N * N * N;
   return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * nn * 2 * esz +
-         (size_t)G * P * 2 * nhp * 2 * esz + (size_t)S_cap * nh * n1 * 16 + 3 * N3 * 16 +
+         (size_t)G * P * 2 * nhp * 2 * esz + plane_rows_elems(*this, G) * 2 * esz + (size_t)S_cap * nh * n1 * 16 +
+         3 * N3 * 16 +
          (otf ? (size_t)2 * Gw * nh * n1 * esz : 0) + 4 * sizeof(int);
 }
 
@@ -89,6 +90,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   w.cs.a = (size_t)p.G * p.P * p.nn;
   w.cs.b = (size_t)p.G * p.P * 2 * p.nhp;
   w.cs.qp = (size_t)p.S_cap * p.nh * p.n1;
+  w.cs.pc = plane_rows_elems(p, p.G);
   w.cs.cells = cells;
   const size_t N3 = (size_t)p.N * p.N * p.N;
   bzq_status s;
@@ -96,6 +98,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   if ((s = w.arena.get(&w.fgrid, cells * w.cs.fg * p.esz)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.A, cells * w.cs.a * 2 * p.esz)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.B, cells * w.cs.b * 2 * p.esz)) != BZQ_OK) return s;
+  if (w.cs.pc && (s = w.arena.get(&w.C, cells * w.cs.pc * 2 * p.esz)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.Qpart, cells * w.cs.qp * 16)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.q1, cells * N3 * 16)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.q2, cells * N3 * 16)) != BZQ_OK) return s;
@@ -153,7 +156,7 @@ constexpr int kSTargets[3] = {512, 1024, 2048};
 // 1071).  S never exceeds its value without the rounding.
 int zfwd_splits_for(const Plan& p, int G, int zv, int s_target) {
   const bool pipe = zv == 2 && (p.P == 48 || p.P == 72 || p.P == 96);
-  const bool reg_zfwd = p.fp32 ? true : (p.P <= 48);
+  const bool reg_zfwd = p.fp32 ? p.P <= 96 : p.P <= 48;
   const int tq = pipe ? 32 : reg_zfwd ? (p.fp32 ? 32 : 16) : 8;
   const int pt_group = pipe ? 1 : reg_zfwd ? (p.fp32 ? 2 : 4) : 1;
   const int groups = (G + pt_group - 1) / pt_group;
@@ -171,7 +174,7 @@ int zfwd_splits(const Plan& p, int zv, int s_target) { return zfwd_splits_for(p,
 void set_chunking(Plan& p) {
   p.esz = p.fp32 ? 4 : 8;
   p.nhp = (p.nh + 15) / 16 * 16;
-  const size_t per_pt = (size_t)p.P * (p.nn + 2 * p.nhp) * 2 * p.esz;
+  const size_t per_pt = ((size_t)p.P * (p.nn + 2 * p.nhp) + plane_rows_elems(p, 1)) * 2 * p.esz;
   const char* env = std::getenv("BZQ_CHUNK_MB");
   const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
   p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
@@ -205,7 +208,8 @@ size_t plan_footprint(int N, int N_rho, int M, int precision) {
   set_chunking(p);
   const size_t n3 = (size_t)N * N * N;
   const size_t tables = plan_shared_bytes_estimate(N, N_rho, M, precision) + (size_t)p.npairs * 8;
-  const size_t grid = (size_t)p.n1 * p.nn * 16 + (size_t)N * p.nn * 16 + 2 * n3 * 8 + 256 * 8 * 8 + 16;
+  const size_t grid = (size_t)p.n1 * p.nn * 16 + (size_t)N * p.nn * 16 + 2 * n3 * 8 + 256 * 8 * 8 + 16 +
+                      (needs_plane_rows(N) ? (size_t)N * p.n1 * N * 16 : 0);
   return tables + p.workspace_bytes_per_cell() + grid;
 }
 
@@ -284,8 +288,8 @@ bzq_status build_series(Plan* p, const std::vector<double>& rho, int Mh, int nre
     terms[ip] = fh_lmax(a * std::sqrt((double)(p->ncoef - 1))) / 2 + 1;
     need = std::max(need, terms[ip]);
   }
-  if (need > 64)
-    return fail(BZQ_EUNSUPPORTED, "weights on the fly: a |k| too large for the series (at most 64 even terms)");
+  if (need > 80)
+    return fail(BZQ_EUNSUPPORTED, "weights on the fly: a |k| too large for the series (at most 80 even terms)");
   p->mt = (need + 7) / 8 * 8;   // coefficient slots: the kernel unrolls in multiples of 8 terms
   std::vector<long double> mu, Ml;
   if (!fh_moments(2 * (need - 1), p->bc, p->bs, p->br, mu)) return fail(BZQ_EINVAL, "Gauss-Jacobi rule failed");
@@ -342,6 +346,9 @@ bzq_status alloc_scratch(Plan* p) {
   const size_t n3 = (size_t)N * N * N;
   if ((s = p->grid_scratch.get(&p->gfc, (size_t)p->n1 * nn * 2 * sizeof(double))) != BZQ_OK) return s;
   if ((s = p->grid_scratch.get(&p->gA, (size_t)N * nn * 2 * sizeof(double))) != BZQ_OK) return s;
+  if (needs_plane_rows(N) &&
+      (s = p->grid_scratch.get(&p->gC, (size_t)N * p->n1 * N * 2 * sizeof(double))) != BZQ_OK)
+    return s;
   if ((s = p->grid_scratch.get(&p->gf, n3 * sizeof(double))) != BZQ_OK) return s;
   if ((s = p->grid_scratch.get(&p->gq, n3 * sizeof(double))) != BZQ_OK) return s;
   if ((s = p->grid_scratch.get(&p->part, (size_t)kMomentBlocks * 8 * sizeof(double))) != BZQ_OK) return s;
@@ -514,7 +521,7 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
   }
   if (!zinv_ingest_fits(p.P, p.fp32))
     TIMED(ST_PREP, launch_zinv(w.fc, nullptr, w.A, p.tw_pad, g, 0, 1, ZINV_PLAIN, p.fp32, cs, st));
-  TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st));
+  TIMED(ST_PREP, launch_plane(w.A, nullptr, nullptr, w.fgrid, p.tw_pad, g, 1, PLANE_TO_GRID, p.fp32, cs, st, 0, w.C));
   // the first last-stage launch writes the S partial accumulators of every
   // cell, later ones add to them
   // the chunk geometry: the plan's, or the workspace's own for scratch of
@@ -524,7 +531,7 @@ bzq_status enqueue_collision(Plan& p, Workspace& w, const PtrPack& f, const PtrP
     const int n = std::min(G, p.npt - c0);
     TIMED(ST_ZINV, launch_zinv(w.fc, p.ph, w.A, p.tw_pad, g, 2 * c0, n, ZINV_PAIRS, p.fp32, cs, st, p.var[0]));
     TIMED(ST_PLANE, launch_plane(w.A, w.B, w.fgrid, nullptr, p.tw_pad, g, n, PLANE_PRODUCT, p.fp32, cs, st,
-                                 p.var[1]));
+                                 p.var[1], w.C));
     if (p.otf) {
       // weights of Gw pair-twos at a time, then the last stage over those pair-twos
       for (int w0 = 0; w0 < n; w0 += Gw) {
@@ -621,7 +628,7 @@ bzq_status create_plan(bzq_plan* out, int N, double L, double R, double gamma, d
   if (precision != BZQ_FP64 && precision != BZQ_FP32_ACC64) return fail(BZQ_EINVAL, "unknown precision");
   std::vector<double> tmp;
   if (!lebedev_rule(M, tmp)) return fail(BZQ_EINVAL, "M is not the size of an available Lebedev rule");
-  if (!supported_N(N)) return fail(BZQ_EUNSUPPORTED, "no FFT schedule for this N (supported: 8 16 24 32 48 64)");
+  if (!supported_N(N)) return fail(BZQ_EUNSUPPORTED, "no FFT schedule for this N (supported: 8 16 24 32 48 64 128)");
   bzq_plan_s* p = new bzq_plan_s();
   p->N = N;
   p->P = 3 * N / 2;
@@ -685,7 +692,8 @@ bzq_status enqueue_to_grid(Plan& p, const double* f_hat, double* dst, hipStream_
   cs.cells = 1;
   BZQ_HIP_TRY(launch_ingest(single(f_hat), p.gfc, 0, 1, p.N, false, st));
   BZQ_HIP_TRY(launch_zinv(p.gfc, nullptr, p.gA, p.tw_grid, g, 0, 1, ZINV_GRID_SIGN, false, cs, st));
-  BZQ_HIP_TRY(launch_plane(p.gA, nullptr, nullptr, dst, p.tw_grid, g, 1, PLANE_TO_GRID, false, cs, st));
+  cs.pc = (size_t)p.N * p.n1 * p.N;
+  BZQ_HIP_TRY(launch_plane(p.gA, nullptr, nullptr, dst, p.tw_grid, g, 1, PLANE_TO_GRID, false, cs, st, 0, p.gC));
   return BZQ_OK;
 }
 
@@ -760,15 +768,16 @@ bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat,
   const size_t b_fc = al((size_t)p->n1 * p->nn * 2 * esz), b_fg = al((size_t)p->P * p->P * p->P * esz);
   const int zv = effective_variant(*p, 2);
   int G = p->G, S = 0, Gw = 0;
-  size_t b_a = 0, b_b = 0, b_q = 0, b_w = 0;
+  size_t b_a = 0, b_b = 0, b_c = 0, b_q = 0, b_w = 0;
   auto need = [&](int g) {
     S = zfwd_splits_for(*p, g, zv, p->s_target);
     Gw = p->otf ? std::min(p->Gw, g) : 0;
     b_a = al((size_t)g * p->P * p->nn * 2 * esz);
     b_b = al((size_t)g * p->P * 2 * p->nhp * 2 * esz);
+    b_c = al(plane_rows_elems(*p, g) * 2 * esz);
     b_q = al((size_t)S * p->nh * p->n1 * 16);
     b_w = al((size_t)2 * Gw * p->nh * p->n1 * esz);
-    return b_fc + b_fg + b_a + b_b + b_q + b_w;
+    return b_fc + b_fg + b_a + b_b + b_c + b_q + b_w;
   };
   while (G > 1 && need(G) > kNoAllocScratchBytes) --G;
   if (need(G) > kNoAllocScratchBytes)
@@ -790,6 +799,7 @@ bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat,
   w.fgrid = at; at += b_fg;
   w.A = at; at += b_a;
   w.B = at; at += b_b;
+  w.C = b_c ? at : nullptr; at += b_c;
   w.Qpart = (double*)at; at += b_q;
   w.Vc = p->otf ? at : nullptr;
   w.cs.fc = (size_t)p->n1 * p->nn;
@@ -797,6 +807,7 @@ bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat,
   w.cs.a = (size_t)G * p->P * p->nn;
   w.cs.b = (size_t)G * p->P * 2 * p->nhp;
   w.cs.qp = (size_t)S * p->nh * p->n1;
+  w.cs.pc = plane_rows_elems(*p, G);
   w.cs.cells = 1;
   return enqueue_collision(*p, w, single(f_hat), single(Q_hat), 1, (hipStream_t)stream);
 }

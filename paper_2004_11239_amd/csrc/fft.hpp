@@ -136,16 +136,19 @@ __host__ __device__ __forceinline__ void dft(cx<T>* v) {
 // ------------------------------------------------------------- radix plans
 template <int P>
 struct RadixPlan;
-template <> struct RadixPlan<8>  { static constexpr int R0 = 8, R1 = 1; };
-template <> struct RadixPlan<12> { static constexpr int R0 = 12, R1 = 1; };
-template <> struct RadixPlan<16> { static constexpr int R0 = 4, R1 = 4; };
-template <> struct RadixPlan<24> { static constexpr int R0 = 4, R1 = 6; };
-template <> struct RadixPlan<32> { static constexpr int R0 = 4, R1 = 8; };
-template <> struct RadixPlan<36> { static constexpr int R0 = 6, R1 = 6; };
-template <> struct RadixPlan<48> { static constexpr int R0 = 4, R1 = 12; };
-template <> struct RadixPlan<64> { static constexpr int R0 = 8, R1 = 8; };
-template <> struct RadixPlan<72> { static constexpr int R0 = 6, R1 = 12; };
-template <> struct RadixPlan<96> { static constexpr int R0 = 8, R1 = 12; };
+template <> struct RadixPlan<8>  { static constexpr int R0 = 8, R1 = 1, R2 = 1; };
+template <> struct RadixPlan<12> { static constexpr int R0 = 12, R1 = 1, R2 = 1; };
+template <> struct RadixPlan<16> { static constexpr int R0 = 4, R1 = 4, R2 = 1; };
+template <> struct RadixPlan<24> { static constexpr int R0 = 4, R1 = 6, R2 = 1; };
+template <> struct RadixPlan<32> { static constexpr int R0 = 4, R1 = 8, R2 = 1; };
+template <> struct RadixPlan<36> { static constexpr int R0 = 6, R1 = 6, R2 = 1; };
+template <> struct RadixPlan<48> { static constexpr int R0 = 4, R1 = 12, R2 = 1; };
+template <> struct RadixPlan<64> { static constexpr int R0 = 8, R1 = 8, R2 = 1; };
+template <> struct RadixPlan<72> { static constexpr int R0 = 6, R1 = 12, R2 = 1; };
+template <> struct RadixPlan<96> { static constexpr int R0 = 8, R1 = 12, R2 = 1; };
+// three passes (LDS kernels only: these pencils do not fit the register file)
+template <> struct RadixPlan<128> { static constexpr int R0 = 8, R1 = 4, R2 = 4; };
+template <> struct RadixPlan<192> { static constexpr int R0 = 8, R1 = 4, R2 = 6; };
 
 // ------------------------------------------------------ Stockham LDS passes
 // One radix-R pass over `npencils` pencils of length P stored in LDS.
@@ -208,9 +211,13 @@ __device__ __forceinline__ void fft_pencils(cx<T>* __restrict__ buf, int npencil
                                             const cx<T>* __restrict__ tw) {
   constexpr int R0 = RadixPlan<P>::R0;
   constexpr int R1 = RadixPlan<P>::R1;
+  constexpr int R2 = RadixPlan<P>::R2;
+  static_assert(R0 * R1 * R2 == P, "radix plan");
   stockham_pass<T, P, R0, 1, SIGN, Bmax<MAXP, P, R0, NT>::value, NT>(buf, npencils, addr, es, tw);
   if constexpr (R1 > 1)
     stockham_pass<T, P, R1, R0, SIGN, Bmax<MAXP, P, R1, NT>::value, NT>(buf, npencils, addr, es, tw);
+  if constexpr (R2 > 1)
+    stockham_pass<T, P, R2, R0 * R1, SIGN, Bmax<MAXP, P, R2, NT>::value, NT>(buf, npencils, addr, es, tw);
 }
 
 // ------------------------------------------------- compile-time twiddles
@@ -295,6 +302,7 @@ template <int P, int SIGN, typename T>
 __host__ __device__ __forceinline__ void fft_reg(cx<T>* x) {
   constexpr int R0 = RadixPlan<P>::R0;
   constexpr int R1 = RadixPlan<P>::R1;
+  static_assert(RadixPlan<P>::R2 == 1, "register transforms take two-factor lengths");
   if constexpr (R1 == 1) {
     dft<R0, SIGN>(x);
   } else {

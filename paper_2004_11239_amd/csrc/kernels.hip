@@ -361,6 +361,153 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
 }
 
 
+// ------------------------------------------------- plane in three passes
+// At P = 128 and 192 a whole plane (P (P+1) complex values) does not fit LDS,
+// so the plane stage of one (pair-two, z) plane runs in three launches through
+// the row buffer C[pt][z][i1][y] (the N-1 mode rows i1, P values each):
+//   rows:    inverse along axis 2 of the N-1 rows of A            -> C
+//   columns: inverse along axis 1, product with f (or the real grid
+//            out), forward along axis 1 keeping the N-1 modes      -> C in place
+//   rows:    forward along axis 2 keeping the N-1 modes           -> B
+// Each pass is the same arithmetic as the one-workgroup plane kernels, in LDS
+// Stockham passes over a block of rows or columns.
+template <typename T>
+struct SplitCfg {
+  static constexpr int RB = 16;                        // rows per workgroup
+  static constexpr int CB = sizeof(T) == 4 ? 32 : 16;  // columns per workgroup
+  static constexpr int NT = 256;
+};
+
+template <typename T, int P>
+__global__ __launch_bounds__(SplitCfg<T>::NT) void k_prow_inv(const cx<T>* __restrict__ A, cx<T>* __restrict__ C,
+                                                             const cx<T>* __restrict__ twg, int N, CellStrides cs) {
+  constexpr int LD = P + 1, RB = SplitCfg<T>::RB, NT = SplitCfg<T>::NT;
+  __shared__ cx<T> buf[RB * LD];
+  __shared__ cx<T> tw[P];
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1;
+  const int nrb = (n1 + RB - 1) / RB;
+  const int z = blockIdx.x / nrb, r0 = (blockIdx.x - z * nrb) * RB;
+  const int nr = min(RB, n1 - r0);
+  const int pt = blockIdx.y;
+  A += blockIdx.z * cs.a;
+  C += blockIdx.z * cs.pc;
+  for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < RB * LD; i += NT) buf[i] = cx<T>{0, 0};
+  __syncthreads();
+  // row i1 = r0 + r holds A[i2 n1 + i1] at position posK(i2)
+  const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + r0;
+  for (int e = threadIdx.x; e < nr * n1; e += NT) {
+    const int i2 = e / nr, r = e - i2 * nr;
+    buf[r * LD + posK(i2, h, P)] = Ain[(size_t)i2 * n1 + r];
+  }
+  __syncthreads();
+  fft_pencils<T, P, +1, NT, RB>(buf, nr, RowAddr{LD}, 1, tw);
+  cx<T>* Cout = C + (((size_t)pt * P + z) * n1 + r0) * P;
+  for (int e = threadIdx.x; e < nr * P; e += NT) {
+    const int r = e / P, y = e - r * P;
+    Cout[(size_t)r * P + y] = buf[r * LD + y];
+  }
+}
+
+template <typename T, int P, int MODE>
+__global__ __launch_bounds__(SplitCfg<T>::NT) void k_pcol(cx<T>* __restrict__ C, const T* __restrict__ fgrid,
+                                                         T* __restrict__ gridout, const cx<T>* __restrict__ twg, int N,
+                                                         CellStrides cs) {
+  constexpr int LD = P + 1, CB = SplitCfg<T>::CB, NT = SplitCfg<T>::NT;
+  static_assert(P % CB == 0, "column blocks");
+  __shared__ cx<T> buf[CB * LD];
+  __shared__ cx<T> tw[P];
+  const int n1 = N - 1, h = N / 2;
+  constexpr int ncb = P / CB;
+  const int z = blockIdx.x / ncb, y0 = (blockIdx.x - z * ncb) * CB;
+  const int pt = blockIdx.y;
+  C += blockIdx.z * cs.pc;
+  for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < CB * LD; i += NT) buf[i] = cx<T>{0, 0};
+  __syncthreads();
+  // column y0 + q holds the N-1 rows' values at positions posK(i1)
+  cx<T>* Cz = C + ((size_t)pt * P + z) * n1 * P + y0;
+  for (int e = threadIdx.x; e < n1 * CB; e += NT) {
+    const int i1 = e / CB, q = e - i1 * CB;
+    buf[q * LD + posK(i1, h, P)] = Cz[(size_t)i1 * P + q];
+  }
+  __syncthreads();
+  fft_pencils<T, P, +1, NT, CB>(buf, CB, RowAddr{LD}, 1, tw);
+  if constexpr (MODE == PLANE_TO_GRID) {
+    T* out = gridout + blockIdx.z * cs.fg + (size_t)z * P * P + y0;
+    for (int e = threadIdx.x; e < P * CB; e += NT) {
+      const int x = e / CB, q = e - x * CB;
+      out[(size_t)x * P + q] = buf[q * LD + x].x;
+    }
+  } else {
+    const T* fz = fgrid + blockIdx.z * cs.fg + (size_t)z * P * P + y0;
+    for (int e = threadIdx.x; e < P * CB; e += NT) {
+      const int x = e / CB, q = e - x * CB;
+      buf[q * LD + x] = cscale(buf[q * LD + x], fz[(size_t)x * P + q]);
+    }
+    __syncthreads();
+    fft_pencils<T, P, -1, NT, CB>(buf, CB, RowAddr{LD}, 1, tw);
+    for (int e = threadIdx.x; e < n1 * CB; e += NT) {
+      const int k1 = e / CB, q = e - k1 * CB;
+      Cz[(size_t)k1 * P + q] = buf[q * LD + posK(k1, h, P)];
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(SplitCfg<T>::NT) void k_prow_fwd(const cx<T>* __restrict__ C, cx<T>* __restrict__ B,
+                                                             const cx<T>* __restrict__ twg, int N, CellStrides cs) {
+  constexpr int LD = P + 1, RB = SplitCfg<T>::RB, NT = SplitCfg<T>::NT;
+  __shared__ cx<T> buf[RB * LD];
+  __shared__ cx<T> tw[P];
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1;
+  const int nrb = (n1 + RB - 1) / RB;
+  const int z = blockIdx.x / nrb, r0 = (blockIdx.x - z * nrb) * RB;
+  const int nr = min(RB, n1 - r0);
+  const int pt = blockIdx.y;
+  C += blockIdx.z * cs.pc;
+  B += blockIdx.z * cs.b;
+  for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
+  const cx<T>* Cin = C + (((size_t)pt * P + z) * n1 + r0) * P;
+  for (int e = threadIdx.x; e < nr * P; e += NT) {
+    const int r = e / P, y = e - r * P;
+    buf[r * LD + y] = Cin[(size_t)r * P + y];
+  }
+  __syncthreads();
+  fft_pencils<T, P, -1, NT, RB>(buf, nr, RowAddr{LD}, 1, tw);
+  // row k1 = r0 + r gives the modes c = k2 n1 + k1 of the folded B layout
+  const int nhp = nh_pad(N), cmid = (nn - 1) / 2;
+  cx<T>* Bout = B + ((size_t)pt * P + z) * 2 * nhp;
+  for (int e = threadIdx.x; e < nr * n1; e += NT) {
+    const int k2 = e / nr, r = e - k2 * nr;
+    const int c = k2 * n1 + r0 + r;
+    const cx<T> w = buf[r * LD + posK(k2, h, P)];
+    Bout[fold_slot(c, nn, nhp)] = w;
+    if (c == cmid) Bout[nhp + cmid] = w;
+  }
+}
+
+template <typename T, int P>
+hipError_t plane_rows_t(const void* A, void* B, const void* fgrid, void* gridout, void* C, const void* tw, int N,
+                        int npt, int mode, const CellStrides& cs, hipStream_t st) {
+  if (!C || N < 2 || N - 1 > P) return hipErrorInvalidValue;
+  using S = SplitCfg<T>;
+  const int n1 = N - 1, nrb = (n1 + S::RB - 1) / S::RB;
+  const dim3 grow(nrb * P, npt, cs.cells), gcol((P / S::CB) * P, npt, cs.cells);
+  hipLaunchKernelGGL((k_prow_inv<T, P>), grow, dim3(S::NT), 0, st, (const cx<T>*)A, (cx<T>*)C, (const cx<T>*)tw, N,
+                     cs);
+  if (mode == PLANE_TO_GRID) {
+    hipLaunchKernelGGL((k_pcol<T, P, PLANE_TO_GRID>), gcol, dim3(S::NT), 0, st, (cx<T>*)C, (const T*)nullptr,
+                       (T*)gridout, (const cx<T>*)tw, N, cs);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_pcol<T, P, PLANE_PRODUCT>), gcol, dim3(S::NT), 0, st, (cx<T>*)C, (const T*)fgrid,
+                     (T*)nullptr, (const cx<T>*)tw, N, cs);
+  hipLaunchKernelGGL((k_prow_fwd<T, P>), grow, dim3(S::NT), 0, st, (const cx<T>*)C, (cx<T>*)B, (const cx<T>*)tw, N,
+                     cs);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------- register-FFT kernels
 // A pencil fits the register file when it has at most 96 FP32 or 48 FP64
 // complex values; larger pencils use the LDS kernels above.
@@ -1945,7 +2092,9 @@ __global__ __launch_bounds__(256) void k_wgen(T* __restrict__ Vc, const double* 
       case 5: wgen_run<T, PB, 40>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
       case 6: wgen_run<T, PB, 48>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
       case 7: wgen_run<T, PB, 56>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
-      default: wgen_run<T, PB, 64>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 8: wgen_run<T, PB, 64>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      case 9: wgen_run<T, PB, 72>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
+      default: wgen_run<T, PB, 80>(Vc, cq, pdv, j, jend, j0, per, e, k1, k2, k3, rinv); break;
     }
     j = jend;
   }
@@ -2215,6 +2364,9 @@ int zfwd_blocks_t(int variant) {
 
 #define BZQ_ALL_P(X) X(8) X(12) X(16) X(24) X(32) X(36) X(48) X(64) X(72) X(96)
 #define BZQ_PAD_P(X) X(12) X(24) X(36) X(48) X(72) X(96)
+// lengths whose plane takes the three-pass kernels (P = 192 for N = 128, and
+// the unpadded physical grid P = N = 128)
+#define BZQ_BIG_P(X) X(128) X(192)
 
 }  // namespace
 
@@ -2475,19 +2627,27 @@ hipError_t launch_zinv(const void* fc, const double* ph, void* A, const void* tw
   case PP:                                                                                       \
     return fp32 ? zinv_t<float, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, variant, cs, st)      \
                 : zinv_t<double, PP>(fc, ph, A, tw, g.N, pair0, npt, mode, variant, cs, st);
-  switch (g.P) { BZQ_ALL_P(CASE) }
+  switch (g.P) { BZQ_ALL_P(CASE) BZQ_BIG_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
 }
 
+bool needs_plane_rows(int P) { return P == 128 || P == 192; }
+
 hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
                         Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st,
-                        int variant) {
+                        int variant, void* C) {
 #define CASE(PP)                                                                                   \
   case PP:                                                                                         \
     return fp32 ? plane_t<float, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, variant, cs, st)   \
                 : plane_t<double, PP>(A, B, fgrid, gridout, tw, g.N, npt, mode, variant, cs, st);
   switch (g.P) { BZQ_ALL_P(CASE) }
+#undef CASE
+#define CASE(PP)                                                                                           \
+  case PP:                                                                                                 \
+    return fp32 ? plane_rows_t<float, PP>(A, B, fgrid, gridout, C, tw, g.N, npt, mode, cs, st)            \
+                : plane_rows_t<double, PP>(A, B, fgrid, gridout, C, tw, g.N, npt, mode, cs, st);
+  switch (g.P) { BZQ_BIG_P(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
 }
@@ -2499,7 +2659,7 @@ hipError_t launch_zfwd(const void* B, const void* V, const double* ph, const dou
   case PP:                                                                                            \
     return fp32 ? zfwd_t<float, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, first, variant, cs, st) \
                 : zfwd_t<double, PP>(B, V, ph, cp, Qpart, tw, g.N, pair0, vpair0, npt, S, first, variant, cs, st);
-  switch (g.P) { BZQ_PAD_P(CASE) }
+  switch (g.P) { BZQ_PAD_P(CASE) CASE(192) }
 #undef CASE
   return hipErrorInvalidValue;
 }
@@ -2561,7 +2721,7 @@ hipError_t launch_table(void* V, const double* pd, const double* gj, int nj, int
 
 hipError_t launch_wgen(void* Vc, const double* coef, const double* pdv, const int* terms, int mt, int N, int Mh,
                        int nreal, int j0, int nj, int ncoef, bool fp32, hipStream_t st) {
-  if (mt < 8 || mt > 64 || (mt & 7)) return hipErrorInvalidValue;
+  if (mt < 8 || mt > 80 || (mt & 7)) return hipErrorInvalidValue;
   const int n1 = N - 1, per = ((n1 * n1 + 1) / 2) * n1;
   const int bx = (per + 255) / 256;
   // about 2048 workgroups, each over at least 16 pairs

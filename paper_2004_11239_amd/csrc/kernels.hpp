@@ -23,6 +23,7 @@ struct CellStrides {
   size_t a;    // first intermediate
   size_t b;    // second intermediate
   size_t qp;   // partial accumulators (complex128)
+  size_t pc;   // plane rows between the passes of the three-pass plane (P = 128, 192)
   int cells;
 };
 
@@ -61,10 +62,14 @@ hipError_t launch_zinv(const void* fc, const double* phase, void* A, const void*
 
 // Step 2: per (pt, z) plane: inverse along axes 2 and 1, product with the
 // physical f (mode PLANE_PRODUCT) or output of the real grid (PLANE_TO_GRID),
-// forward along axes 1 and 2.
+// forward along axes 1 and 2.  At P = 128 and 192 a plane does not fit LDS
+// and the stage runs in three passes through C (needs_plane_rows): C holds,
+// per pair-two and z plane, the N-1 mode rows of P values (npt x P x (N-1) x P
+// complex, cell stride cs.pc); elsewhere C is unused.
+bool needs_plane_rows(int P);
 hipError_t launch_plane(const void* A, void* B, const void* fgrid, void* gridout, const void* tw,
                         Geometry g, int npt, int mode, bool fp32, const CellStrides& cs, hipStream_t st,
-                        int variant = 0);
+                        int variant = 0, void* C = nullptr);
 
 // Step 3: forward along axis 3, split the two packed pairs, apply the stored
 // weights and the phase e^{i a k.sigma}, accumulate in FP64 into Qpart[s].
@@ -86,7 +91,7 @@ int zfwd_blocks_per_cu(int P, bool fp32, int variant);
 // Re(e^{-ix} F) = sum_k coef[p][n][k] T_k(2 t^2 - 1), t = k.sigma/|k|, for
 // radial node p and n = |k|^2 < ncoef (k < terms[p], zero above);
 // pdv[j] = {sigma_x, sigma_y, sigma_z, 2 w_sigma / P^3} (0 for the padding
-// pair).  mt (coefficient slots) is a multiple of 8, at most 64, and at
+// pair).  mt (coefficient slots) is a multiple of 8, at most 80, and at
 // least every terms[p] rounded up to a multiple of 8.
 hipError_t launch_wgen(void* Vc, const double* coef, const double* pdv, const int* terms, int mt, int N, int Mh,
                        int nreal, int j0, int nj, int ncoef, bool fp32, hipStream_t st);

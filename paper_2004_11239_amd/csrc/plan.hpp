@@ -55,6 +55,7 @@ struct Workspace {
   void* fgrid = nullptr;     // cells x P^3 real
   void* A = nullptr;         // cells x G x P x nn complex
   void* B = nullptr;         // cells x G x P x 2 nhp complex
+  void* C = nullptr;         // cells x G x P x (N-1) x P complex: plane rows (P = 192 only)
   double* Qpart = nullptr;   // cells x S x nh x n1 complex128
   double* q1 = nullptr;      // cells x N^3 complex128 (Heun stages)
   double* q2 = nullptr;
@@ -91,7 +92,7 @@ struct Plan {
   // weights on the fly: no table V; per chunk, k_wgen evaluates the series
   // of the angular weight (funk_hecke.hpp) into the workspace
   bool otf = false;
-  int mt = 0;                   // coefficient slots per (radial node, |k|^2): multiple of 8, <= 64
+  int mt = 0;                   // coefficient slots per (radial node, |k|^2): multiple of 8, <= 80
   int Gw = 0;                   // pair-twos per block of generated weights
   int Mh = 0;                   // pairs per radial node
   int nreal = 0;                // pairs before the zero-weight pad
@@ -113,6 +114,7 @@ struct Plan {
   Workspace ws;
   double* gfc = nullptr;
   double* gA = nullptr;
+  double* gC = nullptr;   // plane rows of the physical grid (N = 128 only)
   double* gf = nullptr;
   double* gq = nullptr;
   double* part = nullptr;
@@ -128,6 +130,10 @@ struct Plan {
 };
 
 bzq_status workspace_init(Workspace& w, const Plan& p, int cells);
+// elements of the plane-row buffer for G pair-twos (0 where the plane fits LDS)
+inline size_t plane_rows_elems(const Plan& p, int G) {
+  return needs_plane_rows(p.P) ? (size_t)G * p.P * p.n1 * p.P : 0;
+}
 int effective_variant(const Plan& p, int stage);
 // Autotuning cache: "key|value" lines in $BZQ_TUNE_CACHE or ~/.cache/bzq_autotune.txt
 std::map<std::string, int> tune_cache_read();

@@ -49,7 +49,13 @@ BROADBAND = {
     "broadband_N32": (32, 8.0, 4.0, 0.0, 0.50, 32, 110, 7),
     "broadband_N48": (48, 9.0, 4.5, 0.0, 0.75, 16, 110, 8),
     "broadband_N64": (64, 10.0, 5.0, 0.0, 0.50, 64, 302, 9),
+    # N = 128 (P = 192: the three-pass plane and the 72-slot weight series at
+    # the large workload's box, a|k| up to 86) with a small quadrature
+    "broadband_N128": (128, 10.0, 5.0, 0.0, 0.50, 8, 6, 11),
 }
+
+# N = 128 on a smooth random Maxwellian mixture (kind 1), gamma = -1
+CASES["huge_mix_gm1"] = (128, 10.0, 5.0, -1.0, 0.50, 8, 14, 12, 1, 16)
 
 
 # 2-D broadband cases at N = 64: the register pipeline at 16 pair-twos, the
@@ -105,7 +111,10 @@ def make(name):
     d = oracle.Discretization.power(N, L, R, gamma, s, N_rho, M)
     f = input_of(N, L, seed, kind)
     t0 = time.time()
-    q = oracle.collision_direct(f, d, k_out=ks, k_block=len(ks), j_block=64 if N >= 64 else 256)
+    if N >= 128:   # 2 M modes m: bound the [m, k] blocks to about 1 GB
+        q = oracle.collision_direct(f, d, k_out=ks, k_block=16, j_block=16)
+    else:
+        q = oracle.collision_direct(f, d, k_out=ks, k_block=len(ks), j_block=64 if N >= 64 else 256)
     params = np.array([N, L, R, gamma, s, N_rho, M, seed], dtype=np.float64)
     np.savez(os.path.join(HERE, name + ".npz"), modes=ks, Q=q, params=params, kind=np.array(kind))
     print(f"{name}: {len(ks)} modes in {time.time() - t0:.1f} s", flush=True)

@@ -1,0 +1,122 @@
+"""GPU parity at N = 128 (P = 192), the size the weights on the fly are for.
+
+At P = 192 a padded plane (192^2 complex values) does not fit LDS, so the plane
+stage runs in three passes through a row buffer (rows inverse, columns with
+the product, rows forward); the z stages take the LDS Stockham kernels with a
+three-factor radix plan (8 x 4 x 6), and at the large workload's box (L = 10,
+R = 5) the weight series reaches a|k| = 86 (72 coefficient slots).
+
+* Stored oracle samples (tests/golden/make_golden.py) with a small quadrature
+  (N_rho = 8, M = 6 or 14): a broadband spectrum at every |k|_inf <= 2 mode,
+  the corners and 128 random modes, and a smooth random mixture at gamma = -1;
+  table and on-the-fly weights, both precisions, each mode checked against
+  tol * max|Q| beside the relative L2 norm.
+* The physical-grid path at N = 128 (P = N = 128, the same three-pass plane in
+  FP64): moments of f against the oracle's, and the sign of the entropy
+  production.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = {"fp64": 1e-11, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def bzq():
+    import torch  # noqa: F401
+    from paper_2004_11239_amd import bzq as b
+    return b
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _load(name):
+    data = np.load(os.path.join(GOLDEN, name + ".npz"), allow_pickle=False)
+    N, L, R, gamma, s, N_rho, M, seed = data["params"]
+    N, N_rho, M, seed = int(N), int(N_rho), int(M), int(seed)
+    kind = int(data["kind"])
+    if kind == 2:
+        f = workloads.broadband_spectrum(N, seed)
+    else:
+        f = workloads.to_spectral(workloads.random_mixture(seed).sample(N, L))
+    return (N, L, R, gamma, s, N_rho, M), f, data["modes"], data["Q"]
+
+
+@pytest.mark.parametrize("weights", ["table", "otf"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["broadband_N128", "huge_mix_gm1"])
+def test_n128_stored_samples_per_mode(bzq, name, prec, weights):
+    (N, L, R, gamma, s, N_rho, M), f, ks, ref = _load(name)
+    print(f"case {name} N={N} prec={prec} weights={weights}", flush=True)
+    plan = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision=prec, weights=weights)
+    info = plan.info()
+    assert info["P"] == 192
+    Q = _host(plan.collision(_dev(f)))
+    plan.destroy()
+    got = Q[tuple(np.mod(ks, N).T)]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    worst = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"{name} {prec} {weights}: rel L2 {err:.3e}, worst mode / max|Q| {worst:.3e}", flush=True)
+    assert err < TOL[prec] and worst < TOL[prec]
+    # Q_0 = 0 and the Hermitian mirror, exactly; Nyquist planes zero
+    assert Q[0, 0, 0] == 0.0
+    k = np.array([[1, 2, 3], [63, -63, 5], [-7, 0, 63]])
+    a, b = Q[tuple(np.mod(k, N).T)], Q[tuple(np.mod(-k, N).T)]
+    assert np.array_equal(a, np.conj(b))
+    assert not Q[N // 2].any() and not Q[:, N // 2].any() and not Q[:, :, N // 2].any()
+
+
+def test_n128_tables_agree_with_series(bzq):
+    """The stored table and the weights on the fly give the same Q at N = 128
+    to the series' truncation level (FP64, every mode)."""
+    (N, L, R, gamma, s, N_rho, M), f, _, _ = _load("broadband_N128")
+    fd = _dev(f)
+    qt = _host(bzq.Plan(N, L, R, gamma, s, N_rho, M, precision="fp64").collision(fd))
+    qo = _host(bzq.Plan(N, L, R, gamma, s, N_rho, M, precision="fp64", weights="otf").collision(fd))
+    err = float(np.max(np.abs(qt - qo)) / np.max(np.abs(qt)))
+    print(f"table vs series at N=128: {err:.3e}", flush=True)
+    assert err < 1e-11
+
+
+def test_n128_moments_and_entropy(bzq):
+    N, L = 128, 10.0
+    f = workloads.to_spectral(workloads.random_mixture(12).sample(N, L))
+    plan = bzq.Plan(N, L, 5.0, 0.0, 0.5, 8, 14, precision="fp64")
+    fd = _dev(f)
+    Q = plan.collision(fd)
+    m = plan.moments(fd, Q)
+    mass, mom, energy = oracle.moments(f, L)
+    print(f"N=128 moments: {m} vs {mass}, {mom}, {energy}", flush=True)
+    assert abs(m["mass"] - mass) < 1e-13 * abs(mass)
+    assert np.max(np.abs(np.array(m["momentum"]) - mom)) < 1e-12 * abs(mass)
+    assert abs(m["energy"] - energy) < 1e-12 * abs(energy)
+    # H-theorem: the entropy production of the collision operator is negative
+    assert m["entropy_dissipation"] < 0
+
+
+def test_n128_noalloc_refused(bzq):
+    """The static scratch (128 MiB) holds no chunk at N = 128: refused, nothing run."""
+    import torch
+    plan = bzq.Plan(128, 10.0, 5.0, 0.0, 0.5, 8, 6, precision="fp32")
+    f = _dev(workloads.broadband_spectrum(128, 11))
+    q = torch.empty_like(f)
+    with pytest.raises(bzq.BzqError) as e:
+        plan.collision_noalloc(f, q)
+    assert e.value.code == 4

@@ -71,7 +71,8 @@ def test_argument_validation_without_device(lib):
         ((16, 8.0, 4.0, 0.0, 0.5, 16, 37, 0), 1),     # no Lebedev rule of size 37
         ((16, 8.0, 4.0, 0.0, 0.5, 16, 38, 7), 1),     # unknown precision
         ((12, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),     # valid but no FFT schedule
-        ((128, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),
+        ((96, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),
+        ((256, 8.0, 4.0, 0.0, 0.5, 16, 38, 0), 4),
     ]
     # kernel selector (BZQ_KERNEL_POWER = 0, BZQ_KERNEL_CUTOFF_CONST = 1)
     cases = [(a + (0,), c) for a, c in cases] + [
