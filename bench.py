@@ -457,6 +457,54 @@ def bench_otf(bzq, torch, cfg, fhat_np, q_ref, n_evals=3):
     return out
 
 
+HUGE = dict(N=128, L=10.0, R=5.0, gamma=0.0, s=0.5, N_rho=128, M=302)
+
+
+def bench_n128(bzq, torch, cfg=HUGE):
+    """N = 128 (P = 192) with weights on the fly, in the large workload's box:
+    evals/s per precision, plan device memory against what a stored weight
+    table would take, plan creation time, per-stage times and the FP32 result
+    against the FP64 one."""
+    import numpy as np
+    f = workloads.to_spectral(workloads.random_mixture(0).sample(cfg["N"], cfg["L"]))
+    fd = torch.from_numpy(f).to("cuda")
+    out = {"workload": "N=128^3 L=10 R=5 N_rho=128 M=302 Lebedev gamma=0 s=0.5, weights on the fly "
+                       "(random Maxwellian mixture, seed 0)"}
+    qs = {}
+    for prec in ("fp32", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = bzq.Plan(cfg["N"], cfg["L"], cfg["R"], cfg["gamma"], cfg["s"], cfg["N_rho"], cfg["M"],
+                     precision=prec, weights="otf")
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - t0
+        q = torch.empty_like(fd)
+        p.collision(fd, q)                      # warm-up
+        p.set_timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        p.collision(fd, q)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st = p.stage_times()
+        info = p.info()
+        out[prec] = {"evals_per_s": round(1000.0 / ms, 3), "ms_per_eval": round(ms, 1),
+                     "stage_ms_per_eval": {k: round(v[0], 1) for k, v in st.items()},
+                     "plan_device_MB": round(p.device_bytes() / 2 ** 20, 1),
+                     "table_plan_would_hold_GB": round(
+                         bzq.plan_bytes_estimate(cfg["N"], cfg["N_rho"], cfg["M"], prec) / 2 ** 30, 1),
+                     "plan_create_s": round(t_create, 2), "npairs": info["npairs"],
+                     "pairs_per_chunk": info["pairs_per_chunk"]}
+        qs[prec] = q.cpu().numpy()
+        p.destroy()
+        del p, q
+        torch.cuda.empty_cache()
+    out["err_fp32_vs_fp64"] = float(np.linalg.norm(qs["fp32"] - qs["fp64"]) / np.linalg.norm(qs["fp64"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +515,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-otf", dest="otf", action="store_false",
                     help="skip the plans with weights on the fly (beside the N = 64 workload)")
+    ap.add_argument("--no-n128", dest="n128", action="store_false",
+                    help="skip the N = 128 plans with weights on the fly")
     ap.add_argument("--no-2d", dest="two_d", action="store_false",
                     help="skip the 2-D operator at Table 1's N = 64 setting")
     ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
@@ -618,6 +668,8 @@ def main():
         out["large_N64"] = large
         if args.otf:
             out["weights_on_the_fly"] = bench_otf(bzq, torch, cl, fl, qs["fp64"])
+    if args.n128:
+        out["n128_on_the_fly"] = bench_n128(bzq, torch)
     if args.two_d:
         out["two_d"] = bench_2d(bzq, torch)
     if args.batch_cells > 0:
