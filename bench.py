@@ -249,6 +249,18 @@ def batch_bench(bzq, torch, n_cells, steps, seed=0):
            "ms_per_step": round(ms / steps, 2), "steps": steps,
            "groups": batch.groups(), "setup_s": round(setup, 1),
            "workspace_gb": round(batch.device_bytes() / 1e9, 2)}
+    # the batch's roofline: per cell, two evaluations of the whole-path floor
+    # (the method's own flops and bytes at that N, binding roof per cell)
+    counts = {}
+    for N, _ in cells:
+        counts[N] = counts.get(N, 0) + 1
+    roof_ms = 0.0
+    for N, n in counts.items():
+        nreal = N * (110 // 2)
+        roof_ms += 2 * n * whole_path(N, nreal + (nreal & 1), 4, 1.0)["t_roof_ms"]
+    out["roofline"] = {"t_roof_ms_per_step": round(roof_ms, 2),
+                       "frac_of_roof": round(roof_ms / (ms / steps), 4),
+                       "cells_by_N": {str(k): v for k, v in sorted(counts.items())}}
     batch.destroy()
     return out
 
@@ -466,6 +478,7 @@ def bench_n128(bzq, torch, cfg=HUGE):
     table would take, plan creation time, per-stage times and the FP32 result
     against the FP64 one."""
     import numpy as np
+    import workloads
     f = workloads.to_spectral(workloads.random_mixture(0).sample(cfg["N"], cfg["L"]))
     fd = torch.from_numpy(f).to("cuda")
     out = {"workload": "N=128^3 L=10 R=5 N_rho=128 M=302 Lebedev gamma=0 s=0.5, weights on the fly "
