@@ -148,7 +148,8 @@ constexpr int kSTargets[3] = {512, 1024, 2048};
 // Splits of the z-forward stage for kernel variant zv: about s_target
 // workgroups of tq pencils, at most one per group of pair-twos.  Pipelined
 // kernel: 32 pencils, one pair-two per step; other register kernels: 32 or 16
-// pencils, 2 or 4 pair-twos per step; LDS kernels (FP64 P > 48): 8 pencils.
+// pencils, 2 or 4 pair-twos per step; LDS kernels (FP64 P > 48, FP32 P > 96):
+// 8 pencils.
 // When the kernel's residency is known and at most s_target, the workgroups
 // fill whole rounds of the chip: s_target is rounded down to a multiple of the
 // resident workgroups and S down to what fits it, so that no launch ends with

@@ -36,8 +36,11 @@ namespace bzq {
 
 namespace {
 
-constexpr int K1_TP = 32;   // pencils per zinv workgroup
-constexpr int K3_TQ = 8;    // half-spectrum pencils per zfwd workgroup (LDS variant)
+// Tiles of the LDS z kernels (measured at 128^3, P = 192: 16 z-inverse pencils
+// per workgroup, 5.4 / 11.3 ms FP32 / FP64 against 7.3 / 16.8 with 32; 8
+// z-forward pencils, 7.3 ms FP32 against 14.8 with 16)
+constexpr int K1_TP = 16;   // pencils per zinv workgroup
+constexpr int K3_TQ = 8;    // half-spectrum pencils per zfwd workgroup
 constexpr int NT_SMALL = 256;
 
 template <int P>
@@ -59,6 +62,33 @@ __device__ __forceinline__ int fold_slot(int c, int nn, int nhp) {
 __device__ __forceinline__ int posK(int i, int h, int P) {
   const int k = i - (h - 1);
   return k >= 0 ? k : k + P;
+}
+
+// Largest N - 1 that a length-P axis carries: P - 1 on an unpadded grid
+// (P = N), 2P/3 - 1 on a padded one (P = 3N/2).
+template <int P>
+constexpr int maxN1() {
+  return (P == 8 || P == 16 || P == 24 || P == 32 || P == 48 || P == 64 || P == 128) ? P - 1 : 2 * P / 3 - 1;
+}
+
+// n element copies (element e: v = load(e), then store(e, v)) by NT threads,
+// every load of a thread issued before its first store, so that its loads are
+// in flight together rather than one memory round trip per element.  MAXN
+// bounds n at compile time.
+template <typename V, int MAXN, int NT, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int n, Load load, Store store) {
+  constexpr int K = (MAXN + NT - 1) / NT;
+  V v[K];
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const int e = (int)threadIdx.x + b * NT;
+    if (e < n) v[b] = load(e);
+  }
+#pragma unroll
+  for (int b = 0; b < K; ++b) {
+    const int e = (int)threadIdx.x + b * NT;
+    if (e < n) store(e, v[b]);
+  }
 }
 
 // Workgroup barrier that orders LDS accesses only: global loads issued before
@@ -183,48 +213,63 @@ __global__ void k_ingest(PtrPack fin, cx<T>* __restrict__ fc, size_t fc_stride, 
 }
 
 // -------------------------------------------------------------------- zinv
+// LDS kernel for pencils that do not fit the register file: K1_TP pencils
+// per workgroup.  The pair-two's phase factors are staged in LDS once per
+// workgroup (axes 1 and 2 per pencil, axis 3 per height) and multiplied in
+// the order of the register kernels' modulation.
 template <typename T, int P, int NT>
 __global__ __launch_bounds__(NT) void k_zinv(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
                                              cx<T>* __restrict__ A, const cx<T>* __restrict__ twg, int N,
                                              int pair0, int mode, CellStrides cs) {
-  constexpr int LD = P + 1;
+  constexpr int LD = P + 1, MN1 = maxN1<P>();
   fc += blockIdx.z * cs.fc;
   A += blockIdx.z * cs.a;
   __shared__ cx<T> buf[K1_TP * LD];
   __shared__ cx<T> tw[P];
+  __shared__ double2 e12[2][K1_TP];
+  __shared__ double2 e3[2][MN1];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
   const int c0 = blockIdx.x * K1_TP;
   const int np = min(K1_TP, nn - c0);
   const int pt = blockIdx.y;
   for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
   for (int i = threadIdx.x; i < K1_TP * LD; i += NT) buf[i] = cx<T>{0, 0};
-  __syncthreads();
-  const double2* phA = nullptr;
-  const double2* phB = nullptr;
   if (mode == ZINV_PAIRS) {
-    phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
-    phB = phA + 3 * PL;
-  }
-  for (int e = threadIdx.x; e < np * n1; e += NT) {
-    const int i3 = e / np, p = e - i3 * np;
-    const int c = c0 + p;
-    const int i2 = c / n1, i1 = c - i2 * n1;
-    const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
-    const cx<T> f = fc[(size_t)i3 * nn + c];
-    cx<T> z;
-    if (mode == ZINV_PAIRS) {
-      cx<double> eA = cmul(cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2])), d2c(phA[2 * PL - 2 * k3]));
-      cx<double> eB = cmul(cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2])), d2c(phB[2 * PL - 2 * k3]));
-      // E_A + i E_B
-      cx<T> m = {(T)(eA.x - eB.y), (T)(eA.y + eB.x)};
-      z = cmul(f, m);
-    } else if (mode == ZINV_GRID_SIGN) {
-      z = ((k1 + k2 + k3) & 1) ? cx<T>{-f.x, -f.y} : f;
-    } else {
-      z = f;
+    const double2* phA = ph + (size_t)(pair0 + 2 * pt) * 3 * PL + (N - 2);
+    for (int t = threadIdx.x; t < 2 * np; t += NT) {
+      const int w = t / np, p = t - w * np;
+      const int c = c0 + p, i2 = c / n1, i1 = c - i2 * n1;
+      const double2* pw = phA + w * 3 * PL;
+      const cx<double> e = cmul(d2c(pw[-2 * (i1 - h + 1)]), d2c(pw[PL - 2 * (i2 - h + 1)]));
+      e12[w][p] = double2{e.x, e.y};
     }
-    buf[p * LD + posK(i3, h, P)] = z;
+    for (int t = threadIdx.x; t < 2 * n1; t += NT) {
+      const int w = t / n1, i3 = t - w * n1;
+      e3[w][i3] = phA[w * 3 * PL + 2 * PL - 2 * (i3 - h + 1)];
+    }
   }
+  __syncthreads();
+  staged_copy<cx<T>, K1_TP * MN1, NT>(
+      np * n1, [&](int e) { const int i3 = e / np; return fc[(size_t)i3 * nn + c0 + e - i3 * np]; },
+      [&](int e, cx<T> f) {
+        const int i3 = e / np, p = e - i3 * np;
+        const int c = c0 + p;
+        const int i2 = c / n1, i1 = c - i2 * n1;
+        const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
+        cx<T> z;
+        if (mode == ZINV_PAIRS) {
+          const cx<double> eA = cmul(d2c(e12[0][p]), d2c(e3[0][i3]));
+          const cx<double> eB = cmul(d2c(e12[1][p]), d2c(e3[1][i3]));
+          // E_A + i E_B
+          const cx<T> m = {(T)(eA.x - eB.y), (T)(eA.y + eB.x)};
+          z = cmul(f, m);
+        } else if (mode == ZINV_GRID_SIGN) {
+          z = ((k1 + k2 + k3) & 1) ? cx<T>{-f.x, -f.y} : f;
+        } else {
+          z = f;
+        }
+        buf[p * LD + posK(i3, h, P)] = z;
+      });
   __syncthreads();
   fft_pencils<T, P, +1, NT, K1_TP>(buf, np, RowAddr{LD}, 1, tw);
   cx<T>* Aout = A + (size_t)pt * P * nn;
@@ -296,14 +341,15 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
   constexpr int LD = P + 1;
   B += blockIdx.z * cs.b;
   Qpart += blockIdx.z * cs.qp;
-  constexpr int ROWS = 2 * K3_TQ;
+  constexpr int TQ = K3_TQ;
+  constexpr int ROWS = 2 * TQ;
   constexpr int NMAX = (2 * P) / 3;                       // N for the padded length P
-  constexpr int OPT = (K3_TQ * (NMAX - 1) + NT - 1) / NT;
+  constexpr int OPT = (TQ * (NMAX - 1) + NT - 1) / NT;
   __shared__ cx<T> buf[ROWS * LD];
   __shared__ cx<T> tw[P];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
-  const int c0 = blockIdx.x * K3_TQ;
-  const int nq = min(K3_TQ, nh - c0);
+  const int c0 = blockIdx.x * TQ;
+  const int nq = min(TQ, nh - c0);
   const int s = blockIdx.y;
   for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
   for (int i = threadIdx.x; i < ROWS * LD; i += NT) buf[i] = cx<T>{0, 0};
@@ -314,29 +360,35 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
   for (int pt = s; pt < npt; pt += S) {
     const int nhp = nh_pad(N);
     const cx<T>* Bin = B + (size_t)pt * P * 2 * nhp;
-    for (int e = threadIdx.x; e < 2 * nq * P; e += NT) {
-      const int z = e / (2 * nq), q = e - z * (2 * nq);
-      int slot, row;
-      if (q < nq) { slot = c0 + q; row = q; }
-      else { slot = nhp + c0 + q - nq; row = K3_TQ + q - nq; }
-      buf[row * LD + z] = Bin[(size_t)z * 2 * nhp + slot];
-    }
+    // the tile's 2 nq pencils (nq half-spectrum pencils and their mirrors)
+    staged_copy<cx<T>, ROWS * P, NT>(
+        2 * nq * P,
+        [&](int e) {
+          const int z = e / (2 * nq), q = e - z * (2 * nq);
+          return Bin[(size_t)z * 2 * nhp + (q < nq ? c0 + q : nhp + c0 + q - nq)];
+        },
+        [&](int e, cx<T> v) {
+          const int z = e / (2 * nq), q = e - z * (2 * nq);
+          buf[(q < nq ? q : TQ + q - nq) * LD + z] = v;
+        });
     __syncthreads();
     fft_pencils<T, P, -1, NT, ROWS>(buf, ROWS, RowAddr{LD}, 1, tw);
     const int jA = pair0 + 2 * pt, jB = jA + 1;
     const double2* phA = ph + (size_t)jA * 3 * PL + (N - 2);
     const double2* phB = phA + 3 * PL;
     const double cA = cp[jA], cB = cp[jB];
+    // output mode o: height i3 = o / TQ, pencil c0 + o % TQ (adjacent lanes
+    // take adjacent pencils: coalesced weight reads and partial-sum writes)
 #pragma unroll
     for (int b = 0; b < OPT; ++b) {
       const int o = threadIdx.x + b * NT;
-      if (o < nq * n1) {
-        const int q = o / n1, i3 = o - q * n1;
+      const int i3 = o / TQ, q = o - i3 * TQ;
+      if (i3 < n1 && q < nq) {
         const int c = c0 + q;
         const int i2 = c / n1, i1 = c - i2 * n1;
         const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
         const cx<T> w1 = buf[q * LD + posK(i3, h, P)];
-        const cx<T> w2 = buf[(K3_TQ + q) * LD + posK(n1 - 1 - i3, h, P)];
+        const cx<T> w2 = buf[(TQ + q) * LD + posK(n1 - 1 - i3, h, P)];
         // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
         const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
         const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
@@ -354,8 +406,8 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
   }
   add_partials<OPT>(Qpart, accx, accy, first, [&](int b) -> long long {
     const int o = threadIdx.x + b * NT;
-    if (o >= nq * n1) return -1;
-    const int q = o / n1, i3 = o - q * n1;
+    const int i3 = o / TQ, q = o - i3 * TQ;
+    if (i3 >= n1 || q >= nq) return -1;
     return ((long long)s * n1 + i3) * nh + c0 + q;
   });
 }
@@ -371,10 +423,12 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
 //   rows:    forward along axis 2 keeping the N-1 modes           -> B
 // Each pass is the same arithmetic as the one-workgroup plane kernels, in LDS
 // Stockham passes over a block of rows or columns.
+// (16 rows and 16 columns per workgroup: at 128^3 FP32 the plane takes 25.8 ms
+// per 440 pair-twos against 27.6 with 32 columns and 28.0 with 8 rows)
 template <typename T>
 struct SplitCfg {
-  static constexpr int RB = 16;                        // rows per workgroup
-  static constexpr int CB = sizeof(T) == 4 ? 32 : 16;  // columns per workgroup
+  static constexpr int RB = 16;   // rows per workgroup
+  static constexpr int CB = 16;   // columns per workgroup
   static constexpr int NT = 256;
 };
 
@@ -396,10 +450,9 @@ __global__ __launch_bounds__(SplitCfg<T>::NT) void k_prow_inv(const cx<T>* __res
   __syncthreads();
   // row i1 = r0 + r holds A[i2 n1 + i1] at position posK(i2)
   const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + r0;
-  for (int e = threadIdx.x; e < nr * n1; e += NT) {
-    const int i2 = e / nr, r = e - i2 * nr;
-    buf[r * LD + posK(i2, h, P)] = Ain[(size_t)i2 * n1 + r];
-  }
+  staged_copy<cx<T>, RB * maxN1<P>(), NT>(
+      nr * n1, [&](int e) { const int i2 = e / nr; return Ain[(size_t)i2 * n1 + e - i2 * nr]; },
+      [&](int e, cx<T> v) { const int i2 = e / nr; buf[(e - i2 * nr) * LD + posK(i2, h, P)] = v; });
   __syncthreads();
   fft_pencils<T, P, +1, NT, RB>(buf, nr, RowAddr{LD}, 1, tw);
   cx<T>* Cout = C + (((size_t)pt * P + z) * n1 + r0) * P;
@@ -427,10 +480,9 @@ __global__ __launch_bounds__(SplitCfg<T>::NT) void k_pcol(cx<T>* __restrict__ C,
   __syncthreads();
   // column y0 + q holds the N-1 rows' values at positions posK(i1)
   cx<T>* Cz = C + ((size_t)pt * P + z) * n1 * P + y0;
-  for (int e = threadIdx.x; e < n1 * CB; e += NT) {
-    const int i1 = e / CB, q = e - i1 * CB;
-    buf[q * LD + posK(i1, h, P)] = Cz[(size_t)i1 * P + q];
-  }
+  staged_copy<cx<T>, maxN1<P>() * CB, NT>(
+      n1 * CB, [&](int e) { return Cz[(size_t)(e / CB) * P + e % CB]; },
+      [&](int e, cx<T> v) { buf[(e % CB) * LD + posK(e / CB, h, P)] = v; });
   __syncthreads();
   fft_pencils<T, P, +1, NT, CB>(buf, CB, RowAddr{LD}, 1, tw);
   if constexpr (MODE == PLANE_TO_GRID) {
@@ -441,10 +493,9 @@ __global__ __launch_bounds__(SplitCfg<T>::NT) void k_pcol(cx<T>* __restrict__ C,
     }
   } else {
     const T* fz = fgrid + blockIdx.z * cs.fg + (size_t)z * P * P + y0;
-    for (int e = threadIdx.x; e < P * CB; e += NT) {
-      const int x = e / CB, q = e - x * CB;
-      buf[q * LD + x] = cscale(buf[q * LD + x], fz[(size_t)x * P + q]);
-    }
+    staged_copy<T, P * CB, NT>(
+        P * CB, [&](int e) { return fz[(size_t)(e / CB) * P + e % CB]; },
+        [&](int e, T f) { cx<T>& v = buf[(e % CB) * LD + e / CB]; v = cscale(v, f); });
     __syncthreads();
     fft_pencils<T, P, -1, NT, CB>(buf, CB, RowAddr{LD}, 1, tw);
     for (int e = threadIdx.x; e < n1 * CB; e += NT) {
@@ -469,10 +520,8 @@ __global__ __launch_bounds__(SplitCfg<T>::NT) void k_prow_fwd(const cx<T>* __res
   B += blockIdx.z * cs.b;
   for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
   const cx<T>* Cin = C + (((size_t)pt * P + z) * n1 + r0) * P;
-  for (int e = threadIdx.x; e < nr * P; e += NT) {
-    const int r = e / P, y = e - r * P;
-    buf[r * LD + y] = Cin[(size_t)r * P + y];
-  }
+  staged_copy<cx<T>, RB * P, NT>(
+      nr * P, [&](int e) { return Cin[e]; }, [&](int e, cx<T> v) { buf[(e / P) * LD + e % P] = v; });
   __syncthreads();
   fft_pencils<T, P, -1, NT, RB>(buf, nr, RowAddr{LD}, 1, tw);
   // row k1 = r0 + r gives the modes c = k2 n1 + k1 of the folded B layout
