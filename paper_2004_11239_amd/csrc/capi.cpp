@@ -77,7 +77,7 @@ size_t Plan::workspace_bytes_per_cell() const {
   return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * nn * 2 * esz +
          (size_t)G * P * 2 * nhp * 2 * esz + plane_rows_elems(*this, G) * 2 * esz + (size_t)S_cap * nh * n1 * 16 +
          3 * N3 * 16 +
-         (otf ? (size_t)2 * Gw * nh * n1 * esz : 0) + 4 * sizeof(int);
+         (otf ? (size_t)2 * Gw * weight_row(N) * n1 * esz : 0) + 4 * sizeof(int);
 }
 
 bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
@@ -103,7 +103,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   if ((s = w.arena.get(&w.q1, cells * N3 * 16)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.q2, cells * N3 * 16)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.fs, cells * N3 * 16)) != BZQ_OK) return s;
-  if (p.otf && (s = w.arena.get(&w.Vc, (size_t)2 * p.Gw * p.nh * p.n1 * p.esz)) != BZQ_OK) return s;
+  if (p.otf && (s = w.arena.get(&w.Vc, (size_t)2 * p.Gw * weight_row(p.N) * p.n1 * p.esz)) != BZQ_OK) return s;
   if ((s = w.arena.get(&w.flag, 4 * sizeof(int))) != BZQ_OK) return s;
   return BZQ_OK;
 }
@@ -183,7 +183,7 @@ void set_chunking(Plan& p) {
   // BZQ_OTF_MB, default 128 MiB)
   const char* envw = std::getenv("BZQ_OTF_MB");
   const size_t capw = (envw && std::atoll(envw) > 0 ? (size_t)std::atoll(envw) : 128ull) << 20;
-  const size_t per_w = (size_t)2 * p.nh * p.n1 * p.esz;
+  const size_t per_w = (size_t)2 * weight_row(p.N) * p.n1 * p.esz;
   p.Gw = p.otf ? (int)std::max<size_t>(1, std::min<size_t>((size_t)p.G, capw / per_w)) : 0;
   p.S = zfwd_splits(p, effective_variant(p, 2), p.s_target);
   p.S_cap = p.S;
@@ -219,11 +219,11 @@ bzq_status alloc_scratch(Plan* p);
 }  // namespace
 
 size_t plan_shared_bytes_estimate(int N, int N_rho, int M, int precision) {
-  const int P = 3 * N / 2, n1 = N - 1, nh = (n1 * n1 + 1) / 2;
+  const int P = 3 * N / 2, n1 = N - 1;
   const size_t esz = precision == BZQ_FP32_ACC64 ? 4 : 8;
   const int nreal = N_rho * (M / 2);
   const size_t npairs = nreal + (nreal & 1);
-  return npairs * nh * n1 * esz + npairs * 3 * (2 * N - 3) * 16 + (size_t)P * 2 * esz + (size_t)N * 16;
+  return npairs * weight_row(N) * n1 * esz + npairs * 3 * (2 * N - 3) * 16 + (size_t)P * 2 * esz + (size_t)N * 16;
 }
 
 bzq_status derive_plan(const Plan& base, double gamma, bzq_plan* out, hipStream_t st) {
@@ -427,7 +427,7 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
   set_chunking(*p);
   // -- tables
   bzq_status s;
-  const size_t vcount = (size_t)p->npairs * nh * p->n1;
+  const size_t vcount = (size_t)p->npairs * weight_row(N) * p->n1;
   if (p->otf) {
     if ((s = build_series(p, rho, Mh, nreal, st)) != BZQ_OK) return s;
   } else if ((s = p->shared->get(&p->V, vcount * p->esz)) != BZQ_OK) {
@@ -777,7 +777,7 @@ bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat,
     b_b = al((size_t)g * p->P * 2 * p->nhp * 2 * esz);
     b_c = al(plane_rows_elems(*p, g) * 2 * esz);
     b_q = al((size_t)S * p->nh * p->n1 * 16);
-    b_w = al((size_t)2 * Gw * p->nh * p->n1 * esz);
+    b_w = al((size_t)2 * Gw * weight_row(p->N) * p->n1 * esz);
     return b_fc + b_fg + b_a + b_b + b_c + b_q + b_w;
   };
   while (G > 1 && need(G) > kNoAllocScratchBytes) --G;
@@ -1065,7 +1065,7 @@ bzq_status bzq_plan_info(bzq_plan p, double* out) {
   out[5] = p->fp32 ? BZQ_FP32_ACC64 : BZQ_FP64;
   out[6] = p->nj;
   out[7] = p->otf ? (double)((size_t)p->N_rho * p->mt * p->ncoef * sizeof(double))
-                  : (double)((size_t)p->npairs * p->nh * p->n1 * p->esz);
+                  : (double)((size_t)p->npairs * weight_row(p->N) * p->n1 * p->esz);
   return BZQ_OK;
 }
 
@@ -1078,8 +1078,9 @@ bzq_status bzq_plan_pairs(bzq_plan p, double* out) {
 bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
   if (!p || !out) return fail(BZQ_EINVAL, "NULL argument");
   if (pair < 0 || pair >= p->npairs) return fail(BZQ_EINVAL, "pair index out of range");
-  // stored as [i3][c]; returned as [c][i3]
-  const size_t cnt = (size_t)p->nh * p->n1;
+  // stored as [i3][c] (rows of weight_row(N) entries); returned as [c][i3]
+  const int nhv = weight_row(p->N);
+  const size_t cnt = (size_t)nhv * p->n1;
   const char* src = nullptr;
   DeviceArena scratch;
   if (!p->otf) {
@@ -1103,7 +1104,7 @@ bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out) {
     BZQ_HIP_TRY(hipMemcpy(tmp.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost));
   }
   for (int i3 = 0; i3 < p->n1; ++i3)
-    for (int c = 0; c < p->nh; ++c) out[(size_t)c * p->n1 + i3] = tmp[(size_t)i3 * p->nh + c];
+    for (int c = 0; c < p->nh; ++c) out[(size_t)c * p->n1 + i3] = tmp[(size_t)i3 * nhv + c];
   return BZQ_OK;
 }
 

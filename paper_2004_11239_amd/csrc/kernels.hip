@@ -347,7 +347,7 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
   constexpr int OPT = (TQ * (NMAX - 1) + NT - 1) / NT;
   __shared__ cx<T> buf[ROWS * LD];
   __shared__ cx<T> tw[P];
-  const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3, nhv = weight_row(N);
   const int c0 = blockIdx.x * TQ;
   const int nq = min(TQ, nh - c0);
   const int s = blockIdx.y;
@@ -392,9 +392,9 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
         // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
         const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
         const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
-        const size_t vi = (size_t)i3 * nh + c;
-        const double vA = cA * (double)V[(size_t)(jA - vpair0) * nh * n1 + vi];
-        const double vB = cB * (double)V[(size_t)(jB - vpair0) * nh * n1 + vi];
+        const size_t vi = (size_t)i3 * nhv + c;
+        const double vA = cA * (double)V[(size_t)(jA - vpair0) * nhv * n1 + vi];
+        const double vB = cB * (double)V[(size_t)(jB - vpair0) * nhv * n1 + vi];
         const cx<double> eA = cmul(cmul(d2c(phA[k1]), d2c(phA[PL + k2])), d2c(phA[2 * PL + k3]));
         const cx<double> eB = cmul(cmul(d2c(phB[k1]), d2c(phB[PL + k2])), d2c(phB[2 * PL + k3]));
         const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
@@ -1631,7 +1631,7 @@ __device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, cons
                                                int first, int bx, int s, ZfwdPipeLds<T, N, P>& L, const unsigned tx) {
   using C = ZfwdPipeCfg<P>;
   constexpr int TQ = C::TQ, PW = C::PW, NC = 64 * C::CW;
-  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3, nhv = weight_row(N);
   constexpr int nhp = (nh + 15) / 16 * 16;
   constexpr int OPT = (TQ * n1 + NC - 1) / NC;
   auto& W = L.W;
@@ -1716,14 +1716,14 @@ __device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, cons
       if (i < nmine) {
         // weights of the pair-two the producers are transforming now
         const int jA = pair0 + 2 * (s + i * S);
-        const T* VA = V + (size_t)(jA - vpair0) * nh * n1;
-        const T* VB = VA + (size_t)nh * n1;
+        const T* VA = V + (size_t)(jA - vpair0) * nhv * n1;
+        const T* VB = VA + (size_t)nhv * n1;
 #pragma unroll
         for (int bb = 0; bb < OPT; ++bb) {
           const int o = t + bb * NC;
           const int i3 = o / TQ, qq = o - i3 * TQ;
           const bool ok = o < TQ * n1 && c0 + qq < nh;
-          const size_t vi = (size_t)i3 * nh + c0 + qq;
+          const size_t vi = (size_t)i3 * nhv + c0 + qq;
           va[bb] = ok ? VA[vi] : T(0);
           vb[bb] = ok ? VB[vi] : T(0);
         }
@@ -1781,7 +1781,7 @@ __device__ __forceinline__ void zfwd_reg_body(const cx<T>* __restrict__ B, const
                                               int first, int bx, int s, ZfwdRegLds<T, N, P>& L, const unsigned tx) {
   using C = ZfwdCfg<T, P>;
   constexpr int TQ = C::TQ, PT = C::PT, NT = C::NT;
-  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3;
+  constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3, nhv = weight_row(N);
   constexpr int OPT = (TQ * n1 + NT - 1) / NT;
   auto& W = L.W;
   auto& E12 = L.E12;
@@ -1846,9 +1846,9 @@ __device__ __forceinline__ void zfwd_reg_body(const cx<T>* __restrict__ B, const
             // h_A = (w(k) + conj w(-k))/2,  h_B = (w(k) - conj w(-k))/(2i)
             const cx<double> hA = {0.5 * ((double)w1.x + (double)w2.x), 0.5 * ((double)w1.y - (double)w2.y)};
             const cx<double> hB = {0.5 * ((double)w1.y + (double)w2.y), -0.5 * ((double)w1.x - (double)w2.x)};
-            const size_t vi = (size_t)i3 * nh + c;
-            const double vA = CPV[pp][0] * (double)V[(size_t)(jA - vpair0) * nh * n1 + vi];
-            const double vB = CPV[pp][1] * (double)V[(size_t)(jA + 1 - vpair0) * nh * n1 + vi];
+            const size_t vi = (size_t)i3 * nhv + c;
+            const double vA = CPV[pp][0] * (double)V[(size_t)(jA - vpair0) * nhv * n1 + vi];
+            const double vB = CPV[pp][1] * (double)V[(size_t)(jA + 1 - vpair0) * nhv * n1 + vi];
             const cx<double> eA = cmul(d2c(E12[pp][0][qq]), d2c(E3[pp][0][i3]));
             const cx<double> eB = cmul(d2c(E12[pp][1][qq]), d2c(E3[pp][1][i3]));
             const cx<double> tA = cmul(eA, hA), tB = cmul(eB, hB);
@@ -2022,14 +2022,14 @@ __global__ void k_table(TV* __restrict__ V, const double* __restrict__ pd, const
     sw[i] = gj[nj + i];
   }
   __syncthreads();
-  const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2;
-  const size_t per = (size_t)nh * n1;
+  const int n1 = N - 1, h = N / 2, nhv = weight_row(N);
+  const size_t per = (size_t)nhv * n1;
   const size_t total = per * npairs;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
     const int j = (int)(e / per);
     const int rem = (int)(e - (size_t)j * per);
-    const int i3 = rem / nh, c = rem - i3 * nh;
+    const int i3 = rem / nhv, c = rem - i3 * nhv;   // c < nhv < (N-1)^2: a mode of K_N
     const int i2 = c / n1, i1 = c - i2 * n1;
     const double k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
     const double* p = pd + (size_t)j * 8;
@@ -2110,11 +2110,11 @@ template <typename T, int PB>
 __global__ __launch_bounds__(256) void k_wgen(T* __restrict__ Vc, const double* __restrict__ coef,
                                               const double4* __restrict__ pdv, const int* __restrict__ terms,
                                               int mt, int N, int Mh, int nreal, int j0, int nj, int ncoef) {
-  const int n1 = N - 1, h = N / 2, nh = (n1 * n1 + 1) / 2;
-  const int per = nh * n1;
+  const int n1 = N - 1, h = N / 2, nhv = weight_row(N);
+  const int per = nhv * n1;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= per) return;
-  const int i3 = e / nh, c = e - i3 * nh;
+  const int i3 = e / nhv, c = e - i3 * nhv;   // c < nhv < (N-1)^2: a mode of K_N
   const int i2 = c / n1, i1 = c - i2 * n1;
   const int k1 = i1 - h + 1, k2 = i2 - h + 1, k3 = i3 - h + 1;
   const int n = k1 * k1 + k2 * k2 + k3 * k3;
@@ -2758,8 +2758,8 @@ hipError_t launch_heun_cells(const PtrPack& f, const PtrPack& q1, const PtrPack&
 
 hipError_t launch_table(void* V, const double* pd, const double* gj, int nj, int N, int npairs, bool fp32,
                         hipStream_t st) {
-  const size_t n1 = N - 1, nh = (n1 * n1 + 1) / 2;
-  const size_t n = nh * n1 * npairs;
+  const size_t n1 = N - 1;
+  const size_t n = (size_t)weight_row(N) * n1 * npairs;
   const int g = grid_for(n, 256) < 4096 ? grid_for(n, 256) : 4096;
   if (fp32)
     hipLaunchKernelGGL(k_table<float>, dim3(g), dim3(256), 0, st, (float*)V, pd, gj, nj, N, npairs);
@@ -2771,7 +2771,7 @@ hipError_t launch_table(void* V, const double* pd, const double* gj, int nj, int
 hipError_t launch_wgen(void* Vc, const double* coef, const double* pdv, const int* terms, int mt, int N, int Mh,
                        int nreal, int j0, int nj, int ncoef, bool fp32, hipStream_t st) {
   if (mt < 8 || mt > 80 || (mt & 7)) return hipErrorInvalidValue;
-  const int n1 = N - 1, per = ((n1 * n1 + 1) / 2) * n1;
+  const int n1 = N - 1, per = weight_row(N) * n1;
   const int bx = (per + 255) / 256;
   // about 2048 workgroups, each over at least 16 pairs
   const int by = std::max(1, std::min((2048 + bx - 1) / bx, nj / 16));

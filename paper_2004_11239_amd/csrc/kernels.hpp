@@ -27,6 +27,13 @@ struct CellStrides {
   int cells;
 };
 
+// Row length of the weight table V[pair][i3][c]: the nh = ((N-1)^2 + 1) / 2
+// half-spectrum modes of one height, padded to a multiple of 32 entries so
+// that every row starts on a 128-byte line and the last stage's tiles (32
+// FP32 or 16 FP64 pencils) read whole lines.  The padding entries hold the
+// weights of the next modes c >= nh (valid modes, never read).
+__host__ __device__ constexpr int weight_row(int N) { return ((((N - 1) * (N - 1) + 1) / 2) + 31) / 32 * 32; }
+
 // Per-cell device pointers passed by value (at most kMaxCells per launch).
 constexpr int kMaxCells = 64;
 struct PtrPack {
