@@ -120,3 +120,29 @@ def test_n128_noalloc_refused(bzq):
     with pytest.raises(bzq.BzqError) as e:
         plan.collision_noalloc(f, q)
     assert e.value.code == 4
+
+
+def test_n128_batch_two_cells_bitwise_equal_solo(bzq):
+    """Two N = 128 cells in one launch per stage (the three-pass plane's row
+    buffer and grid strided by cell): Q and a Heun step equal the single-cell
+    path bit for bit, in both precisions."""
+    import torch
+    for prec in ("fp32", "fp64"):
+        plan = bzq.Plan(128, 10.0, 5.0, 0.0, 0.5, 8, 6, precision=prec)
+        fs = [workloads.broadband_spectrum(128, 21), workloads.broadband_spectrum(128, 22)]
+        solo = [_host(plan.collision(_dev(f))) for f in fs]
+        fd = [_dev(f) for f in fs]
+        batch = bzq.Batch([plan, plan], fd, cells_per_launch=2)
+        assert batch.groups()[0]["cells_per_launch"] == 2
+        outs = [torch.empty_like(f) for f in fd]
+        batch.collision(outs)
+        for a, b in zip(solo, outs):
+            assert np.array_equal(a, _host(b)), prec
+        ref = [_dev(f) for f in fs]
+        for r in ref:
+            plan.step(r, 0.01, 1)
+        batch.step(0.01, 1, use_graph=False)
+        for a, b in zip(ref, fd):
+            assert np.array_equal(_host(a), _host(b)), prec
+        batch.destroy()
+        plan.destroy()
