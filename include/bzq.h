@@ -302,8 +302,11 @@ bzq_status bzq_batch_destroy(bzq_batch b);
  *     the tuning cache) before that request runs.  A worker thread owns all
  *     device work.
  *   bzq_server_submit: copies f_host (host, complex128 N^3) and queues the
- *     request; returns its id at once.  BZQ_EBUSY (nothing queued, counted as
- *     rejected) when max_queued requests already wait.  Thread-safe.
+ *     request; returns its id at once.  N is any size bzq_plan_create takes
+ *     (BZQ_EINVAL for odd N or N < 8, BZQ_EUNSUPPORTED for a size without an
+ *     FFT schedule); requests use table plans.  BZQ_EBUSY (nothing queued,
+ *     counted as rejected) when max_queued requests already wait.
+ *     Thread-safe.
  *   bzq_server_poll: 1 = done (result, the new state or Q_hat, copied to f_out
  *     if not NULL, request released), 0 = not yet, -1 = unknown id, -2 =
  *     failed (bzq_last_error tells why; released).  times (optional, host

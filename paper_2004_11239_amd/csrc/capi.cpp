@@ -42,8 +42,9 @@ thread_local std::string g_last_error;
 const long double kPi = 3.141592653589793238462643383279502884L;
 constexpr int kMomentBlocks = 256;
 
-bool supported_N(int N) { return N == 8 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64 || N == 128; }
 }  // namespace
+
+bool supported_N(int N) { return N == 8 || N == 16 || N == 24 || N == 32 || N == 48 || N == 64 || N == 128; }
 
 bzq_status fail(bzq_status s, const std::string& msg) {
   g_last_error = msg;

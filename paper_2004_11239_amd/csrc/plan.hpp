@@ -129,6 +129,8 @@ struct Plan {
   size_t workspace_bytes_per_cell() const;
 };
 
+// Grid sizes with an FFT schedule (8, 16, 24, 32, 48, 64, 128)
+bool supported_N(int N);
 bzq_status workspace_init(Workspace& w, const Plan& p, int cells);
 // elements of the plane-row buffer for G pair-twos (0 where the plane fits LDS)
 inline size_t plane_rows_elems(const Plan& p, int G) {

@@ -435,7 +435,8 @@ bzq_status bzq_server_create(bzq_server* out, size_t budget_bytes, int slots, in
 bzq_status bzq_server_submit(bzq_server s, const bzq_request* req, const double* f_host, unsigned long long* id) {
   if (!s || !req || !f_host || !id) return fail(BZQ_EINVAL, "NULL argument");
   const int N = req->N;
-  if (N < 8 || N > 64 || (N & 1)) return fail(BZQ_EINVAL, "N must be even, 8..64");
+  if (N < 8 || (N & 1)) return fail(BZQ_EINVAL, "N must be even and >= 8");
+  if (!supported_N(N)) return fail(BZQ_EUNSUPPORTED, "no FFT schedule for this N (supported: 8 16 24 32 48 64 128)");
   if (req->kind != BZQ_REQ_STEP && req->kind != BZQ_REQ_COLLISION) return fail(BZQ_EINVAL, "unknown request kind");
   if (req->kind == BZQ_REQ_STEP && (req->n_steps < 0 || !std::isfinite(req->dt)))
     return fail(BZQ_EINVAL, "bad dt or n_steps");

@@ -146,3 +146,32 @@ def test_n128_batch_two_cells_bitwise_equal_solo(bzq):
             assert np.array_equal(_host(a), _host(b)), prec
         batch.destroy()
         plan.destroy()
+
+
+def test_n128_tuning_gamma_sibling_and_server(bzq):
+    """N = 128 through the rest of the API: the schedule tuner (whose result
+    must agree with the default schedule to rounding), a plan derived for
+    another gamma (bitwise equal to one built from scratch), and a Q(f)
+    request to the server (bitwise equal to bzq_collision)."""
+    N, L, R, s, N_rho, M = 128, 10.0, 5.0, 0.5, 8, 6
+    f = workloads.broadband_spectrum(N, 23)
+    fd = _dev(f)
+    plan = bzq.Plan(N, L, R, 0.0, s, N_rho, M, precision="fp32", weights="otf")
+    q0 = _host(plan.collision(fd))
+    sched = plan.autotune(fd, use_cache=False)
+    print(f"N=128 tuned schedule: {sched}", flush=True)
+    q1 = _host(plan.collision(fd))
+    assert float(np.max(np.abs(q1 - q0)) / np.max(np.abs(q0))) < 1e-6
+    sib = plan.with_gamma(-1.0)
+    fresh = bzq.Plan(N, L, R, -1.0, s, N_rho, M, precision="fp32", weights="otf")
+    fresh.set_schedule(**{k: sched[k] for k in ("zinv", "plane", "zfwd", "s_target")})
+    assert np.array_equal(_host(sib.collision(fd)), _host(fresh.collision(fd)))
+    srv = bzq.Server(64 << 30, slots=2)
+    try:
+        rid = srv.submit(f, N, L, R, 0.0, s, N_rho, M, "fp64", kind="collision")
+        assert srv.wait(rid, 120) is None
+        got, _ = srv.poll(rid, N)
+    finally:
+        srv.destroy()
+    ref = _host(bzq.Plan(N, L, R, 0.0, s, N_rho, M, precision="fp64").collision(fd))
+    assert np.array_equal(got, ref)
