@@ -4,8 +4,9 @@ sample of output modes, for the medium (32^3) and large (64^3) workloads.
 
 Calls only `oracle` and `workloads` (seeded inputs).  Run from the repository
 root:  python tests/golden/make_golden.py [name ...]
-Also the 2-D operator (d = 2, Section 5.2) on broadband inputs at N = 64, all
-modes: tests/golden/<name>.npz with Q2 (complex128 N^2, FFT order) and params2
+Also the paper's kernels b5 and b8 (Section 5.3) at N = 128 (paper128_*.npz,
+with the kernel name in `kernel`), and the 2-D operator (d = 2, Section 5.2)
+on broadband inputs at N = 64, all modes: tests/golden/<name>.npz with Q2 (complex128 N^2, FFT order) and params2
 (N, L, R, gamma, N_rho, N_sigma, seed) and the kernel name.
 Each 3-D case writes tests/golden/<name>.npz with arrays
   modes  int64 [n, 3]   sampled output modes k
@@ -56,6 +57,28 @@ BROADBAND = {
 
 # N = 128 on a smooth random Maxwellian mixture (kind 1), gamma = -1
 CASES["huge_mix_gm1"] = (128, 10.0, 5.0, -1.0, 0.50, 8, 14, 12, 1, 16)
+
+
+# the paper's kernels of Section 5.3 at N = 128 (general b = c t^{-1-s}(1-t)^{-r}),
+# broadband input, every |k|_inf <= 1 mode, the corners and 40 random modes
+PAPER_128 = {
+    # name: (N, L, R, gamma, kernel, N_rho, M, seed)
+    "paper128_b5": (128, 10.0, 5.0, 0.0, "b5", 8, 6, 13),
+    "paper128_b8": (128, 10.0, 5.0, -1.0, "b8", 8, 6, 14),
+}
+
+
+def make_paper128(name):
+    N, L, R, gamma, kname, N_rho, M, seed = PAPER_128[name]
+    d = oracle.Discretization(N, L, R, gamma, oracle.PAPER_KERNELS[kname], N_rho, M)
+    f = workloads.broadband_spectrum(N, seed)
+    ks = workloads.survey_mode_sample(N, seed, n_random=40, inf_radius=1)
+    t0 = time.time()
+    q = oracle.collision_direct(f, d, k_out=ks, k_block=16, j_block=16)
+    params = np.array([N, L, R, gamma, 0.0, N_rho, M, seed], dtype=np.float64)
+    np.savez(os.path.join(HERE, name + ".npz"), modes=ks, Q=q, params=params, kind=np.array(2),
+             kernel=np.array(kname))
+    print(f"{name}: {len(ks)} modes in {time.time() - t0:.1f} s", flush=True)
 
 
 # 2-D broadband cases at N = 64: the register pipeline at 16 pair-twos, the
@@ -121,8 +144,10 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CASES) + list(BROADBAND) + list(CASES_2D)):
+    for n in (sys.argv[1:] or list(CASES) + list(BROADBAND) + list(CASES_2D) + list(PAPER_128)):
         if n in CASES_2D:
             make2d(n)
+        elif n in PAPER_128:
+            make_paper128(n)
         else:
             make(n)

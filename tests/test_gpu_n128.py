@@ -175,3 +175,28 @@ def test_n128_tuning_gamma_sibling_and_server(bzq):
         srv.destroy()
     ref = _host(bzq.Plan(N, L, R, 0.0, s, N_rho, M, precision="fp64").collision(fd))
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("weights", ["table", "otf"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["paper128_b5", "paper128_b8"])
+def test_n128_paper_kernels_per_mode(bzq, name, prec, weights):
+    """The kernels b5 and b8 of Section 5.3 (b = c t^{-1-s}(1-t)^{-r}) at N = 128
+    on a broadband input, stored table and weights on the fly, against stored
+    oracle samples (every |k|_inf <= 1 mode, the corners, 40 random modes)."""
+    data = np.load(os.path.join(GOLDEN, name + ".npz"), allow_pickle=False)
+    N, L, R, gamma, _, N_rho, M, seed = data["params"]
+    N, N_rho, M, seed = int(N), int(N_rho), int(M), int(seed)
+    kern = oracle.PAPER_KERNELS[str(data["kernel"])]
+    f = workloads.broadband_spectrum(N, seed)
+    print(f"case {name} prec={prec} weights={weights}", flush=True)
+    plan = bzq.Plan(N, L, R, gamma, 0.0, N_rho, M, precision=prec, weights=weights,
+                    kernel=(kern.c, kern.s, kern.r))
+    Q = _host(plan.collision(_dev(f)))
+    plan.destroy()
+    ks, ref = data["modes"], data["Q"]
+    got = Q[tuple(np.mod(ks, N).T)]
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    worst = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"{name} {prec} {weights}: rel L2 {err:.3e}, worst mode / max|Q| {worst:.3e}", flush=True)
+    assert err < TOL[prec] and worst < TOL[prec]
