@@ -75,7 +75,7 @@ Plan::~Plan() {
 
 size_t Plan::workspace_bytes_per_cell() const {
   const size_t N3 = (size_t)N * N * N;
-  return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * nn * 2 * esz +
+  return (size_t)n1 * nn * 2 * esz + (size_t)P * P * P * esz + (size_t)G * P * a_plane(N) * 2 * esz +
          (size_t)G * P * 2 * nhp * 2 * esz + plane_rows_elems(*this, G) * 2 * esz + (size_t)S_cap * nh * n1 * 16 +
          3 * N3 * 16 +
          (otf ? (size_t)2 * Gw * weight_row(N) * n1 * esz : 0) + 4 * sizeof(int);
@@ -88,7 +88,7 @@ bzq_status workspace_init(Workspace& w, const Plan& p, int cells) {
   w.G = w.S = w.Gw = 0;   // the plan's geometry, whatever its schedule
   w.cs.fc = (size_t)p.n1 * p.nn;
   w.cs.fg = (size_t)p.P * p.P * p.P;
-  w.cs.a = (size_t)p.G * p.P * p.nn;
+  w.cs.a = (size_t)p.G * p.P * a_plane(p.N);
   w.cs.b = (size_t)p.G * p.P * 2 * p.nhp;
   w.cs.qp = (size_t)p.S_cap * p.nh * p.n1;
   w.cs.pc = plane_rows_elems(p, p.G);
@@ -176,7 +176,7 @@ int zfwd_splits(const Plan& p, int zv, int s_target) { return zfwd_splits_for(p,
 void set_chunking(Plan& p) {
   p.esz = p.fp32 ? 4 : 8;
   p.nhp = (p.nh + 15) / 16 * 16;
-  const size_t per_pt = ((size_t)p.P * (p.nn + 2 * p.nhp) + plane_rows_elems(p, 1)) * 2 * p.esz;
+  const size_t per_pt = ((size_t)p.P * (a_plane(p.N) + 2 * p.nhp) + plane_rows_elems(p, 1)) * 2 * p.esz;
   const char* env = std::getenv("BZQ_CHUNK_MB");
   const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
   p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
@@ -347,7 +347,7 @@ bzq_status alloc_scratch(Plan* p) {
   if ((s = workspace_init(p->ws, *p, 1)) != BZQ_OK) return s;
   const size_t n3 = (size_t)N * N * N;
   if ((s = p->grid_scratch.get(&p->gfc, (size_t)p->n1 * nn * 2 * sizeof(double))) != BZQ_OK) return s;
-  if ((s = p->grid_scratch.get(&p->gA, (size_t)N * nn * 2 * sizeof(double))) != BZQ_OK) return s;
+  if ((s = p->grid_scratch.get(&p->gA, (size_t)N * a_plane(N) * 2 * sizeof(double))) != BZQ_OK) return s;
   if (needs_plane_rows(N) &&
       (s = p->grid_scratch.get(&p->gC, (size_t)N * p->n1 * N * 2 * sizeof(double))) != BZQ_OK)
     return s;
@@ -774,7 +774,7 @@ bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat,
   auto need = [&](int g) {
     S = zfwd_splits_for(*p, g, zv, p->s_target);
     Gw = p->otf ? std::min(p->Gw, g) : 0;
-    b_a = al((size_t)g * p->P * p->nn * 2 * esz);
+    b_a = al((size_t)g * p->P * a_plane(p->N) * 2 * esz);
     b_b = al((size_t)g * p->P * 2 * p->nhp * 2 * esz);
     b_c = al(plane_rows_elems(*p, g) * 2 * esz);
     b_q = al((size_t)S * p->nh * p->n1 * 16);
@@ -806,7 +806,7 @@ bzq_status bzq_collision_noalloc(bzq_plan p, const double* f_hat, double* Q_hat,
   w.Vc = p->otf ? at : nullptr;
   w.cs.fc = (size_t)p->n1 * p->nn;
   w.cs.fg = (size_t)p->P * p->P * p->P;
-  w.cs.a = (size_t)G * p->P * p->nn;
+  w.cs.a = (size_t)G * p->P * a_plane(p->N);
   w.cs.b = (size_t)G * p->P * 2 * p->nhp;
   w.cs.qp = (size_t)S * p->nh * p->n1;
   w.cs.pc = plane_rows_elems(*p, G);

@@ -272,10 +272,11 @@ __global__ __launch_bounds__(NT) void k_zinv(const cx<T>* __restrict__ fc, const
       });
   __syncthreads();
   fft_pencils<T, P, +1, NT, K1_TP>(buf, np, RowAddr{LD}, 1, tw);
-  cx<T>* Aout = A + (size_t)pt * P * nn;
+  const int na = a_plane(N);
+  cx<T>* Aout = A + (size_t)pt * P * na;
   for (int e = threadIdx.x; e < np * P; e += NT) {
     const int z = e / np, p = e - z * np;
-    Aout[(size_t)z * nn + c0 + p] = buf[p * LD + z];
+    Aout[(size_t)z * na + c0 + p] = buf[p * LD + z];
   }
 }
 
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_plane(const cx<T>* __restrict__ A, cx<T>
   for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
   for (int i = threadIdx.x; i < P * LD; i += NT) plane[i] = cx<T>{0, 0};
   __syncthreads();
-  const cx<T>* Ain = A + ((size_t)pt * P + z) * nn;
+  const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N);
   for (int c = threadIdx.x; c < nn; c += NT) {
     const int i2 = c / n1, i1 = c - i2 * n1;
     plane[posK(i1, h, P) * LD + posK(i2, h, P)] = Ain[c];
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(SplitCfg<T>::NT) void k_prow_inv(const cx<T>* __res
   for (int i = threadIdx.x; i < RB * LD; i += NT) buf[i] = cx<T>{0, 0};
   __syncthreads();
   // row i1 = r0 + r holds A[i2 n1 + i1] at position posK(i2)
-  const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + r0;
+  const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N) + r0;
   staged_copy<cx<T>, RB * maxN1<P>(), NT>(
       nr * n1, [&](int e) { const int i2 = e / nr; return Ain[(size_t)i2 * n1 + e - i2 * nr]; },
       [&](int e, cx<T> v) { const int i2 = e / nr; buf[(e - i2 * nr) * LD + posK(i2, h, P)] = v; });
@@ -627,9 +628,10 @@ __device__ __forceinline__ void zinv_reg_body(const cx<T>* __restrict__ fc, cons
     v[posKc<N, P>(i3)] = z;
   }
   fft_reg<P, +1>(v);
-  cx<T>* Aout = A + (size_t)pt * P * nn + c;
+  constexpr int na = a_plane(N);
+  cx<T>* Aout = A + (size_t)pt * P * na + c;
 #pragma unroll
-  for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * nn] = v[zi];
+  for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * na] = v[zi];
 }
 
 template <typename T, int N, int P, int NT, int MODE>
@@ -666,9 +668,10 @@ __device__ __forceinline__ void zinv_ingest_body(const double2* __restrict__ f, 
   }
   if (bad && flag) flag[0] = 1;
   fft_reg<P, +1>(v);
+  constexpr int na = a_plane(N);
   cx<T>* Aout = A + c;
 #pragma unroll
-  for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * nn] = v[zi];
+  for (int zi = 0; zi < P; ++zi) Aout[(size_t)zi * na] = v[zi];
 }
 
 template <typename T, int N, int P, int NT>
@@ -703,7 +706,7 @@ __device__ __forceinline__ void plane_reg_body(const cx<T>* __restrict__ A, cx<T
   // rows: inverse along axis 2
   if (tid < Z * n1) {
     const int zz = tid / n1, i1 = tid - zz * n1;
-    const cx<T>* Ain = A + ((size_t)pt * P + z0 + zz) * nn + i1;
+    const cx<T>* Ain = A + ((size_t)pt * P + z0 + zz) * a_plane(N) + i1;
     cx<T> v[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) v[i] = cx<T>{0, 0};
@@ -931,14 +934,14 @@ __device__ __forceinline__ void zinv_half_body(const cx<T>* __restrict__ fcb, un
       },
       u);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) *at32(Ab, c + (unsigned)((2 * j + PAR) * nn)) = u[j];
+  for (int j = 0; j < Q; ++j) *at32(Ab, c + (unsigned)((2 * j + PAR) * a_plane(N))) = u[j];
 }
 
 template <typename T, int N, int P>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_zinv_half(const cx<T>* __restrict__ fc, const double2* __restrict__ ph,
                                                    cx<T>* __restrict__ A, int pair0, CellStrides cs) {
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
-  static_assert((size_t)P * nn * sizeof(cx<T>) < (1ull << 32), "32-bit offsets");
+  static_assert((size_t)P * a_plane(N) * sizeof(cx<T>) < (1ull << 32), "32-bit offsets");
   fc += blockIdx.z * cs.fc;
   A += blockIdx.z * cs.a;
   const int pt = blockIdx.y;
@@ -957,7 +960,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const int k1 = i1 - h + 1, k2 = i2 - h + 1;
   const cx<T> eA12 = cvt<T>(cmul(d2c(phA[-2 * k1]), d2c(phA[PL - 2 * k2])));
   const cx<T> eB12 = cvt<T>(cmul(d2c(phB[-2 * k1]), d2c(phB[PL - 2 * k2])));
-  cx<T>* Ab = A + (size_t)pt * P * nn;
+  cx<T>* Ab = A + (size_t)pt * P * a_plane(N);
   if (par == 0) zinv_half_body<T, N, P, 0>(fc, (unsigned)c, s3, s3 + n1, eA12, eB12, Ab);
   else zinv_half_body<T, N, P, 1>(fc, (unsigned)c, s3, s3 + n1, eA12, eB12, Ab);
 }
@@ -987,7 +990,7 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
   const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
   if constexpr (quarter) {
     if (lq < n1) {
-      const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + lq;
+      const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N) + lq;
       cx<T>* row = sm + lq * LD;
       if (wq == 0) quarter_rows_inv<T, N, P, 0>(Ain, row);
       else if (wq == 1) quarter_rows_inv<T, N, P, 1>(Ain, row);
@@ -995,7 +998,7 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
       else quarter_rows_inv<T, N, P, 3>(Ain, row);
     }
   } else if (l < n1) {
-    const cx<T>* Ain = A + ((size_t)pt * P + z) * nn + l;
+    const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N) + l;
     if (par == 0) half_rows_inv<T, N, P, 0>(Ain, sm + l * LD);
     else half_rows_inv<T, N, P, 1>(Ain, sm + l * LD);
   }
@@ -1234,7 +1237,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   __shared__ cx<T> xch[4 * 2 * 4 * NC];
   const int z = blockIdx.x, pt = blockIdx.y;
   const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
-  const cx<T>* Ain = A + ((size_t)pt * P + z) * nn;
+  const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N);
   cx<T>* Bout = B + ((size_t)pt * P + z) * 2 * (((nn + 1) / 2 + 15) / 16 * 16);
   const T* fz = fgrid + (size_t)z * P * P;
   cx<T> d0[NC / 4];

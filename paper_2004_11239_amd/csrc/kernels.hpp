@@ -34,6 +34,13 @@ struct CellStrides {
 // weights of the next modes c >= nh (valid modes, never read).
 __host__ __device__ constexpr int weight_row(int N) { return ((((N - 1) * (N - 1) + 1) / 2) + 31) / 32 * 32; }
 
+// Pitch of one height z of the first intermediate A[pair-two][z][c] (and of
+// the physical-grid path's A[z][c]): the (N-1)^2 modes of a plane rounded up
+// to 16 complex values, so that every plane starts on a 128-byte line.  With
+// the unpadded pitch every wave of the axis-3 stage writes lines it covers
+// only in part; the entries c >= (N-1)^2 are never written or read.
+__host__ __device__ constexpr int a_plane(int N) { return ((N - 1) * (N - 1) + 15) / 16 * 16; }
+
 // Per-cell device pointers passed by value (at most kMaxCells per launch).
 constexpr int kMaxCells = 64;
 struct PtrPack {

@@ -53,7 +53,7 @@ struct Workspace {
   CellStrides cs{};
   void* fc = nullptr;        // cells x (N-1)^3 complex, compute precision
   void* fgrid = nullptr;     // cells x P^3 real
-  void* A = nullptr;         // cells x G x P x nn complex
+  void* A = nullptr;         // cells x G x P x a_plane(N) complex
   void* B = nullptr;         // cells x G x P x 2 nhp complex
   void* C = nullptr;         // cells x G x P x (N-1) x P complex: plane rows (P = 192 only)
   double* Qpart = nullptr;   // cells x S x nh x n1 complex128
