@@ -43,6 +43,21 @@ constexpr int K1_TP = 16;   // pencils per zinv workgroup
 constexpr int K3_TQ = 8;    // half-spectrum pencils per zfwd workgroup
 constexpr int NT_SMALL = 256;
 
+// Tile of workgroup x (of gx along the grid's x axis) when LG consecutive
+// tiles share the 128-byte lines of their rows.  Workgroups go to the eight
+// XCDs (each with its own L2) in turn by linear id, so the workgroups
+// x = q 8 LG + k + 8 j (j < LG) all run on one XCD at nearly the same time:
+// they take the tiles q 8 LG + k LG + j, the LG tiles of one line.  Within a
+// whole group of 8 LG workgroups this is a bijection (an LG x 8 transpose); a
+// ragged last group keeps the identity map.
+template <int LG>
+__device__ __forceinline__ int xcd_line_tile(int x, int gx) {
+  constexpr int W = 8 * LG;
+  const int q = x / W, r = x - q * W;
+  if (LG == 1 || (q + 1) * W > gx) return x;
+  return q * W + LG * (r & 7) + (r >> 3);
+}
+
 template <int P>
 struct PlaneThreads {
   static constexpr int value = P >= 72 ? 512 : 256;
@@ -349,7 +364,9 @@ __global__ __launch_bounds__(NT) void k_zfwd(const cx<T>* __restrict__ B, const 
   __shared__ cx<T> buf[ROWS * LD];
   __shared__ cx<T> tw[P];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3, nhv = weight_row(N);
-  const int c0 = blockIdx.x * TQ;
+  // a tile's weight segment is TQ sizeof(T) bytes of a 128-byte line
+  constexpr int LG = 128 / (TQ * (int)sizeof(T)) > 1 ? 128 / (TQ * (int)sizeof(T)) : 1;
+  const int c0 = xcd_line_tile<LG>((int)blockIdx.x, (int)gridDim.x) * TQ;
   const int nq = min(TQ, nh - c0);
   const int s = blockIdx.y;
   for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
@@ -877,18 +894,16 @@ struct QuarterRows {
   static constexpr bool value = P == 96;
 };
 
+// rows (axis 2) inverse, class R of the radix-4 split: outputs y = 4j + R of
+// the row whose N-1 modes sit at row[i2] (i2 < N-1) of the LDS plane
 template <typename T, int N, int P, int R>
-__device__ __forceinline__ void quarter_rows_inv(const cx<T>* __restrict__ Ain, cx<T>* row) {
-  constexpr int n1 = N - 1, Q4 = P / 4;
-  cx<T> u[Q4];
+__device__ __forceinline__ void quarter_rows_inv(const cx<T>* row, cx<T>* u) {
   dft_quarter_dif<P, +1, R>(
       [&](int n) -> cx<T> {
         const int i2 = keptK<N, P>(n);
-        return i2 >= 0 ? ld_row(Ain + (size_t)i2 * n1) : cx<T>{0, 0};
+        return i2 >= 0 ? row[i2] : cx<T>{0, 0};
       },
       u);
-#pragma unroll
-  for (int j = 0; j < Q4; ++j) row[4 * j + R] = u[j];
 }
 
 template <typename T, int N, int P, int R>
@@ -989,13 +1004,31 @@ __global__ __launch_bounds__((HalfCfg<P>::NT)) void k_plane_half(const cx<T>* __
   static_assert(!quarter || (C::NT == 256 && n1 <= 64), "quarter rows need four waves and one row per lane");
   const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
   if constexpr (quarter) {
+    // The plane's modes are read from HBM once, coalesced, into the LDS plane
+    // (A[i2 n1 + i1] to row i1, position i2); each of the four waves then
+    // forms its class of every row from LDS and, once all have read their
+    // inputs, writes it over the row in place.  (Each wave reading the rows
+    // from memory itself fetched A about twice over at 64^3.)
+    const cx<T>* Ap = A + ((size_t)pt * P + z) * a_plane(N);
+    staged_copy<cx<T>, nn, C::NT>(
+        nn, [&](int e) { return ld_nt(Ap + e); },
+        [&](int e, cx<T> v) {
+          const int i2 = e / n1;
+          sm[(e - i2 * n1) * LD + i2] = v;
+        });
+    __syncthreads();
+    cx<T> u4[P / 4];
     if (lq < n1) {
-      const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N) + lq;
-      cx<T>* row = sm + lq * LD;
-      if (wq == 0) quarter_rows_inv<T, N, P, 0>(Ain, row);
-      else if (wq == 1) quarter_rows_inv<T, N, P, 1>(Ain, row);
-      else if (wq == 2) quarter_rows_inv<T, N, P, 2>(Ain, row);
-      else quarter_rows_inv<T, N, P, 3>(Ain, row);
+      const cx<T>* row = sm + lq * LD;
+      if (wq == 0) quarter_rows_inv<T, N, P, 0>(row, u4);
+      else if (wq == 1) quarter_rows_inv<T, N, P, 1>(row, u4);
+      else if (wq == 2) quarter_rows_inv<T, N, P, 2>(row, u4);
+      else quarter_rows_inv<T, N, P, 3>(row, u4);
+    }
+    __syncthreads();
+    if (lq < n1) {
+#pragma unroll
+      for (int j = 0; j < P / 4; ++j) sm[lq * LD + 4 * j + wq] = u4[j];
     }
   } else if (l < n1) {
     const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N) + l;
