@@ -406,8 +406,8 @@ bzq_status bzq_plan_weights(bzq_plan p, int pair, double* out);
  * Schedule of a plan: the kernel variant of each pipeline stage {0 modulation
  * and FFT along axis 3, 1 plane transforms and product, 2 FFT along axis 3,
  * weighting and accumulation}: 1 = one whole pencil per lane, 2 = two waves
- * per pencil (stages 0, 1) or the pipelined producer/consumer kernel (stage 2),
- * available for N = 32, 48, 64; 3 (stage 1, FP64 at N = 64 only) = the plane
+ * per pencil (stages 0, 1: N = 32, 48, 64) or the pipelined producer/consumer
+ * kernel (stage 2: N = 16, 24, 32, 48, 64); 3 (stage 1, FP64 at N = 64 only) = the plane
  * taken by column parity in half the LDS; 0 = the default variant.  s_target is the
  * number of workgroups the last stage aims at (512, 1024 or 2048).  Every
  * schedule evaluates eq. realQ; schedules differ in rounding order only

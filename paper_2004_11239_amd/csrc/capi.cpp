@@ -157,7 +157,7 @@ constexpr int kSTargets[3] = {512, 1024, 2048};
 // a nearly empty round (64^3 FP32: 1008 workgroups on 512 slots instead of
 // 1071).  S never exceeds its value without the rounding.
 int zfwd_splits_for(const Plan& p, int G, int zv, int s_target) {
-  const bool pipe = zv == 2 && (p.P == 48 || p.P == 72 || p.P == 96);
+  const bool pipe = zv == 2 && (stage_variants(2, p.P, p.fp32) & 0x4u);
   const bool reg_zfwd = p.fp32 ? p.P <= 96 : p.P <= 48;
   const int tq = pipe ? 32 : reg_zfwd ? (p.fp32 ? 32 : 16) : 8;
   const int pt_group = pipe ? 1 : reg_zfwd ? (p.fp32 ? 2 : 4) : 1;

@@ -2330,22 +2330,28 @@ hipError_t plane_split_t(const void* A, void* B, const void* fgrid, int npt, con
 // FP32 pencils of 72 and 96 points use the two-wave kernels
 // Kernel variants of the three pipeline stages: 1 = one whole pencil per lane
 // (register kernels; LDS kernels where a pencil does not fit the register
-// file), 2 = two waves per pencil (z-inverse, plane) and the pipelined
-// z-forward, for P = 48, 72, 96; 3 = the plane by column parity
+// file), 2 = two waves per pencil (z-inverse, plane: P = 48, 72, 96) and the
+// pipelined z-forward (P = 24 to 96); 3 = the plane by column parity
 // (k_plane_split, FP64 at P = 96 only).  0 selects the default below (the
-// fastest in measurements at 32^3 and 64^3); plans can be autotuned to another.
+// fastest in measurements at 16^3 to 64^3: the pipelined z-forward at 24^3
+// 35.8 vs 41.5 us FP32, 54.6 vs 69.0 us FP64; a tie at 16^3); plans can be
+// autotuned to another.
 template <int P>
 constexpr bool hasTwo() { return P == 48 || P == 72 || P == 96; }
+// lengths with the pipelined z-forward (below P = 48 one producer wave with
+// whole register transforms)
+template <int P>
+constexpr bool hasPipe() { return P == 24 || P == 36 || hasTwo<P>(); }
 template <typename T, int P>
 constexpr int defaultVariant(int stage) {
   if constexpr (sizeof(T) == 4) {
-    if (stage == 2) return P == 48 || P == 72 || P == 96 ? 2 : 1;   // z-forward
+    if (stage == 2) return P == 36 || P == 48 || P == 72 || P == 96 ? 2 : 1;   // z-forward
     if (stage == 1) return P == 96 ? 2 : 1;                          // plane
     return 1;                                                        // z-inverse
   }
   if (stage == 0) return P == 72 || P == 96 ? 2 : 1;                 // FP64 z-inverse
   if (stage == 1) return P == 96 ? 3 : P == 72 ? 2 : 1;               // FP64 plane
-  if (stage == 2) return P == 48 ? 2 : 1;                            // FP64 z-forward
+  if (stage == 2) return P == 36 || P == 48 ? 2 : 1;                 // FP64 z-forward
   return 1;
 }
 
@@ -2396,7 +2402,7 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
                   const void* tw, int N, int pair0, int vpair0, int npt, int S, int first, int variant,
                   const CellStrides& cs, hipStream_t st) {
   const int v = variant ? variant : defaultVariant<T, P>(2);
-  if constexpr (hasTwo<P>())
+  if constexpr (hasPipe<P>())
     if (v == 2) {
       using C = ZfwdPipeCfg<P>;
       constexpr int NN = padN<P>();
@@ -2429,7 +2435,7 @@ int zfwd_blocks_t(int variant) {
   int nb = 0;
   hipError_t e = hipSuccess;
   bool done = false;
-  if constexpr (hasTwo<P>())
+  if constexpr (hasPipe<P>())
     if (v == 2) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &nb, reinterpret_cast<const void*>(&k_zfwd_pipe<T, padN<P>(), P>), ZfwdPipeCfg<P>::NT, 0);
@@ -2769,6 +2775,7 @@ int stage_default_variant(int stage, int P, bool fp32) {
 
 unsigned stage_variants(int stage, int P, bool fp32) {
   if (stage == 1 && P == 96 && !fp32) return 0xEu;   // 3: the plane by column parity (k_plane_split)
+  if (stage == 2 && (P == 24 || P == 36)) return 0x6u;   // 2: the pipelined z-forward
   return (P == 48 || P == 72 || P == 96) ? 0x6u : 0x2u;
 }
 

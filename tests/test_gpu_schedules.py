@@ -7,6 +7,7 @@ same parity bar against the stored oracle samples (32^3 and 64^3) and against
 the oracle evaluated live on a 48^3 sample (ragged radix-3 lengths).
 Tolerances as in test_gpu_parity.py.
 """
+import functools
 import itertools
 import os
 
@@ -137,3 +138,32 @@ def test_autotune_keeps_parity_and_caches(bzq, tmp_path, monkeypatch):
     assert (tmp_path / "tune.txt").exists()
     plan2 = bzq.Plan(*params, precision="fp32")
     assert plan2.autotune(fd, use_cache=True) == sched
+
+
+@functools.lru_cache(maxsize=None)
+def _small_n_reference(N):
+    f = workloads.broadband_spectrum(N, 31 + N)
+    d = oracle.Discretization.power(N, 8.0, 4.0, -1.0, 0.5, 4, 14)
+    return f, oracle.collision_direct(f, d)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("N", [16, 24])
+def test_pipelined_last_stage_small_n_matches_oracle(bzq, N, prec):
+    """The pipelined z-forward at P = 24 and 36 (one producer wave with whole
+    register transforms, one consumer wave): every mode of a broadband input
+    against the oracle evaluated live, per mode and in the L2 norm, beside the
+    whole-pencil kernel; both s_target values that change the split count."""
+    L, R, gamma, s, N_rho, M = 8.0, 4.0, -1.0, 0.5, 4, 14
+    f, ref = _small_n_reference(N)
+    plan = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision=prec)
+    fd = _dev(f)
+    for sched in [(1, 1, 2, 512), (1, 1, 2, 2048), (1, 1, 1, 1024)]:
+        got_s = plan.set_schedule(*sched)
+        assert got_s["zfwd"] == sched[2]
+        Q = _host(plan.collision(fd))
+        err = float(np.linalg.norm(Q - ref) / np.linalg.norm(ref))
+        worst = float(np.max(np.abs(Q - ref)) / np.max(np.abs(ref)))
+        print(f"N={N} {prec} {sched} -> {got_s}: rel L2 {err:.3e}, worst {worst:.3e}", flush=True)
+        assert err < TOL[prec] and worst < TOL[prec], (sched, err, worst)
+    plan.destroy()
