@@ -131,7 +131,7 @@ bzq_status bzq_plan_create_debye(bzq_plan* out, int N, double L, double R, doubl
 
 /* The operator of eq. realQ (Section 4) with its weights evaluated on the fly
  * (beyond the paper): no table of J N^3 / 2 weights is stored or built.  Before the last stage of
- * each block of pairs (at most 128 MiB of weights, or $BZQ_OTF_MB), a kernel
+ * each block of pairs (at most 256 MiB of weights, or $BZQ_OTF_MB), a kernel
  * evaluates that block's weights from the Funk-Hecke series of the exact
  * weight of eq. FF,
  *   Re(e^{-ix} F) = sum_{l even} (2l+1) (-1)^{l/2} mu_l j_l(a|k|) P_l(k.sigma/|k|),

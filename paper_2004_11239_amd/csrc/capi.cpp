@@ -181,9 +181,11 @@ void set_chunking(Plan& p) {
   const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
   p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
   // weights on the fly: pair-twos per generated block of weights (below
-  // BZQ_OTF_MB, default 128 MiB)
+  // BZQ_OTF_MB, default 256 MiB: at 64^3 FP32 blocks of 32 / 64 / 128 MiB took
+  // 27.9 / 24.8 / 23.8 ms per evaluation, 192 MiB and more 22.9 ms, since every
+  // block is one more last-stage launch over fewer pair-twos)
   const char* envw = std::getenv("BZQ_OTF_MB");
-  const size_t capw = (envw && std::atoll(envw) > 0 ? (size_t)std::atoll(envw) : 128ull) << 20;
+  const size_t capw = (envw && std::atoll(envw) > 0 ? (size_t)std::atoll(envw) : 256ull) << 20;
   const size_t per_w = (size_t)2 * weight_row(p.N) * p.n1 * p.esz;
   p.Gw = p.otf ? (int)std::max<size_t>(1, std::min<size_t>((size_t)p.G, capw / per_w)) : 0;
   p.S = zfwd_splits(p, effective_variant(p, 2), p.s_target);

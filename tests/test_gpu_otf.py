@@ -155,3 +155,23 @@ def test_otf_batch_bitwise_equals_solo(bzq):
     for a, b in zip(solo, outs):
         assert np.array_equal(a, _host(b))
     batch.destroy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_otf_many_small_blocks_match_one_block(bzq, prec, monkeypatch):
+    """Weights generated in many small blocks (BZQ_OTF_MB = 16: 14 blocks at
+    32^3 FP64, the last one ragged) give the same Q as the default block size,
+    to the rounding of the regrouped FP64 sums."""
+    N, L, R, gamma, s, N_rho, M = 32, 8.0, 4.0, -1.0, 0.5, 32, 110
+    f = workloads.broadband_spectrum(N, 77)
+    fd = _dev(f)
+    ref_plan = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision=prec, weights="otf")
+    ref = _host(ref_plan.collision(fd))
+    ref_plan.destroy()
+    monkeypatch.setenv("BZQ_OTF_MB", "16")
+    plan = bzq.Plan(N, L, R, gamma, s, N_rho, M, precision=prec, weights="otf")
+    got = _host(plan.collision(fd))
+    plan.destroy()
+    err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"{prec}: many blocks vs one, worst mode / max|Q| {err:.3e}", flush=True)
+    assert err < 1e-12
