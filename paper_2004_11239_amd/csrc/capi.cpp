@@ -169,8 +169,12 @@ int zfwd_splits_for(const Plan& p, int G, int zv, int s_target) {
 }
 int zfwd_splits(const Plan& p, int zv, int s_target) { return zfwd_splits_for(p, p.G, zv, s_target); }
 
-// Chunking of the pair loop: the two pipeline intermediates stay below 1 GiB
-// per cell (one chunk per evaluation up to N = 32); the splits S of the last
+// Chunking of the pair loop: the pipeline intermediates stay below 2 GiB per
+// cell (BZQ_CHUNK_MB; one chunk per evaluation up to N = 32 in both
+// precisions).  Fewer, larger chunks mean fewer launches and fewer round trips
+// of the last stage's partial sums: at 64^3 1024 / 2048 / 4096 MiB took
+// 19.32 / 19.02 / 19.00 ms per FP32 evaluation, 42.85 / 41.44 / 40.65 ms per
+// FP64 one.  The splits S of the last
 // stage give about s_target workgroups (enough to fill the chip) but no more
 // than there are groups of pair-twos.  S_cap bounds S over every schedule.
 void set_chunking(Plan& p) {
@@ -178,16 +182,20 @@ void set_chunking(Plan& p) {
   p.nhp = (p.nh + 15) / 16 * 16;
   const size_t per_pt = ((size_t)p.P * (a_plane(p.N) + 2 * p.nhp) + plane_rows_elems(p, 1)) * 2 * p.esz;
   const char* env = std::getenv("BZQ_CHUNK_MB");
-  const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 1024ull) << 20;
+  const size_t cap = (env && std::atoll(env) > 0 ? (size_t)std::atoll(env) : 2048ull) << 20;
   p.G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p.npt, cap / per_pt));
   // weights on the fly: pair-twos per generated block of weights (below
   // BZQ_OTF_MB, default 256 MiB: at 64^3 FP32 blocks of 32 / 64 / 128 MiB took
   // 27.9 / 24.8 / 23.8 ms per evaluation, 192 MiB and more 22.9 ms, since every
-  // block is one more last-stage launch over fewer pair-twos)
+  // block is one more last-stage launch over fewer pair-twos), and at most half
+  // of the pair-twos, so that a plan with weights on the fly never holds as
+  // many weight bytes as the table it replaces (at 32^3 one block would hold
+  // all of them)
   const char* envw = std::getenv("BZQ_OTF_MB");
   const size_t capw = (envw && std::atoll(envw) > 0 ? (size_t)std::atoll(envw) : 256ull) << 20;
   const size_t per_w = (size_t)2 * weight_row(p.N) * p.n1 * p.esz;
-  p.Gw = p.otf ? (int)std::max<size_t>(1, std::min<size_t>((size_t)p.G, capw / per_w)) : 0;
+  const size_t half = ((size_t)p.npt + 1) / 2;
+  p.Gw = p.otf ? (int)std::max<size_t>(1, std::min<size_t>(std::min<size_t>((size_t)p.G, capw / per_w), half)) : 0;
   p.S = zfwd_splits(p, effective_variant(p, 2), p.s_target);
   p.S_cap = p.S;
   for (int v = 1; v <= 2; ++v)
