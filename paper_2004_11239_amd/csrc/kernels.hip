@@ -50,6 +50,16 @@ constexpr int NT_SMALL = 256;
 // they take the tiles q 8 LG + k LG + j, the LG tiles of one line.  Within a
 // whole group of 8 LG workgroups this is a bijection (an LG x 8 transpose); a
 // ragged last group keeps the identity map.
+// Pencil blocks along the grid's x axis for the register z-inverse kernels:
+// rounded up to a multiple of 8 when that adds at most an eighth, so that
+// linear id mod 8 (the XCD) is the block index mod 8 for every pair-two and
+// each XCD reads one eighth of the compact spectrum, which then stays in its
+// L2 (64^3: 63 -> 64 blocks; the extra block's lanes have no pencil and exit).
+__host__ __forceinline__ int xcd_pencil_blocks(int gx) {
+  const int gp = (gx + 7) / 8 * 8;
+  return gp - gx <= gx / 8 ? gp : gx;
+}
+
 template <int LG>
 __device__ __forceinline__ int xcd_line_tile(int x, int gx) {
   constexpr int W = 8 * LG;
@@ -2268,7 +2278,7 @@ hipError_t zinv_reg_t(const void* fc, const double* ph, void* A, int pair0, int 
                       const CellStrides& cs, hipStream_t st) {
   constexpr int nn = (N - 1) * (N - 1);
   constexpr int NT = 64;
-  dim3 grid((nn + NT - 1) / NT, npt, cs.cells);
+  dim3 grid(xcd_pencil_blocks((nn + NT - 1) / NT), npt, cs.cells);
   if (mode == ZINV_PAIRS)
     hipLaunchKernelGGL((k_zinv_reg<T, N, P, NT, ZINV_PAIRS>), grid, dim3(NT), 0, st, (const cx<T>*)fc,
                        (const double2*)ph, (cx<T>*)A, pair0, cs);
@@ -2362,7 +2372,7 @@ hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int
   if constexpr (hasTwo<P>())
     if (v == 2 && N == padN<P>() && mode == ZINV_PAIRS) {
       constexpr int NN = padN<P>(), nn = (NN - 1) * (NN - 1);
-      dim3 grid((nn + 63) / 64, npt, cs.cells);
+      dim3 grid(xcd_pencil_blocks((nn + 63) / 64), npt, cs.cells);
       hipLaunchKernelGGL((k_zinv_half<T, NN, P>), grid, dim3(128), 0, st, (const cx<T>*)fc, (const double2*)ph,
                          (cx<T>*)A, pair0, cs);
       return hipGetLastError();
