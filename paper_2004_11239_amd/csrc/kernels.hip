@@ -50,11 +50,12 @@ constexpr int NT_SMALL = 256;
 // they take the tiles q 8 LG + k LG + j, the LG tiles of one line.  Within a
 // whole group of 8 LG workgroups this is a bijection (an LG x 8 transpose); a
 // ragged last group keeps the identity map.
-// Pencil blocks along the grid's x axis for the register z-inverse kernels:
+// Pencil blocks along the grid's x axis for the z-inverse kernels:
 // rounded up to a multiple of 8 when that adds at most an eighth, so that
 // linear id mod 8 (the XCD) is the block index mod 8 for every pair-two and
 // each XCD reads one eighth of the compact spectrum, which then stays in its
-// L2 (64^3: 63 -> 64 blocks; the extra block's lanes have no pencil and exit).
+// L2 (64^3: 63 -> 64 blocks of 64 pencils, 128^3: 1009 -> 1016 blocks of 16;
+// the padding blocks have no pencils and exit).
 __host__ __forceinline__ int xcd_pencil_blocks(int gx) {
   const int gp = (gx + 7) / 8 * 8;
   return gp - gx <= gx / 8 ? gp : gx;
@@ -255,6 +256,7 @@ __global__ __launch_bounds__(NT) void k_zinv(const cx<T>* __restrict__ fc, const
   __shared__ double2 e3[2][MN1];
   const int n1 = N - 1, h = N / 2, nn = n1 * n1, PL = 2 * N - 3;
   const int c0 = blockIdx.x * K1_TP;
+  if (c0 >= nn) return;   // a block of the grid's padding (xcd_pencil_blocks)
   const int np = min(K1_TP, nn - c0);
   const int pt = blockIdx.y;
   for (int i = threadIdx.x; i < P; i += NT) tw[i] = twg[i];
@@ -2382,7 +2384,7 @@ hipError_t zinv_t(const void* fc, const double* ph, void* A, const void* tw, int
   if constexpr (RegFit<T, P>::value && isGrid<P>() && sizeof(T) == 8)
     if (N == P) return zinv_reg_t<T, P, P>(fc, ph, A, pair0, npt, mode, cs, st);
   const int nn = (N - 1) * (N - 1);
-  dim3 grid((nn + K1_TP - 1) / K1_TP, npt, cs.cells);
+  dim3 grid(xcd_pencil_blocks((nn + K1_TP - 1) / K1_TP), npt, cs.cells);
   hipLaunchKernelGGL((k_zinv<T, P, NT_SMALL>), grid, dim3(NT_SMALL), 0, st, (const cx<T>*)fc,
                      (const double2*)ph, (cx<T>*)A, (const cx<T>*)tw, N, pair0, mode, cs);
   return hipGetLastError();
