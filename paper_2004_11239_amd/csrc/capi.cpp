@@ -424,6 +424,10 @@ bzq_status build_plan(Plan* p, hipStream_t st) {
         ph[o + 1] = (double)sinl(ang);
       }
   }
+  // the default workgroup target of the last stage: 512 at P = 96 (64^3,
+  // pipelined z-forward: 3.75 vs 3.92 ms FP32, 8.11 vs 8.54 ms FP64 per
+  // evaluation against 1024), 1024 elsewhere (48^3 FP32: 1.14 vs 1.39 ms)
+  p->s_target = P == 96 ? 512 : 1024;
   // residency of the z-forward kernels on this device (sizes the splits S)
   {
     int dev = 0;

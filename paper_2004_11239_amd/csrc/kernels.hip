@@ -1613,27 +1613,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
-template <typename T, int N, int P, int PAR>
-__device__ __forceinline__ void zfwd_half_fft(const cx<T>* __restrict__ Bin, cx<T> (*Wp)[64], int r) {
-  constexpr int n1 = N - 1, nn = n1 * n1, Q = P / 2;
-  constexpr int nhp = ((nn + 1) / 2 + 15) / 16 * 16;
-  cx<T> u[Q];
-  dft_half_dif<P, -1, PAR>([&](int n) -> cx<T> { return Bin[(size_t)n * 2 * nhp]; }, u);
-#pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    const int i3 = keptK<N, P>(2 * j + PAR);
-    if (i3 >= 0) Wp[i3][r] = u[j];
-  }
-}
-
 // Forward FFT along axis 3 with the weighting and accumulation overlapped:
 // producer waves transform the tile's 2 TQ pencils (TQ half-spectrum pencils
 // and their mirrors) of pair-two i+1 into one half of a double-buffered LDS
 // tile while consumer waves apply the weights of pair-two i from the other
 // half and keep their FP64 sums in registers (and fetch the weights of
-// pair-two i+1).  One barrier per pair-two.  A workgroup owns tile
+// pair-two i+1).  One barrier per pair-two (two with two producer waves,
+// which hand each other half of their transforms).  A workgroup owns tile
 // blockIdx.x and the pair-twos s, s + S, s + 2S ... (s = blockIdx.y).
-// Producers: two waves of parities 0/1 (P > 48, dft_half_dif) or one wave
+// Producers: two waves splitting each transform by one decimation step in
+// time (P > 48, zfwd_dit_*: each wave loads half of the heights), or one wave
 // with whole register transforms.
 template <int P>
 struct ZfwdPipeCfg {
@@ -1646,18 +1635,66 @@ struct ZfwdPipeCfg {
   static constexpr int NT = 64 * (PW + CW);
 };
 
-template <typename T, int N, int P, int PAR>
+// one producer wave (P <= 48): the whole transform of the lane's pencil
+template <typename T, int N, int P>
 __device__ __forceinline__ void zfwd_produce(const cx<T>* __restrict__ Bin, cx<T> (*Wb)[64], int r) {
-  if constexpr (PAR < 0) {
-    constexpr int nhp = (((N - 1) * (N - 1) + 1) / 2 + 15) / 16 * 16;
-    cx<T> v[P];
+  constexpr int nhp = (((N - 1) * (N - 1) + 1) / 2 + 15) / 16 * 16;
+  cx<T> v[P];
 #pragma unroll
-    for (int z = 0; z < P; ++z) v[z] = Bin[(size_t)z * 2 * nhp];
-    fft_reg<P, -1>(v);
+  for (int z = 0; z < P; ++z) v[z] = Bin[(size_t)z * 2 * nhp];
+  fft_reg<P, -1>(v);
 #pragma unroll
-    for (int i3 = 0; i3 < N - 1; ++i3) Wb[i3][r] = v[posKc<N, P>(i3)];
+  for (int i3 = 0; i3 < N - 1; ++i3) Wb[i3][r] = v[posKc<N, P>(i3)];
+}
+
+// Two producer waves by one decimation step in time (P > 48).  Wave W loads
+// the heights n = 2m + W of its pencil (P/2 of them) and forms
+// F_W = DFT_{P/2}; wave 1 scales F_1[k] by w^k (w = e^{-2 pi i / P}), so that
+// X[k] = F_0[k] + F_1[k] and X[k + P/2] = F_0[k] - F_1[k].  Wave 0 owns the
+// kept outputs k < N/2, wave 1 the kept k + P/2 > P - N/2.  Before a
+// workgroup barrier each wave writes into the other's output slots the half
+// that one needs (zfwd_dit_send); after it each reads its slots and writes
+// its outputs over them (zfwd_dit_finish).
+template <typename T, int N, int P, int W>
+__device__ __forceinline__ void zfwd_dit_load(const cx<T>* __restrict__ Bin, cx<T>* u) {
+  constexpr int nhp = (((N - 1) * (N - 1) + 1) / 2 + 15) / 16 * 16, Q = P / 2;
+#pragma unroll
+  for (int m = 0; m < Q; ++m) u[m] = Bin[(size_t)(2 * m + W) * 2 * nhp];
+  fft_reg<Q, -1>(u);
+  if constexpr (W == 1) {
+#pragma unroll
+    for (int k = 1; k < Q; ++k) u[k] = twiddle_mul<P, -1>(u[k], k);
+  }
+}
+
+template <typename T, int N, int P, int W>
+__device__ __forceinline__ void zfwd_dit_send(const cx<T>* u, cx<T> (*Wb)[64], int r) {
+  constexpr int Q = P / 2, h = N / 2;
+  static_assert(Q - h + 1 > 0 && h <= Q, "kept outputs of each half");
+  if constexpr (W == 1) {
+#pragma unroll
+    for (int k = 0; k < h; ++k) Wb[keptK<N, P>(k)][r] = u[k];
   } else {
-    zfwd_half_fft<T, N, P, PAR>(Bin, Wb, r);
+#pragma unroll
+    for (int k = Q - h + 1; k < Q; ++k) Wb[keptK<N, P>(k + Q)][r] = u[k];
+  }
+}
+
+template <typename T, int N, int P, int W>
+__device__ __forceinline__ void zfwd_dit_finish(const cx<T>* u, cx<T> (*Wb)[64], int r) {
+  constexpr int Q = P / 2, h = N / 2;
+  if constexpr (W == 0) {
+#pragma unroll
+    for (int k = 0; k < h; ++k) {
+      cx<T>& w = Wb[keptK<N, P>(k)][r];
+      w = cadd(u[k], w);
+    }
+  } else {
+#pragma unroll
+    for (int k = Q - h + 1; k < Q; ++k) {
+      cx<T>& w = Wb[keptK<N, P>(k + Q)][r];
+      w = csub(w, u[k]);
+    }
   }
 }
 
@@ -1698,14 +1735,22 @@ __device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, cons
     const int cpen = r < TQ ? c0 + q : nn - 1 - (c0 + q);
     const int slot = r < TQ ? c0 + q : nhp + c0 + q;
     for (int i = 0; i <= nmine; ++i) {
+      cx<T> u[PW == 2 ? P / 2 : 1];   // this wave's half transform (PW == 2)
+      const int b = i & 1;
       if (i < nmine) {
-        const int pt = s + i * S, b = i & 1;
+        const int pt = s + i * S;
         const int jA = pair0 + 2 * pt;
         if (have) {
           const cx<T>* Bin = B + (size_t)pt * P * 2 * nhp + slot;
-          if constexpr (PW == 1) zfwd_produce<T, N, P, -1>(Bin, W[b], r);
-          else if (wv == 0) zfwd_produce<T, N, P, 0>(Bin, W[b], r);
-          else zfwd_produce<T, N, P, 1>(Bin, W[b], r);
+          if constexpr (PW == 1) {
+            zfwd_produce<T, N, P>(Bin, W[b], r);
+          } else if (wv == 0) {
+            zfwd_dit_load<T, N, P, 0>(Bin, u);
+            zfwd_dit_send<T, N, P, 0>(u, W[b], r);
+          } else {
+            zfwd_dit_load<T, N, P, 1>(Bin, u);
+            zfwd_dit_send<T, N, P, 1>(u, W[b], r);
+          }
         }
         if (wv == 0) {
           if (r < TQ && have) {
@@ -1726,6 +1771,13 @@ __device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, cons
             const double2* pj = ph + (size_t)(jA + w) * 3 * PL + (N - 2);
             E3[b][w][i3] = pj[2 * PL + i3 - h + 1];
           }
+        }
+      }
+      if constexpr (PW == 2) {
+        lds_barrier();   // the halves handed over are in LDS
+        if (i < nmine && have) {
+          if (wv == 0) zfwd_dit_finish<T, N, P, 0>(u, W[b], r);
+          else zfwd_dit_finish<T, N, P, 1>(u, W[b], r);
         }
       }
       lds_barrier();
@@ -1776,6 +1828,7 @@ __device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, cons
           vb[bb] = ok ? VB[vi] : T(0);
         }
       }
+      if constexpr (PW == 2) lds_barrier();   // the producers' hand-over
       lds_barrier();
     }
     add_partials<OPT>(Qpart, accx, accy, first, [&](int bb) -> long long {
@@ -2363,7 +2416,7 @@ constexpr int defaultVariant(int stage) {
   }
   if (stage == 0) return P == 72 || P == 96 ? 2 : 1;                 // FP64 z-inverse
   if (stage == 1) return P == 96 ? 3 : P == 72 ? 2 : 1;               // FP64 plane
-  if (stage == 2) return P == 36 || P == 48 ? 2 : 1;                 // FP64 z-forward
+  if (stage == 2) return P == 36 || P == 48 || P == 96 ? 2 : 1;      // FP64 z-forward
   return 1;
 }
 
