@@ -1204,24 +1204,35 @@ __device__ __forceinline__ void split_phase(const cx<T>* __restrict__ Ain0, cx<T
                                             cx<T>* d0) {
   constexpr int n1 = N - 1, nn = n1 * n1, NC = P / 2, LDC = NC + 1, Q4 = P / 4, Q8 = NC / 4;
   constexpr int nhp = ((nn + 1) / 2 + 15) / 16 * 16, cmid = (nn - 1) / 2;
-  // rows, inverse: classes PH (wave 0) and PH + 2 (wave 1) of the P-point split
+  // rows, inverse: classes PH (wave 0) and PH + 2 (wave 1) of the P-point
+  // split.  The plane's modes are read once per phase, coalesced, by all four
+  // waves into LDS (row i1 at sm[i1 n1 ...], over the half plane and the
+  // exchange buffer, which follow each other); the two waves form their
+  // classes from there and write them into the half plane once every row has
+  // been read.  (Each of the two waves reading the rows from memory itself
+  // fetched A twice per phase.)
+  staged_copy<cx<T>, nn, 256>(
+      nn, [&](int e) { return Ain0[e]; },
+      [&](int e, cx<T> v) {
+        const int i2 = e / n1;
+        sm[(e - i2 * n1) * n1 + i2] = v;
+      });
+  __syncthreads();
+  cx<T> u[Q4];
   if (wq < 2 && lq < n1) {
-    cx<T> u[Q4];
-    const cx<T>* Ain = Ain0 + lq;
+    const cx<T>* rin = sm + lq * n1;
     auto get = [&](int n) -> cx<T> {
       const int i2 = keptK<N, P>(n);
-      return i2 >= 0 ? ld_row(Ain + (size_t)i2 * n1) : cx<T>{0, 0};
+      return i2 >= 0 ? rin[i2] : cx<T>{0, 0};
     };
+    if (wq == 0) dft_quarter_dif<P, +1, PH>(get, u);
+    else dft_quarter_dif<P, +1, PH + 2>(get, u);
+  }
+  __syncthreads();
+  if (wq < 2 && lq < n1) {
     cx<T>* row = sm + lq * LDC;
-    if (wq == 0) {
-      dft_quarter_dif<P, +1, PH>(get, u);
 #pragma unroll
-      for (int j = 0; j < Q4; ++j) row[2 * j] = u[j];
-    } else {
-      dft_quarter_dif<P, +1, PH + 2>(get, u);
-#pragma unroll
-      for (int j = 0; j < Q4; ++j) row[2 * j + 1] = u[j];
-    }
+    for (int j = 0; j < Q4; ++j) row[2 * j + wq] = u[j];
   }
   __syncthreads();
   // columns c (y = 2c + PH), class wq of the points along axis 1
@@ -1278,8 +1289,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   A += blockIdx.z * cs.a;
   B += blockIdx.z * cs.b;
   fgrid += blockIdx.z * cs.fg;
-  __shared__ cx<T> sm[n1 * LDC];
-  __shared__ cx<T> xch[4 * 2 * 4 * NC];
+  // the half plane, then the exchange buffer, in one array: together they also
+  // hold the plane's n1 x n1 modes staged at the start of each phase
+  __shared__ cx<T> lds[n1 * LDC + 4 * 2 * 4 * NC];
+  static_assert(n1 * n1 <= n1 * LDC + 4 * 2 * 4 * NC, "staged modes fit");
+  cx<T>* sm = lds;
+  cx<T>* xch = lds + n1 * LDC;
   const int z = blockIdx.x, pt = blockIdx.y;
   const int wq = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lq = (int)threadIdx.x & 63;
   const cx<T>* Ain = A + ((size_t)pt * P + z) * a_plane(N);
