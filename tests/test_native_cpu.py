@@ -187,3 +187,21 @@ def test_otf_plan_limits_without_device(lib):
         h.value = 1234
         assert f(ctypes.byref(h), *args, None) == code, args
         assert h.value is None
+
+
+def test_chunk_cap_bounds_the_workspace(lib, monkeypatch):
+    """The pipeline's chunk of pairs is sized so that its intermediates stay
+    below BZQ_CHUNK_MB (default 2048 MB): at 64^3 FP32 one pair-two's A and B
+    take 96 x (3984 + 2 x 1984) x 8 bytes, so halving the cap takes about
+    1 GB (175 or 176 pair-twos) off the device bytes of a request."""
+    rb = lib.bzq_request_device_bytes
+    rb.restype = ctypes.c_size_t
+    rb.argtypes = [ctypes.c_int, ctypes.c_int]
+    monkeypatch.delenv("BZQ_CHUNK_MB", raising=False)
+    default = rb(64, 1)
+    monkeypatch.setenv("BZQ_CHUNK_MB", "2048")
+    assert rb(64, 1) == default
+    monkeypatch.setenv("BZQ_CHUNK_MB", "1024")
+    half = rb(64, 1)
+    per_pt = 96 * (3984 + 2 * 1984) * 8
+    assert 175 * per_pt <= default - half <= 177 * per_pt, (default, half)
