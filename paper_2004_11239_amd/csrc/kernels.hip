@@ -43,32 +43,6 @@ constexpr int K1_TP = 16;   // pencils per zinv workgroup
 constexpr int K3_TQ = 8;    // half-spectrum pencils per zfwd workgroup
 constexpr int NT_SMALL = 256;
 
-// Tile of workgroup x (of gx along the grid's x axis) when LG consecutive
-// tiles share the 128-byte lines of their rows.  Workgroups go to the eight
-// XCDs (each with its own L2) in turn by linear id, so the workgroups
-// x = q 8 LG + k + 8 j (j < LG) all run on one XCD at nearly the same time:
-// they take the tiles q 8 LG + k LG + j, the LG tiles of one line.  Within a
-// whole group of 8 LG workgroups this is a bijection (an LG x 8 transpose); a
-// ragged last group keeps the identity map.
-// Pencil blocks along the grid's x axis for the z-inverse kernels:
-// rounded up to a multiple of 8 when that adds at most an eighth, so that
-// linear id mod 8 (the XCD) is the block index mod 8 for every pair-two and
-// each XCD reads one eighth of the compact spectrum, which then stays in its
-// L2 (64^3: 63 -> 64 blocks of 64 pencils, 128^3: 1009 -> 1016 blocks of 16;
-// the padding blocks have no pencils and exit).
-__host__ __forceinline__ int xcd_pencil_blocks(int gx) {
-  const int gp = (gx + 7) / 8 * 8;
-  return gp - gx <= gx / 8 ? gp : gx;
-}
-
-template <int LG>
-__device__ __forceinline__ int xcd_line_tile(int x, int gx) {
-  constexpr int W = 8 * LG;
-  const int q = x / W, r = x - q * W;
-  if (LG == 1 || (q + 1) * W > gx) return x;
-  return q * W + LG * (r & 7) + (r >> 3);
-}
-
 template <int P>
 struct PlaneThreads {
   static constexpr int value = P >= 72 ? 512 : 256;

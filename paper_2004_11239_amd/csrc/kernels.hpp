@@ -41,6 +41,32 @@ __host__ __device__ constexpr int weight_row(int N) { return ((((N - 1) * (N - 1
 // only in part; the entries c >= (N-1)^2 are never written or read.
 __host__ __device__ constexpr int a_plane(int N) { return ((N - 1) * (N - 1) + 15) / 16 * 16; }
 
+// Launch shapes aware of the eight XCDs, each with its own L2: workgroups go
+// to the XCDs in turn by linear id.
+//
+// Pencil blocks along the grid's x axis for the z-inverse kernels: rounded up
+// to a multiple of 8 when that adds at most an eighth, so that linear id mod
+// 8 (the XCD) is the block index mod 8 for every pair-two and each XCD reads
+// one eighth of the compact spectrum, which then stays in its L2 (64^3:
+// 63 -> 64 blocks of 64 pencils, 128^3: 1009 -> 1016 blocks of 16; the
+// padding blocks have no pencils and exit).
+__host__ __device__ constexpr int xcd_pencil_blocks(int gx) {
+  return ((gx + 7) / 8 * 8) - gx <= gx / 8 ? (gx + 7) / 8 * 8 : gx;
+}
+
+// Tile of workgroup x (of gx along the grid's x axis) when LG consecutive
+// tiles share the 128-byte lines of their rows: the workgroups
+// x = q 8 LG + k + 8 j (j < LG) all run on one XCD at nearly the same time
+// and take the tiles q 8 LG + k LG + j, the LG tiles of one line.  Within a
+// whole group of 8 LG workgroups this is a bijection (an LG x 8 transpose); a
+// ragged last group keeps the identity map.
+template <int LG>
+__host__ __device__ constexpr int xcd_line_tile(int x, int gx) {
+  return (LG == 1 || (x / (8 * LG) + 1) * 8 * LG > gx)
+             ? x
+             : x / (8 * LG) * 8 * LG + LG * ((x % (8 * LG)) & 7) + ((x % (8 * LG)) >> 3);
+}
+
 // Per-cell device pointers passed by value (at most kMaxCells per launch).
 constexpr int kMaxCells = 64;
 struct PtrPack {

@@ -119,6 +119,11 @@ def test_fft_building_blocks_on_host(tmp_path):
     assert r.returncode == 0, r.stdout
 
 
+def test_xcd_launch_shapes_on_host(tmp_path):
+    r = _compile_and_run("xcd_host_check.cpp", [], tmp_path)
+    assert r.returncode == 0, r.stdout
+
+
 def test_plan_quadrature_on_host(tmp_path):
     r = _compile_and_run("quad_host_check.cpp", [os.path.join(CSRC, "quadrature.cpp")], tmp_path)
     assert r.returncode == 0, r.stdout
