@@ -1611,12 +1611,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // which hand each other half of their transforms).  A workgroup owns tile
 // blockIdx.x and the pair-twos s, s + S, s + 2S ... (s = blockIdx.y).
 // Producers: two waves splitting each transform by one decimation step in
-// time (P > 48, zfwd_dit_*: each wave loads half of the heights), or one wave
-// with whole register transforms.
-template <int P>
+// time (P > 48, and FP64 at P = 48; zfwd_dit_*: each wave loads half of the
+// heights), or one wave with whole register transforms (FP32 at P <= 48: at
+// 32^3 two waves took 0.113 ms against 0.087, while in FP64 they took 0.165
+// against 0.176).
+template <typename T, int P>
 struct ZfwdPipeCfg {
   static constexpr int TQ = 32;
-  static constexpr int PW = P > 48 ? 2 : 1;
+  static constexpr int PW = P > 48 || (P == 48 && sizeof(T) == 8) ? 2 : 1;
   // consumer waves: one at P = 48 (smaller workgroups, more of them per CU:
   // 0.113 -> 0.098 ms at 32^3 FP32), two at P = 72, 96 (one or three: 1.5x
   // slower at 64^3)
@@ -1690,8 +1692,8 @@ __device__ __forceinline__ void zfwd_dit_finish(const cx<T>* u, cx<T> (*Wb)[64],
 // LDS of one k_zfwd_pipe workgroup
 template <typename T, int N, int P>
 struct ZfwdPipeLds {
-  cx<T> W[2][N - 1][2 * ZfwdPipeCfg<P>::TQ];
-  double2 E12[2][2][ZfwdPipeCfg<P>::TQ];
+  cx<T> W[2][N - 1][2 * ZfwdPipeCfg<T, P>::TQ];
+  double2 E12[2][2][ZfwdPipeCfg<T, P>::TQ];
   double2 E3[2][2][N - 1];
   double CPV[2][2];
 };
@@ -1703,7 +1705,7 @@ __device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, cons
                                                const double2* __restrict__ ph, const double* __restrict__ cp,
                                                double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
                                                int first, int bx, int s, ZfwdPipeLds<T, N, P>& L, const unsigned tx) {
-  using C = ZfwdPipeCfg<P>;
+  using C = ZfwdPipeCfg<T, P>;
   constexpr int TQ = C::TQ, PW = C::PW, NC = 64 * C::CW;
   constexpr int n1 = N - 1, h = N / 2, nn = n1 * n1, nh = (nn + 1) / 2, PL = 2 * N - 3, nhv = weight_row(N);
   constexpr int nhp = (nh + 15) / 16 * 16;
@@ -1830,7 +1832,7 @@ __device__ __forceinline__ void zfwd_pipe_body(const cx<T>* __restrict__ B, cons
 }
 
 template <typename T, int N, int P>
-__global__ __launch_bounds__((ZfwdPipeCfg<P>::NT)) void k_zfwd_pipe(
+__global__ __launch_bounds__((ZfwdPipeCfg<T, P>::NT)) void k_zfwd_pipe(
     const cx<T>* __restrict__ B, const T* __restrict__ V, const double2* __restrict__ ph,
     const double* __restrict__ cp, double2* __restrict__ Qpart, int pair0, int vpair0, int npt, int S,
     int first, CellStrides cs) {
@@ -2458,7 +2460,7 @@ hipError_t zfwd_t(const void* B, const void* V, const double* ph, const double* 
   const int v = variant ? variant : defaultVariant<T, P>(2);
   if constexpr (hasPipe<P>())
     if (v == 2) {
-      using C = ZfwdPipeCfg<P>;
+      using C = ZfwdPipeCfg<T, P>;
       constexpr int NN = padN<P>();
       constexpr int nh = ((NN - 1) * (NN - 1) + 1) / 2;
       dim3 grid((nh + C::TQ - 1) / C::TQ, S, cs.cells);
@@ -2492,7 +2494,7 @@ int zfwd_blocks_t(int variant) {
   if constexpr (hasPipe<P>())
     if (v == 2) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void*>(&k_zfwd_pipe<T, padN<P>(), P>), ZfwdPipeCfg<P>::NT, 0);
+          &nb, reinterpret_cast<const void*>(&k_zfwd_pipe<T, padN<P>(), P>), ZfwdPipeCfg<T, P>::NT, 0);
       done = true;
     }
   if constexpr (RegFit<T, P>::value && isPad<P>())
