@@ -64,7 +64,7 @@ def test_bessel_route_matches_sphere_route(name):
 
 
 def _psi_mp(x, y, kern, npts=33):
-    """eq. FF with the azimuth done (J0) in t = sin^2(th/2), by 30-digit mpmath
+    r"""eq. FF with the azimuth done (J0) in t = sin^2(th/2), by 30-digit mpmath
     quadrature: 4 pi c \int_0^1 t^{-s} (1-t)^{-r} [e^{2ixt} J0(Y) - 1] / t dt,
     Y = 2 y sqrt(t(1-t)).  The bracket over t is formed without cancellation:
     (J0(Y) - 1)/t = -y^2 (1-t) 1F2(1; 2, 2; -y^2 t(1-t)) and expm1(2ixt)/t; the
