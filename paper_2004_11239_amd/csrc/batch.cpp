@@ -111,12 +111,16 @@ PtrPack pack(const std::vector<double*>& ptrs, const std::vector<int>& idx, size
   return pk;
 }
 
-// time one evaluation of `n` cells of group g with `cpl` cells per launch
+// time one evaluation of `n` cells of group g with `cpl` cells per launch:
+// at least 64 cells (or all of them), so that candidates a few per cent apart
+// are told apart (over two launches' worth of cells the choice at 16^3 and
+// 24^3 fell on 8 and 4 cells per launch, 3 and 4.5 % slower per batch step
+// than 16)
 bzq_status time_candidate(Group& g, const std::vector<double*>& f, int cpl, hipStream_t st, float* ms_per_cell) {
   Workspace w;
   bzq_status s = workspace_init(w, *g.plan, cpl);
   if (s != BZQ_OK) return s;
-  const int n = std::min<int>((int)g.cells.size(), 2 * cpl);
+  const int n = std::min<int>((int)g.cells.size(), std::max(2 * cpl, 64));
   const size_t n3 = (size_t)g.plan->N * g.plan->N * g.plan->N;
   hipEvent_t e0, e1;
   BZQ_HIP_TRY(hipEventCreate(&e0));
