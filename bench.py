@@ -533,7 +533,7 @@ def main():
     ap.add_argument("--no-2d", dest="two_d", action="store_false",
                     help="skip the 2-D operator at Table 1's N = 64 setting")
     ap.add_argument("--batch-cells", type=int, default=4096, help="cells of the batched form (0: skip)")
-    ap.add_argument("--serve-rates", default="10,25,50,100,200,500",
+    ap.add_argument("--serve-rates", default="10,25,50,100,200,500,1000,2000,5000",
                     help="request rates (req/s) of the served form ('': skip)")
     ap.add_argument("--serve-duration", type=float, default=3.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
