@@ -262,6 +262,29 @@ def batch_bench(bzq, torch, n_cells, steps, seed=0):
                        "frac_of_roof": round(roof_ms / (ms / steps), 4),
                        "cells_by_N": {str(k): v for k, v in sorted(counts.items())}}
     batch.destroy()
+    # each size's cells alone (same plans, tuned cells per launch from the
+    # cache): how far each group is from its own roof, and whether the groups'
+    # times add up to the whole batch's
+    per_group = []
+    for N in sorted(counts):
+        idx = [i for i, (n, _) in enumerate(cells) if n == N]
+        b = bzq.Batch([plans[N]] * len(idx), [fs[i] for i in idx], cells_per_launch=0)
+        b.step(0.01, 1, use_graph=True)
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record(st)
+        b.step(0.01, steps, use_graph=True)
+        g1.record(st)
+        torch.cuda.synchronize()
+        gms = g0.elapsed_time(g1) / steps
+        nreal = N * (110 // 2)
+        groof = 2 * len(idx) * whole_path(N, nreal + (nreal & 1), 4, 1.0)["t_roof_ms"]
+        per_group.append({"N": N, "cells": len(idx), "cells_per_launch": b.groups()[0]["cells_per_launch"],
+                          "ms_per_step": round(gms, 2), "t_roof_ms_per_step": round(groof, 2),
+                          "frac_of_roof": round(groof / gms, 4)})
+        b.destroy()
+    out["groups_alone"] = per_group
+    out["groups_alone_ms_sum"] = round(sum(g["ms_per_step"] for g in per_group), 2)
     return out
 
 
