@@ -107,7 +107,7 @@ def run(rate_hz: float, duration_s: float, seed: int = 0, budget_gb: float = 64.
            "rejected": int(sum(rejected)), "max_queued": max_queued,
            "p50_s": _percentile(lat + lat_q, 50), "p99_s": _percentile(lat + lat_q, 99),
            "throughput_req_s": n_done / span if done_t else 0.0,
-           "peak_device_gb": stats["peak_device_bytes"] / 1e9, "evictions": stats["evictions"],
+           "peak_device_gib": stats["peak_device_bytes"] / 2 ** 30, "evictions": stats["evictions"],
            "slots": slots, "precision": precision, "n_steps": n_steps}
     if q_fraction > 0:
         out.update({"q_requests": len(lat_q), "q_p50_s": _percentile(lat_q, 50), "q_p99_s": _percentile(lat_q, 99),
