@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--rates", default="2,10,100")
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="device-memory budget of the server, GiB")
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
