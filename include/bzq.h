@@ -260,8 +260,9 @@ bzq_status bzq_collision_batch(const bzq_plan* plans, const double* const* f_hat
  * kernel and precision).  Cells sharing a plan run in the same launches, up
  * to 64 cells per launch; cells_per_launch = 0 lets an autotuner choose per
  * plan, timing the
- * candidates 1, 2, 4 ... 64 on these cells once, with the
- * choice cached in the file $BZQ_TUNE_CACHE or ~/.cache/bzq_autotune.txt;
+ * candidates 1, 2, 4 ... 64 on these cells once (best of three evaluations
+ * of at least 64 cells each; a larger count is kept only when it is at
+ * least 1 % faster), with the choice cached in the file $BZQ_TUNE_CACHE or ~/.cache/bzq_autotune.txt;
  * workspaces are capped by $BZQ_BATCH_WS_MB, default 8192.  Creation is
  * synchronous and allocates the workspaces.
  *   bzq_batch_collision: Q_hats[i] = Q(f_hats[i]).
